@@ -1,0 +1,289 @@
+/*
+ * potts_oracle.c -- serial CPU oracle for the checkerboard Metropolis sweep of
+ * the two-dimensional q-state Potts model (Ferrero, De Francesco, Wolovick,
+ * Cannas, "q-state Potts model metastability study using optimized GPU-based
+ * Monte Carlo algorithms", arXiv:1101.0876).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it; the product library never calls it
+ * and shares no code, header or table generator with it.
+ *
+ * Every function is written from the paper's definitions, in the order the
+ * paper states them, with no blocking, fusion or reordering:
+ *   - Hamiltonian H = -J sum_<ij> delta(s_i, s_j), J = 1          (Sec. 2.1, Eq. 1)
+ *   - order parameter from N_max = max_v N_v                       (Sec. 2.1, Eq. 7)
+ *   - one MCS = N single-spin Metropolis trials                   (Sec. 2.2)
+ *   - all sites of one checkerboard colour, then the other        (Sec. 3, opening)
+ *   - one integer proposal in {0..q-1} plus one acceptance number (Sec. 3.2)
+ *   - per-temperature table of acceptance weights                 (Sec. 5, CPU code)
+ *   - the spin is always written back                             (Sec. 5)
+ *
+ * Readings where the paper leaves a choice open (all documented with the
+ * library contract):
+ *   - spins are stored 0..q-1 (paper's label s is stored as s-1); the ordered
+ *     start is all zeros;
+ *   - colour c(x,y) = (x+y) & 1; colour 0 is updated first;
+ *   - the proposal is uniform over all q values (the current one included),
+ *     drawn as k = floor(w * q / 2^32) from a 32-bit word w;
+ *   - acceptance compares a 32-bit word against an integer threshold table
+ *     thr[d] = min(floor(exp(-beta d) 2^32), 2^32 - 1), d = 1..4, built in FP64;
+ *     a move with dE <= 0 is always accepted;
+ *   - random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ *     SC'11, "Parallel random numbers: as easy as 1, 2, 3"), one block per
+ *     (4-byte row chunk, sweep, colour): counter = (y*(L/4) + x/4, t_lo, t_hi,
+ *     colour), key = (seed_lo, seed_hi); a site at column x takes the word pair
+ *     (w[2b], w[2b+1]) with b = (x/2) & 1 as (proposal, acceptance).  The random
+ *     start uses counter (y*(L/4) + x/4, 0, 0, 2) and value floor(w[x&3]*q/2^32).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11), written from its published round
+ * definition: two 32x32->64 products, each high half XORed with the other
+ * counter word and a key word, and a Weyl increment of the key between rounds. */
+static void philox_round(uint32_t x[4], const uint32_t k[2])
+{
+    const uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x[0];
+    const uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x[2];
+    const uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    const uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    const uint32_t y0 = hi1 ^ x[1] ^ k[0];
+    const uint32_t y1 = lo1;
+    const uint32_t y2 = hi0 ^ x[3] ^ k[1];
+    const uint32_t y3 = lo0;
+    x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+}
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k[0] += 0x9E3779B9u;
+            k[1] += 0xBB67AE85u;
+        }
+        philox_round(x, k);
+    }
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2]; out[3] = x[3];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Table of acceptance weights for one temperature (Sec. 5: the CPU code keeps
+ * precomputed Boltzmann weights per temperature).  Entry d (1..4) is the
+ * Metropolis weight exp(-beta*d) scaled to 32 bits, floored, saturated. */
+int oracle_threshold_table(double beta, uint32_t thr[4])
+{
+    if (!(beta >= 0.0) || isinf(beta)) return ORACLE_EINVAL;
+    for (int d = 1; d <= 4; ++d) {
+        const double weight = exp(-beta * (double)d);
+        double scaled = floor(weight * 4294967296.0);
+        if (scaled > 4294967295.0) scaled = 4294967295.0;
+        thr[d - 1] = (uint32_t)scaled;
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+static int valid_shape(int L, int q)
+{
+    return L >= 4 && L % 4 == 0 && q >= 2 && q <= 256;
+}
+
+/* Lemire multiply-shift: a 32-bit word mapped onto {0..q-1}. */
+static uint32_t word_to_value(uint32_t w, int q)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)(uint32_t)q) >> 32);
+}
+
+/* Philox words for the chunk holding column x of row y. */
+static void chunk_words(int L, int x, int y, uint64_t seed, uint32_t c1, uint32_t c2,
+                        uint32_t c3, uint32_t w[4])
+{
+    const uint32_t ctr[4] = {(uint32_t)((uint64_t)y * (uint64_t)(L / 4) + (uint64_t)(x / 4)),
+                             c1, c2, c3};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, w);
+}
+
+/* Initial condition (Sec. 3, protocol): ordered = every spin in the first
+ * state; random = each spin drawn independently and uniformly. */
+int oracle_init(int L, int q, uint64_t seed, int start, uint8_t *spins)
+{
+    if (!valid_shape(L, q) || spins == NULL || (start != 0 && start != 1)) return ORACLE_EINVAL;
+    for (int y = 0; y < L; ++y) {
+        for (int x = 0; x < L; ++x) {
+            uint8_t value = 0;
+            if (start == 1) {
+                uint32_t w[4];
+                chunk_words(L, x, y, seed, 0u, 0u, 2u, w);
+                value = (uint8_t)word_to_value(w[x & 3], q);
+            }
+            spins[(size_t)y * (size_t)L + (size_t)x] = value;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* One Metropolis trial for a single site (Sec. 3.2 and Eq. 1).  nb holds the
+ * four nearest-neighbour spins; returns the spin after the trial.  Exported so
+ * that the tests can probe the decision rule directly. */
+int oracle_site_update(int q, int s, const uint8_t nb[4], uint32_t w_prop, uint32_t w_acc,
+                       const uint32_t thr[4])
+{
+    const int k = (int)word_to_value(w_prop, q);
+    int equal_now = 0, equal_new = 0;
+    for (int j = 0; j < 4; ++j) {
+        if (nb[j] == s) ++equal_now;
+        if (nb[j] == k) ++equal_new;
+    }
+    /* H = -(satisfied bonds), so the energy change of s -> k is the number of
+     * satisfied bonds lost: equal_now - equal_new. */
+    const int dE = equal_now - equal_new;
+    int accept;
+    if (dE <= 0) accept = 1;
+    else accept = (w_acc < thr[dE - 1]);
+    return accept ? k : s;
+}
+
+/* Update every site of one colour, in the given visiting order (NULL = row
+ * major).  Sites of one colour only have neighbours of the other colour, so the
+ * order cannot change the result; the tests check exactly that. */
+int oracle_half_sweep(int L, int q, uint64_t seed, uint64_t t, int colour, const uint32_t thr[4],
+                      uint8_t *spins, const int64_t *order)
+{
+    if (!valid_shape(L, q) || spins == NULL || thr == NULL || (colour != 0 && colour != 1))
+        return ORACLE_EINVAL;
+    const int64_t n = (int64_t)L * (int64_t)L;
+    for (int64_t visit = 0; visit < n; ++visit) {
+        const int64_t i = order ? order[visit] : visit;
+        if (i < 0 || i >= n) return ORACLE_EINVAL;
+        const int x = (int)(i % L), y = (int)(i / L);
+        if (((x + y) & 1) != colour) continue;
+        const uint8_t nb[4] = {
+            spins[(size_t)y * L + (size_t)((x + 1) % L)],          /* right */
+            spins[(size_t)y * L + (size_t)((x + L - 1) % L)],      /* left  */
+            spins[(size_t)((y + 1) % L) * L + (size_t)x],          /* down  */
+            spins[(size_t)((y + L - 1) % L) * L + (size_t)x],      /* up    */
+        };
+        uint32_t w[4];
+        chunk_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)colour, w);
+        const int b = (x / 2) & 1;
+        const int s = spins[(size_t)y * L + (size_t)x];
+        spins[(size_t)y * L + (size_t)x] =
+            (uint8_t)oracle_site_update(q, s, nb, w[2 * b], w[2 * b + 1], thr);
+    }
+    return ORACLE_OK;
+}
+
+/* Energy and order-parameter inputs by direct definition (Eq. 1, Eq. 7):
+ * e_sat = number of satisfied nearest-neighbour bonds (H = -e_sat), each bond
+ * counted once through the right and down neighbours; hist[v] = N_v. */
+int oracle_observables(int L, int q, const uint8_t *spins, int64_t *e_sat, int64_t *hist)
+{
+    if (!valid_shape(L, q) || spins == NULL) return ORACLE_EINVAL;
+    int64_t bonds = 0;
+    if (hist) memset(hist, 0, sizeof(int64_t) * (size_t)q);
+    for (int y = 0; y < L; ++y) {
+        for (int x = 0; x < L; ++x) {
+            const uint8_t s = spins[(size_t)y * L + x];
+            if (s == spins[(size_t)y * L + (size_t)((x + 1) % L)]) ++bonds;
+            if (s == spins[(size_t)((y + 1) % L) * L + x]) ++bonds;
+            if (hist) {
+                if (s >= q) return ORACLE_EINVAL;
+                ++hist[s];
+            }
+        }
+    }
+    if (e_sat) *e_sat = bonds;
+    return ORACLE_OK;
+}
+
+/* n full sweeps (1 MCS each: colour 0 then colour 1), starting at sweep index
+ * t0.  If records is not NULL, after sweep j it receives {e_sat, hist[0..q)}
+ * at records[j*(1+q)]. */
+int oracle_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, const uint32_t thr[4],
+                  uint8_t *spins, int64_t *records)
+{
+    if (!valid_shape(L, q) || spins == NULL || thr == NULL || nsweeps < 0) return ORACLE_EINVAL;
+    for (int64_t j = 0; j < nsweeps; ++j) {
+        const uint64_t t = t0 + (uint64_t)j;
+        int rc = oracle_half_sweep(L, q, seed, t, 0, thr, spins, NULL);
+        if (rc) return rc;
+        rc = oracle_half_sweep(L, q, seed, t, 1, thr, spins, NULL);
+        if (rc) return rc;
+        if (records) {
+            int64_t *rec = records + (size_t)j * (size_t)(1 + q);
+            rc = oracle_observables(L, q, spins, &rec[0], &rec[1]);
+            if (rc) return rc;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same chain restricted to an h-by-w window of an L-by-L lattice whose
+ * top-left corner is (x0, y0) (coordinates wrap periodically).  The window
+ * starts from the initial condition and runs nsweeps sweeps from t = 0 with
+ * the random words of the full lattice.  Sites outside the window are unknown,
+ * so each half sweep spoils one more ring of the window; after nsweeps sweeps
+ * only sites at least 2*nsweeps from the window edge equal the full-lattice
+ * chain.  The caller reads those only.  This lets the tests check samples of
+ * very large lattices one window at a time. */
+int oracle_window(int L, int q, uint64_t seed, int start, int64_t nsweeps, const uint32_t thr[4],
+                  int x0, int y0, int h, int w, uint8_t *out)
+{
+    if (!valid_shape(L, q) || out == NULL || thr == NULL || h < 1 || w < 1 || h > L || w > L ||
+        x0 < 0 || y0 < 0 || x0 >= L || y0 >= L || nsweeps < 0 || (start != 0 && start != 1))
+        return ORACLE_EINVAL;
+    uint8_t *cur = (uint8_t *)malloc((size_t)h * (size_t)w);
+    if (!cur) return ORACLE_ENOMEM;
+    for (int r = 0; r < h; ++r) {
+        for (int c = 0; c < w; ++c) {
+            const int x = (x0 + c) % L, y = (y0 + r) % L;
+            uint8_t value = 0;
+            if (start == 1) {
+                uint32_t wd[4];
+                chunk_words(L, x, y, seed, 0u, 0u, 2u, wd);
+                value = (uint8_t)word_to_value(wd[x & 3], q);
+            }
+            cur[(size_t)r * w + c] = value;
+        }
+    }
+    for (int64_t j = 0; j < nsweeps; ++j) {
+        const uint64_t t = (uint64_t)j;
+        for (int colour = 0; colour < 2; ++colour) {
+            for (int r = 0; r < h; ++r) {
+                for (int c = 0; c < w; ++c) {
+                    const int x = (x0 + c) % L, y = (y0 + r) % L;
+                    if (((x + y) & 1) != colour) continue;
+                    /* neighbours outside the window read as the site itself:
+                     * any value works, the ring is discarded anyway */
+                    const uint8_t self = cur[(size_t)r * w + c];
+                    const uint8_t nb[4] = {
+                        c + 1 < w ? cur[(size_t)r * w + c + 1] : self,
+                        c - 1 >= 0 ? cur[(size_t)r * w + c - 1] : self,
+                        r + 1 < h ? cur[(size_t)(r + 1) * w + c] : self,
+                        r - 1 >= 0 ? cur[(size_t)(r - 1) * w + c] : self,
+                    };
+                    uint32_t wd[4];
+                    chunk_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)colour, wd);
+                    const int b = (x / 2) & 1;
+                    cur[(size_t)r * w + c] =
+                        (uint8_t)oracle_site_update(q, self, nb, wd[2 * b], wd[2 * b + 1], thr);
+                }
+            }
+        }
+    }
+    memcpy(out, cur, (size_t)h * (size_t)w);
+    free(cur);
+    return ORACLE_OK;
+}
