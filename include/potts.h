@@ -1,0 +1,161 @@
+/*
+ * potts.h -- C ABI of the MI355X (gfx950) library for checkerboard Metropolis
+ * Monte Carlo of the two-dimensional ferromagnetic q-state Potts model
+ * (Ferrero, De Francesco, Wolovick, Cannas, arXiv:1101.0876).
+ *
+ * Model (Sec. 2.1, Eq. 1): H = -sum over nearest-neighbour bonds of
+ * delta(s_i, s_j) on an L x L periodic square lattice, J = k_B = 1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Lattice: L x L uint8 spins, row-major, site (x, y) at byte y*L + x,
+ *    values 0..q-1 (the paper's label s is stored as s-1).  4 <= L, L % 4 == 0,
+ *    2 <= q <= 256 (one byte per spin, Sec. 3.3).
+ *  - One sweep (one MCS, N = L*L trials, Sec. 2.2) updates every site with
+ *    (x+y) even, then every site with (x+y) odd (checkerboard, Sec. 3).
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed, one
+ *    block per (4-byte row chunk, sweep, colour): counter = (y*(L/4) + x/4,
+ *    t_lo, t_hi, colour).  Site x uses words (w[2b], w[2b+1]), b = (x/2) & 1,
+ *    as (proposal, acceptance).  The proposal is k = floor(w*q / 2^32), uniform
+ *    over all q values (Sec. 3.2: one integer in 0..q-1 and one acceptance
+ *    number).  Random start: counter (y*(L/4) + x/4, 0, 0, 2), spin =
+ *    floor(w[x&3]*q / 2^32).  t counts the sweeps this state has done.
+ *    Results are therefore a pure function of (L, q, seed, start, beta
+ *    schedule) and do not depend on how kernels are launched.
+ *  - Acceptance: dE = n(s) - n(k), n(v) = number of the 4 neighbours equal to
+ *    v; a move is accepted if dE <= 0 or w_acc < thr[dE-1], where
+ *    thr[d-1] = min(floor(exp(-beta d) 2^32), 2^32 - 1) (per-temperature
+ *    Boltzmann table, Sec. 5).  The spin is always written (Sec. 5).
+ *  - Records: after every sweep the library stores {e_sat, hist[0..q)} as
+ *    int64, where e_sat = number of satisfied bonds (H = -e_sat) and hist[v]
+ *    = N_v, the input of the order parameter (Eq. 7).  They are reduced inside
+ *    the sweep kernels (Sec. 3.4 does it in separate kernels; Sec. 7 suggests
+ *    on-the-fly accumulation).
+ *
+ * Return codes: 0 on success, a negative POTTS_E* code otherwise.  The library
+ * never aborts; the text of the last error of the calling thread is available
+ * from potts_last_error().  Every HIP call is checked (Sec. 3.5).
+ *
+ * Threading: a state is not thread-safe; distinct states may be used from
+ * distinct threads and run concurrently on distinct streams.
+ */
+#ifndef POTTS_H
+#define POTTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POTTS_OK 0
+#define POTTS_EINVAL (-1)  /* bad argument: L, q, beta, nsweeps, NULL pointer */
+#define POTTS_ENOMEM (-2)  /* device or host allocation failed                */
+#define POTTS_EDEVICE (-3) /* a HIP call failed; see potts_last_error()       */
+#define POTTS_ERANGE (-4)  /* index outside the record ring, or too large     */
+#define POTTS_EIO (-5)     /* checkpoint file could not be read or written    */
+
+#define POTTS_QMAX 256
+
+typedef struct potts_state potts_state;
+
+typedef enum { POTTS_ORDERED = 0, POTTS_RANDOM = 1 } potts_start;
+
+/* Energy and order-parameter sums of the current configuration. */
+typedef struct {
+    int64_t t;                 /* sweeps done by the state                  */
+    int64_t e_sat;             /* satisfied bonds; H = -e_sat (Eq. 1)       */
+    int64_t nmax;              /* max_v hist[v] (Eq. 7)                     */
+    int32_t q;
+    int32_t L;
+    int64_t hist[POTTS_QMAX];  /* hist[v] = N_v, valid for v < q            */
+} potts_obs;
+
+/* Derived FP64 observables of a window of n consecutive sweep records
+ * (Sec. 2.1, Sec. 4): e = <H>/N, C = beta^2 (<H^2> - <H>^2)/N,
+ * V_L = 1 - <H^4>/(3 <H^2>^2) (Eq. 9), m = <(q N_max/N - 1)/(q-1)> (Eq. 7),
+ * chi = N beta (<m^2> - <m>^2) (Eq. 11).  The integer moments are summed
+ * exactly on the device and each result is rounded once. */
+typedef struct {
+    int64_t n;
+    double e;
+    double C;
+    double V_L;
+    double m;
+    double chi;
+} potts_summary;
+
+/* Creates a state: allocates the lattice, a second lattice buffer and a ring of
+ * records_capacity per-sweep records (0 selects 4096) on the current HIP
+ * device, creates a stream, and writes the initial condition (Sec. 3:
+ * heating starts ordered, cooling starts random).
+ * Errors: EINVAL (L < 4, L % 4 != 0, q outside 2..256, bad start, out NULL),
+ * ERANGE (L*L/4 >= 2^32), ENOMEM, EDEVICE.  On error *out is NULL. */
+int potts_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_state **out);
+
+/* As potts_init, but on caller-owned device buffers and stream: dev_spins and
+ * dev_spins2 each hold at least L*L bytes (bytes gives the size of each) and
+ * must outlive the state; hip_stream is a hipStream_t (NULL = the default
+ * stream).  The records ring is still owned by the library. */
+int potts_init_ex(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spins,
+                  void *dev_spins2, size_t bytes, void *hip_stream, int64_t records_capacity,
+                  potts_state **out);
+
+/* Runs nsweeps Metropolis sweeps at inverse temperature beta, asynchronously on
+ * the state's stream; records one {e_sat, hist} per sweep.  The threshold
+ * table is rebuilt only when beta changes.
+ * Errors: EINVAL (s NULL, beta < 0 or not finite, nsweeps < 0), ERANGE (the
+ * sweep counter would overflow), EDEVICE. */
+int potts_sweep(potts_state *s, double beta, int64_t nsweeps);
+
+/* As potts_sweep with a caller-supplied threshold table thr[0..3] (d = 1..4). */
+int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
+
+/* The table potts_sweep uses for beta: thr[d-1] = min(floor(exp(-beta d)
+ * 2^32), 2^32-1), computed on the host in FP64.  Errors: EINVAL. */
+int potts_threshold_table(double beta, uint32_t thr[4]);
+
+/* Observables of the current configuration (synchronizes the stream).  Uses
+ * the last sweep's record, or measures the lattice if no sweep has run. */
+int potts_observables(potts_state *s, potts_obs *out);
+
+/* Measures the current configuration with the standalone observables kernel
+ * (independent of the fused reductions; synchronizes). */
+int potts_measure(potts_state *s, potts_obs *out);
+
+/* Copies the records of sweeps t0 .. t0+n-1 (sweep t0 = the (t0+1)-th sweep of
+ * this state) into out[n*(1+q)] as {e_sat, hist[0..q)} each (synchronizes).
+ * Errors: ERANGE if any of them is not (or no longer) in the ring. */
+int potts_records(potts_state *s, int64_t t0, int64_t n, int64_t *out);
+
+/* Derived statistics over the records of sweeps t0 .. t0+n-1 at inverse
+ * temperature beta (synchronizes).  Errors: ERANGE as potts_records, EINVAL
+ * for n < 1. */
+int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summary *out);
+
+/* Host copies of the lattice (synchronize).  set_spins also sets the sweep
+ * counter t; values must be < q (EINVAL otherwise). */
+int potts_get_spins(potts_state *s, uint8_t *host_out);
+int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t);
+
+/* Device pointer of the current lattice (valid until the next sweep call). */
+void *potts_device_spins(potts_state *s);
+int64_t potts_time(const potts_state *s);
+
+/* Checkpoint: (L, q, seed, t, lattice) to a file and back; a resumed state
+ * continues with exactly the same random numbers.  Errors: EIO, EINVAL. */
+int potts_save(potts_state *s, const char *path);
+int potts_load(const char *path, potts_state **out);
+
+/* Releases the state (synchronizes its stream first).  NULL is a no-op. */
+void potts_free(potts_state *s);
+
+const char *potts_strerror(int code);
+const char *potts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POTTS_H */

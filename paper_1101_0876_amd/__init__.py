@@ -1,0 +1,142 @@
+"""MI355X-native checkerboard Metropolis Monte Carlo for the 2D q-state Potts model.
+
+Thin Python layer over the C ABI of ``libpotts.so`` (include/potts.h).  Every
+step of a sweep runs in the library's HIP kernels; this module only marshals
+arguments.  PyTorch is optional plumbing: ``Lattice.from_torch`` runs a state
+on torch-allocated device buffers and a torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from ._native import PottsError, PottsObs, PottsSummary, check, load
+
+ORDERED = 0
+RANDOM = 1
+
+__all__ = ["Lattice", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
+
+
+def threshold_table(beta: float) -> np.ndarray:
+    """thr[d-1] = min(floor(exp(-beta d) 2^32), 2^32-1), d = 1..4 (host FP64)."""
+    thr = np.zeros(4, dtype=np.uint32)
+    check(load().potts_threshold_table(float(beta), thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return thr
+
+
+class Lattice:
+    """One L x L Potts lattice resident on the GPU (a potts_state)."""
+
+    def __init__(self, L: int, q: int, seed: int = 1, start: int = RANDOM, _handle=None, _keep=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        self._keep = _keep
+        if _handle is not None:
+            self._h = _handle
+        else:
+            check(self._lib.potts_init(int(L), int(q), int(seed), int(start), ctypes.byref(self._h)))
+        self.L = int(L)
+        self.q = int(q)
+        self.seed = int(seed)
+
+    @classmethod
+    def from_torch(cls, L: int, q: int, seed: int = 1, start: int = RANDOM, device="cuda",
+                   stream=None, records_capacity: int = 0) -> "Lattice":
+        import torch
+
+        a = torch.empty(L * L, dtype=torch.uint8, device=device)
+        b = torch.empty(L * L, dtype=torch.uint8, device=device)
+        st = stream if stream is not None else torch.cuda.current_stream(a.device)
+        h = ctypes.c_void_p()
+        check(load().potts_init_ex(L, q, seed, start, ctypes.c_void_p(a.data_ptr()),
+                                   ctypes.c_void_p(b.data_ptr()), L * L,
+                                   ctypes.c_void_p(st.cuda_stream), int(records_capacity),
+                                   ctypes.byref(h)))
+        return cls(L, q, seed, start, _handle=h, _keep=(a, b, st))
+
+    @classmethod
+    def load_checkpoint(cls, path: str) -> "Lattice":
+        h = ctypes.c_void_p()
+        check(load().potts_load(os.fsencode(path), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj._lib = load()
+        obj._h = h
+        obj._keep = None
+        obs = PottsObs()
+        check(obj._lib.potts_measure(h, ctypes.byref(obs)))
+        obj.L, obj.q, obj.seed = int(obs.L), int(obs.q), -1
+        return obj
+
+    # -- sweeps -----------------------------------------------------------------
+    def sweep(self, beta: float, nsweeps: int = 1) -> None:
+        check(self._lib.potts_sweep(self._h, float(beta), int(nsweeps)))
+
+    def sweep_thr(self, thr, nsweeps: int = 1) -> None:
+        t = np.ascontiguousarray(thr, dtype=np.uint32)
+        check(self._lib.potts_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(nsweeps)))
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.potts_time(self._h))
+
+    # -- observables ------------------------------------------------------------
+    def _obs(self, fn) -> dict:
+        o = PottsObs()
+        check(fn(self._h, ctypes.byref(o)))
+        return {"t": o.t, "e_sat": o.e_sat, "nmax": o.nmax,
+                "hist": np.array(o.hist[: self.q], dtype=np.int64)}
+
+    def observables(self) -> dict:
+        return self._obs(self._lib.potts_observables)
+
+    def measure(self) -> dict:
+        return self._obs(self._lib.potts_measure)
+
+    def records(self, t0: int, n: int) -> np.ndarray:
+        out = np.zeros((n, 1 + self.q), dtype=np.int64)
+        check(self._lib.potts_records(self._h, int(t0), int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return out
+
+    def stats(self, t0: int, n: int, beta: float) -> dict:
+        s = PottsSummary()
+        check(self._lib.potts_stats(self._h, int(t0), int(n), float(beta), ctypes.byref(s)))
+        return {"n": s.n, "e": s.e, "C": s.C, "V_L": s.V_L, "m": s.m, "chi": s.chi}
+
+    # -- lattice access -----------------------------------------------------------
+    def spins(self) -> np.ndarray:
+        out = np.zeros(self.L * self.L, dtype=np.uint8)
+        check(self._lib.potts_get_spins(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.reshape(self.L, self.L)
+
+    def set_spins(self, spins: np.ndarray, t: int) -> None:
+        a = np.ascontiguousarray(spins, dtype=np.uint8).ravel()
+        if a.size != self.L * self.L:
+            raise ValueError("lattice size mismatch")
+        check(self._lib.potts_set_spins(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), int(t)))
+
+    def device_ptr(self) -> int:
+        return int(self._lib.potts_device_spins(self._h) or 0)
+
+    def save(self, path: str) -> None:
+        check(self._lib.potts_save(self._h, os.fsencode(path)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.potts_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,93 @@
+"""ctypes declarations of the C ABI in include/potts.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpotts.so")
+
+POTTS_QMAX = 256
+ERRORS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ERANGE", -5: "EIO"}
+
+
+class PottsError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {message}")
+        self.code = code
+
+
+class PottsObs(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int64),
+        ("e_sat", ctypes.c_int64),
+        ("nmax", ctypes.c_int64),
+        ("q", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("hist", ctypes.c_int64 * POTTS_QMAX),
+    ]
+
+
+class PottsSummary(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("e", ctypes.c_double),
+        ("C", ctypes.c_double),
+        ("V_L", ctypes.c_double),
+        ("m", ctypes.c_double),
+        ("chi", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every exported symbol declared in include/potts.h
+_VP = ctypes.c_void_p
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_U8P = ctypes.POINTER(ctypes.c_uint8)
+SIGNATURES = [
+    ("potts_init", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_VP)]),
+    ("potts_init_ex", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _VP, _VP,
+                                     ctypes.c_size_t, _VP, ctypes.c_int64, ctypes.POINTER(_VP)]),
+    ("potts_sweep", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64]),
+    ("potts_sweep_thr", ctypes.c_int, [_VP, _U32P, ctypes.c_int64]),
+    ("potts_threshold_table", ctypes.c_int, [ctypes.c_double, _U32P]),
+    ("potts_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
+    ("potts_measure", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
+    ("potts_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    ("potts_stats", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.POINTER(PottsSummary)]),
+    ("potts_get_spins", ctypes.c_int, [_VP, _U8P]),
+    ("potts_set_spins", ctypes.c_int, [_VP, _U8P, ctypes.c_int64]),
+    ("potts_device_spins", _VP, [_VP]),
+    ("potts_time", ctypes.c_int64, [_VP]),
+    ("potts_save", ctypes.c_int, [_VP, ctypes.c_char_p]),
+    ("potts_load", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
+    ("potts_free", None, [_VP]),
+    ("potts_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("potts_last_error", ctypes.c_char_p, []),
+]
+
+
+def load():
+    """Loads libpotts.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python paper_1101_0876_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        msg = load().potts_last_error()
+        raise PottsError(rc, msg.decode() if msg else "")

@@ -1,0 +1,412 @@
+// capi.hip -- the C ABI declared in include/potts.h: state lifetime, the
+// per-temperature threshold table, sweep launches, records and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/potts.h"
+#include "kernels.hpp"
+
+struct potts_state {
+  int32_t L = 0, q = 0;
+  uint64_t seed = 0;
+  int64_t t = 0;              // sweeps done
+  int64_t rec_from = 0;       // first sweep index whose record is still valid
+  uint8_t *spins = nullptr;   // current lattice
+  uint8_t *spins2 = nullptr;  // second buffer
+  bool owns_spins = true;
+  hipStream_t stream = nullptr;
+  bool owns_stream = false;
+  unsigned long long *records = nullptr;  // ring of rec_cap slots of (1+q)
+  int64_t rec_cap = 0;
+  unsigned long long *scratch = nullptr;  // 1+q int64 for measurements
+  double *stats_out = nullptr;            // 5 doubles
+  bool have_thr = false;
+  double thr_beta = 0.0;
+  uint32_t thr[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(POTTS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+  do {                                                 \
+    hipError_t hip_err_ = (call);                      \
+    if (hip_err_ != hipSuccess) return hip_fail(hip_err_, #call); \
+  } while (0)
+
+bool valid_shape(int32_t L, int32_t q) { return L >= 4 && L % 4 == 0 && q >= 2 && q <= POTTS_QMAX; }
+
+uint64_t n_sites(const potts_state *s) { return (uint64_t)s->L * (uint64_t)s->L; }
+
+void release(potts_state *s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->owns_spins) {
+    if (s->spins) (void)hipFree(s->spins);
+    if (s->spins2) (void)hipFree(s->spins2);
+  }
+  if (s->records) (void)hipFree(s->records);
+  if (s->scratch) (void)hipFree(s->scratch);
+  if (s->stats_out) (void)hipFree(s->stats_out);
+  if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int write_initial(potts_state *s, potts_start start) {
+  potts::InitParams p{};
+  p.spins = s->spins;
+  p.L = (uint32_t)s->L;
+  p.q = (uint32_t)s->q;
+  p.nchunks = n_sites(s) / 4;
+  p.k0 = (uint32_t)s->seed;
+  p.k1 = (uint32_t)(s->seed >> 32);
+  p.random = start == POTTS_RANDOM;
+  HIP_TRY(potts::launch_init(p, s->stream));
+  return POTTS_OK;
+}
+
+int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spins, void *dev_spins2,
+           size_t bytes, void *stream, bool external, int64_t rec_cap, potts_state **out) {
+  if (!out) return fail(POTTS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_shape(L, q)) return fail(POTTS_EINVAL, "need L >= 4, L % 4 == 0, 2 <= q <= 256");
+  if (start != POTTS_ORDERED && start != POTTS_RANDOM) return fail(POTTS_EINVAL, "bad start");
+  if ((uint64_t)L * (uint64_t)L / 4 >= (1ull << 32))
+    return fail(POTTS_ERANGE, "L*L/4 must be below 2^32 (Philox counter word)");
+  if (rec_cap == 0) rec_cap = 4096;
+  if (rec_cap < 2) return fail(POTTS_EINVAL, "records_capacity must be >= 2");
+  const size_t nbytes = (size_t)L * (size_t)L;
+  if (external && (!dev_spins || !dev_spins2 || bytes < nbytes))
+    return fail(POTTS_EINVAL, "external buffers missing or smaller than L*L bytes");
+  potts_state *s = new (std::nothrow) potts_state();
+  if (!s) return fail(POTTS_ENOMEM, "host allocation failed");
+  s->L = L;
+  s->q = q;
+  s->seed = seed;
+  if (external) {
+    s->owns_spins = false;
+    s->spins = (uint8_t *)dev_spins;
+    s->spins2 = (uint8_t *)dev_spins2;
+    s->stream = (hipStream_t)stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      release(s);
+      return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    s->owns_stream = true;
+    if (hipMalloc(&s->spins, nbytes) != hipSuccess || hipMalloc(&s->spins2, nbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      release(s);
+      return fail(POTTS_ENOMEM, "hipMalloc of the lattice failed");
+    }
+  }
+  s->rec_cap = rec_cap;
+  const size_t rec_bytes = (size_t)rec_cap * (size_t)(q + 1) * sizeof(unsigned long long);
+  if (hipMalloc(&s->records, rec_bytes) != hipSuccess ||
+      hipMalloc(&s->scratch, (size_t)(q + 1) * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&s->stats_out, 8 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    release(s);
+    return fail(POTTS_ENOMEM, "hipMalloc of the record ring failed");
+  }
+  int rc = write_initial(s, start);
+  if (rc == POTTS_OK) {
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
+  }
+  if (rc != POTTS_OK) {
+    release(s);
+    return rc;
+  }
+  *out = s;
+  return POTTS_OK;
+}
+
+int build_table(double beta, uint32_t thr[4]) {
+  if (!(beta >= 0.0) || !isfinite(beta)) return fail(POTTS_EINVAL, "beta must be finite and >= 0");
+  for (int d = 1; d <= 4; ++d) {
+    const double scaled = floor(exp(-beta * d) * 4294967296.0);
+    thr[d - 1] = scaled >= 4294967295.0 ? 4294967295u : (uint32_t)scaled;
+  }
+  return POTTS_OK;
+}
+
+int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
+  if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
+  if (nsweeps == 0) return POTTS_OK;
+  const int64_t rl = s->q + 1;
+  potts::SweepParams p{};
+  p.spins = s->spins;
+  p.L = (uint32_t)s->L;
+  p.q = (uint32_t)s->q;
+  p.nchunks = n_sites(s) / 4;
+  p.k0 = (uint32_t)s->seed;
+  p.k1 = (uint32_t)(s->seed >> 32);
+  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+  HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
+  for (int64_t j = 0; j < nsweeps; ++j) {
+    const int64_t t = s->t + j;
+    p.t_lo = (uint32_t)(uint64_t)t;
+    p.t_hi = (uint32_t)((uint64_t)t >> 32);
+    p.rec = s->records + (t % s->rec_cap) * rl;
+    p.rec_clear = nullptr;
+    HIP_TRY(potts::launch_half_sweep(p, 0, s->stream));
+    p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
+    HIP_TRY(potts::launch_half_sweep(p, 1, s->stream));
+  }
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
+// Validates [t0, t0+n) against the ring; returns the first slot.
+int ring_window(const potts_state *s, int64_t t0, int64_t n, int64_t *slot0) {
+  if (n < 0 || t0 < 0) return fail(POTTS_EINVAL, "negative record index or count");
+  // the last sweep cleared the slot of the next one, so cap - 1 records survive
+  const int64_t oldest = s->t - s->rec_cap + 1;
+  const int64_t first = oldest > s->rec_from ? oldest : s->rec_from;
+  if (t0 < first || t0 + n > s->t)
+    return fail(POTTS_ERANGE, "requested records are not in the ring (kept: sweeps " +
+                                  std::to_string(first) + " .. " + std::to_string(s->t - 1) + ")");
+  *slot0 = t0 % s->rec_cap;
+  return POTTS_OK;
+}
+
+int copy_records(potts_state *s, int64_t t0, int64_t n, int64_t *out) {
+  int64_t slot0 = 0;
+  int rc = ring_window(s, t0, n, &slot0);
+  if (rc) return rc;
+  const int64_t rl = s->q + 1;
+  int64_t done = 0;
+  while (done < n) {
+    const int64_t slot = (slot0 + done) % s->rec_cap;
+    const int64_t run = std::min<int64_t>(n - done, s->rec_cap - slot);
+    HIP_TRY(hipMemcpyAsync(out + done * rl, s->records + slot * rl, (size_t)(run * rl) * 8,
+                           hipMemcpyDeviceToHost, s->stream));
+    done += run;
+  }
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+void fill_obs(const potts_state *s, const int64_t *rec, potts_obs *out) {
+  memset(out, 0, sizeof(*out));
+  out->t = s->t;
+  out->q = s->q;
+  out->L = s->L;
+  out->e_sat = rec[0];
+  for (int v = 0; v < s->q; ++v) {
+    out->hist[v] = rec[1 + v];
+    if (rec[1 + v] > out->nmax) out->nmax = rec[1 + v];
+  }
+}
+
+const uint32_t kMagic[2] = {0x54544f50u, 0x314b4353u};  // "POTTSCK1"
+
+}  // namespace
+
+extern "C" {
+
+int potts_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_state **out) {
+  return create(L, q, seed, start, nullptr, nullptr, 0, nullptr, false, 0, out);
+}
+
+int potts_init_ex(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spins,
+                  void *dev_spins2, size_t bytes, void *hip_stream, int64_t records_capacity,
+                  potts_state **out) {
+  return create(L, q, seed, start, dev_spins, dev_spins2, bytes, hip_stream, true, records_capacity,
+                out);
+}
+
+int potts_threshold_table(double beta, uint32_t thr[4]) {
+  if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
+  return build_table(beta, thr);
+}
+
+int potts_sweep(potts_state *s, double beta, int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (!s->have_thr || s->thr_beta != beta) {
+    uint32_t thr[4];
+    int rc = build_table(beta, thr);
+    if (rc) return rc;
+    memcpy(s->thr, thr, sizeof(thr));
+    s->thr_beta = beta;
+    s->have_thr = true;
+  }
+  return run_sweeps(s, s->thr, nsweeps);
+}
+
+int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
+  return run_sweeps(s, thr, nsweeps);
+}
+
+int potts_measure(potts_state *s, potts_obs *out) {
+  if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
+  const int64_t rl = s->q + 1;
+  HIP_TRY(potts::launch_fill_u64(s->scratch, (uint64_t)rl, 0ull, s->stream));
+  potts::MeasureParams p{};
+  p.spins = s->spins;
+  p.L = (uint32_t)s->L;
+  p.q = (uint32_t)s->q;
+  p.nchunks = n_sites(s) / 4;
+  p.out = s->scratch;
+  HIP_TRY(potts::launch_measure(p, s->stream));
+  std::vector<int64_t> rec((size_t)rl);
+  HIP_TRY(hipMemcpyAsync(rec.data(), s->scratch, (size_t)rl * 8, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  fill_obs(s, rec.data(), out);
+  return POTTS_OK;
+}
+
+int potts_observables(potts_state *s, potts_obs *out) {
+  if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
+  if (s->t == 0 || s->rec_from >= s->t) return potts_measure(s, out);
+  std::vector<int64_t> rec((size_t)(s->q + 1));
+  int rc = copy_records(s, s->t - 1, 1, rec.data());
+  if (rc) return rc;
+  fill_obs(s, rec.data(), out);
+  return POTTS_OK;
+}
+
+int potts_records(potts_state *s, int64_t t0, int64_t n, int64_t *out) {
+  if (!s || (!out && n > 0)) return fail(POTTS_EINVAL, "NULL argument");
+  return copy_records(s, t0, n, out);
+}
+
+int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summary *out) {
+  if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
+  if (n < 1 || n > (1ll << 24)) return fail(POTTS_EINVAL, "window must hold 1 .. 2^24 records");
+  if (!(beta >= 0.0) || !isfinite(beta)) return fail(POTTS_EINVAL, "beta must be finite and >= 0");
+  int64_t slot0 = 0;
+  int rc = ring_window(s, t0, n, &slot0);
+  if (rc) return rc;
+  potts::StatsParams p{};
+  p.ring = s->records;
+  p.cap = s->rec_cap;
+  p.slot0 = slot0;
+  p.n = n;
+  p.q = (uint32_t)s->q;
+  p.N = n_sites(s);
+  p.beta = beta;
+  p.out = s->stats_out;
+  HIP_TRY(potts::launch_stats(p, s->stream));
+  double v[5];
+  HIP_TRY(hipMemcpyAsync(v, s->stats_out, sizeof(v), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  out->n = n;
+  out->e = v[0];
+  out->C = v[1];
+  out->V_L = v[2];
+  out->m = v[3];
+  out->chi = v[4];
+  return POTTS_OK;
+}
+
+int potts_get_spins(potts_state *s, uint8_t *host_out) {
+  if (!s || !host_out) return fail(POTTS_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(host_out, s->spins, (size_t)n_sites(s), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t) {
+  if (!s || !host_in) return fail(POTTS_EINVAL, "NULL argument");
+  if (t < 0) return fail(POTTS_EINVAL, "t must be >= 0");
+  const uint64_t n = n_sites(s);
+  for (uint64_t i = 0; i < n; ++i)
+    if (host_in[i] >= s->q) return fail(POTTS_EINVAL, "spin value >= q");
+  HIP_TRY(hipMemcpyAsync(s->spins, host_in, (size_t)n, hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->t = t;
+  s->rec_from = t;
+  return POTTS_OK;
+}
+
+void *potts_device_spins(potts_state *s) { return s ? (void *)s->spins : nullptr; }
+
+int64_t potts_time(const potts_state *s) { return s ? s->t : -1; }
+
+int potts_save(potts_state *s, const char *path) {
+  if (!s || !path) return fail(POTTS_EINVAL, "NULL argument");
+  std::vector<uint8_t> host((size_t)n_sites(s));
+  int rc = potts_get_spins(s, host.data());
+  if (rc) return rc;
+  FILE *f = fopen(path, "wb");
+  if (!f) return fail(POTTS_EIO, std::string("cannot open ") + path);
+  const int32_t shape[2] = {s->L, s->q};
+  const int64_t tt = s->t;
+  bool ok = fwrite(kMagic, sizeof(kMagic), 1, f) == 1 && fwrite(shape, sizeof(shape), 1, f) == 1 &&
+            fwrite(&s->seed, sizeof(s->seed), 1, f) == 1 && fwrite(&tt, sizeof(tt), 1, f) == 1 &&
+            fwrite(host.data(), 1, host.size(), f) == host.size();
+  ok = (fclose(f) == 0) && ok;
+  return ok ? POTTS_OK : fail(POTTS_EIO, std::string("write failed: ") + path);
+}
+
+int potts_load(const char *path, potts_state **out) {
+  if (!path || !out) return fail(POTTS_EINVAL, "NULL argument");
+  *out = nullptr;
+  FILE *f = fopen(path, "rb");
+  if (!f) return fail(POTTS_EIO, std::string("cannot open ") + path);
+  uint32_t magic[2];
+  int32_t shape[2];
+  uint64_t seed;
+  int64_t t;
+  bool ok = fread(magic, sizeof(magic), 1, f) == 1 && fread(shape, sizeof(shape), 1, f) == 1 &&
+            fread(&seed, sizeof(seed), 1, f) == 1 && fread(&t, sizeof(t), 1, f) == 1;
+  if (!ok || magic[0] != kMagic[0] || magic[1] != kMagic[1] || !valid_shape(shape[0], shape[1]) || t < 0) {
+    fclose(f);
+    return fail(POTTS_EIO, std::string("not a checkpoint: ") + path);
+  }
+  std::vector<uint8_t> host((size_t)shape[0] * (size_t)shape[0]);
+  ok = fread(host.data(), 1, host.size(), f) == host.size();
+  fclose(f);
+  if (!ok) return fail(POTTS_EIO, std::string("truncated checkpoint: ") + path);
+  potts_state *s = nullptr;
+  int rc = potts_init(shape[0], shape[1], seed, POTTS_ORDERED, &s);
+  if (rc) return rc;
+  rc = potts_set_spins(s, host.data(), t);
+  if (rc) {
+    release(s);
+    return rc;
+  }
+  *out = s;
+  return POTTS_OK;
+}
+
+void potts_free(potts_state *s) { release(s); }
+
+const char *potts_strerror(int code) {
+  switch (code) {
+    case POTTS_OK: return "ok";
+    case POTTS_EINVAL: return "invalid argument";
+    case POTTS_ENOMEM: return "out of memory";
+    case POTTS_EDEVICE: return "HIP device error";
+    case POTTS_ERANGE: return "out of range";
+    case POTTS_EIO: return "checkpoint I/O error";
+    default: return "unknown error";
+  }
+}
+
+const char *potts_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

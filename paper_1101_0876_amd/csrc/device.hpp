@@ -1,0 +1,74 @@
+// device.hpp -- gfx950 device helpers for the Potts sweep kernels.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) written for CDNA4: the
+// 32x32->64 products issue as v_mad_u64_u32 at full rate, and the two
+// three-input XORs of each round use gfx950's v_bitop3_b32 (truth table 0x96),
+// which halves the XOR count the compiler would otherwise emit.  The key is
+// wave-uniform, so its Weyl increments stay on the scalar unit.
+//
+// SWAR byte helpers treat a dword as four uint8 spins.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace potts {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kWeyl0 = 0x9E3779B9u;
+constexpr uint32_t kWeyl1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+struct Words {
+  uint32_t w0, w1, w2, w3;
+};
+
+// Ten rounds; round r uses key (k0 + r*W0, k1 + r*W1).
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+    k0 += kWeyl0;
+    k1 += kWeyl1;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
+// floor(w * q / 2^32): a 32-bit word onto 0..q-1.
+__device__ __forceinline__ uint32_t scale_to_q(uint32_t w, uint32_t q) { return __umulhi(w, q); }
+
+// 0x80 in every byte of x that is zero, 0 elsewhere (exact, no carries across bytes).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
+  const uint32_t t = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+  return ~(t | x) & 0x80808080u;
+}
+
+// Per-byte count (0..4) of the four neighbour dwords equal to v, bytewise.
+__device__ __forceinline__ uint32_t count_equal(uint32_t v, uint32_t a, uint32_t b, uint32_t c,
+                                                uint32_t d) {
+  return (zero_bytes(v ^ a) >> 7) + (zero_bytes(v ^ b) >> 7) + (zero_bytes(v ^ c) >> 7) +
+         (zero_bytes(v ^ d) >> 7);
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t x, uint32_t i) { return (x >> (8u * i)) & 0xFFu; }
+
+// Wave64 sum.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace potts

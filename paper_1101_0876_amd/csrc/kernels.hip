@@ -1,0 +1,176 @@
+// kernels.hip -- HIP kernels (gfx950) for the checkerboard Metropolis sweep of
+// the 2D q-state Potts model, and their host-side launchers.
+//
+// Layout: uint8 spins, row-major, L % 4 == 0, so a row is L/4 dwords and every
+// dword ("chunk") holds two sites of each colour.  A thread owns one chunk:
+// it reads its dword, the dwords above and below, and the two side dwords for
+// the outermost left/right neighbours, updates the two sites of the active
+// colour with one Philox4x32-10 block, and writes the dword back.  Sites of one
+// colour only have neighbours of the other colour (Sec. 3), and the other
+// colour's bytes are written back unchanged, so updating in place is race-free.
+//
+// The per-sweep energy and population sums (Sec. 3.4) are fused: the colour-0
+// pass adds the populations of colour-0 sites, the colour-1 pass adds those of
+// colour-1 sites and, per colour-1 site, its number of equal neighbours; since
+// every bond joins the two colours, that sum is e_sat of the finished sweep.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace potts {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t pick_threshold(const Thresholds &thr, int d) {
+  return d == 1 ? thr.v[0] : d == 2 ? thr.v[1] : d == 3 ? thr.v[2] : thr.v[3];
+}
+
+// Accumulates one workgroup's population counts and bond sum into a record.
+__device__ __forceinline__ void flush_record(uint32_t *hist, uint32_t *esum, uint32_t q,
+                                             unsigned long long *rec, bool with_energy) {
+  __syncthreads();
+  for (uint32_t v = threadIdx.x; v < q; v += blockDim.x) {
+    const uint32_t c = hist[v];
+    if (c) atomicAdd(&rec[1 + v], (unsigned long long)c);
+  }
+  if (with_energy && threadIdx.x == 0 && *esum) atomicAdd(&rec[0], (unsigned long long)*esum);
+}
+
+template <int COLOUR>
+__global__ __launch_bounds__(kBlock) void half_sweep_kernel(SweepParams p) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t esum;
+  for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
+  if (threadIdx.x == 0) esum = 0;
+  if (COLOUR == 1 && blockIdx.x == 0 && p.rec_clear) {
+    for (uint32_t i = threadIdx.x; i < p.q + 1; i += kBlock) p.rec_clear[i] = 0;
+  }
+  __syncthreads();
+
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t e = 0;
+  if (g < p.nchunks) {
+    const uint32_t cpr = p.L >> 2;
+    const uint32_t y = (uint32_t)(g / cpr);
+    const uint32_t j = (uint32_t)(g - (uint64_t)y * cpr);
+    const uint32_t yu = y == 0 ? p.L - 1 : y - 1;
+    const uint32_t yd = y + 1 == p.L ? 0 : y + 1;
+    uint32_t *row = reinterpret_cast<uint32_t *>(p.spins + (size_t)y * p.L);
+    const uint32_t *rowu = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yu * p.L);
+    const uint32_t *rowd = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * p.L);
+    const uint32_t cur = row[j];
+    const uint32_t up = rowu[j];
+    const uint32_t dn = rowd[j];
+    const uint32_t lf = row[j == 0 ? cpr - 1 : j - 1];
+    const uint32_t rt = row[j + 1 == cpr ? 0 : j + 1];
+    const uint32_t left = (cur << 8) | (lf >> 24);   // byte i: spin at x-1
+    const uint32_t right = (cur >> 8) | (rt << 24);  // byte i: spin at x+1
+
+    const Words w = philox4x32_10((uint32_t)g, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
+    const uint32_t o = (COLOUR + y) & 1u;  // byte offset of the first active site
+    const uint32_t ka = scale_to_q(w.w0, p.q);
+    const uint32_t kb = scale_to_q(w.w2, p.q);
+    const uint32_t prop = (ka << (8 * o)) | (kb << (8 * (o + 2)));
+    const uint32_t n_cur = count_equal(cur, up, dn, left, right);
+    const uint32_t n_new = count_equal(prop, up, dn, left, right);
+
+    const uint32_t sa = byte_of(cur, o), sb = byte_of(cur, o + 2);
+    const uint32_t nsa = byte_of(n_cur, o), nka = byte_of(n_new, o);
+    const uint32_t nsb = byte_of(n_cur, o + 2), nkb = byte_of(n_new, o + 2);
+    const int da = (int)nsa - (int)nka;
+    const int db = (int)nsb - (int)nkb;
+    const bool acc_a = da <= 0 || w.w1 < pick_threshold(p.thr, da);
+    const bool acc_b = db <= 0 || w.w3 < pick_threshold(p.thr, db);
+    const uint32_t na = acc_a ? ka : sa;
+    const uint32_t nb = acc_b ? kb : sb;
+    const uint32_t keep = ~((0xFFu << (8 * o)) | (0xFFu << (8 * (o + 2))));
+    row[j] = (cur & keep) | (na << (8 * o)) | (nb << (8 * (o + 2)));
+
+    atomicAdd(&hist[na], 1u);
+    atomicAdd(&hist[nb], 1u);
+    if (COLOUR == 1) e = (acc_a ? nka : nsa) + (acc_b ? nkb : nsb);
+  }
+  if (COLOUR == 1) {
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0 && e) atomicAdd(&esum, e);
+  }
+  flush_record(hist, &esum, p.q, p.rec, COLOUR == 1);
+}
+
+__global__ __launch_bounds__(kBlock) void init_kernel(InitParams p) {
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= p.nchunks) return;
+  uint32_t out = 0;
+  if (p.random) {
+    const Words w = philox4x32_10((uint32_t)g, 0u, 0u, 2u, p.k0, p.k1);
+    out = scale_to_q(w.w0, p.q) | (scale_to_q(w.w1, p.q) << 8) | (scale_to_q(w.w2, p.q) << 16) |
+          (scale_to_q(w.w3, p.q) << 24);
+  }
+  reinterpret_cast<uint32_t *>(p.spins)[g] = out;
+}
+
+// Standalone measurement of e_sat and the populations (no sweep).
+__global__ __launch_bounds__(kBlock) void measure_kernel(MeasureParams p) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t esum;
+  for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
+  if (threadIdx.x == 0) esum = 0;
+  __syncthreads();
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t e = 0;
+  if (g < p.nchunks) {
+    const uint32_t cpr = p.L >> 2;
+    const uint32_t y = (uint32_t)(g / cpr);
+    const uint32_t j = (uint32_t)(g - (uint64_t)y * cpr);
+    const uint32_t yd = y + 1 == p.L ? 0 : y + 1;
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(p.spins + (size_t)y * p.L);
+    const uint32_t *rowd = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * p.L);
+    const uint32_t cur = row[j];
+    const uint32_t dn = rowd[j];
+    const uint32_t rt = row[j + 1 == cpr ? 0 : j + 1];
+    const uint32_t right = (cur >> 8) | (rt << 24);
+    e = __popc(zero_bytes(cur ^ right)) + __popc(zero_bytes(cur ^ dn));
+    for (uint32_t i = 0; i < 4; ++i) atomicAdd(&hist[byte_of(cur, i)], 1u);
+  }
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0 && e) atomicAdd(&esum, e);
+  flush_record(hist, &esum, p.q, p.out, true);
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, uint64_t n, unsigned long long value) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+inline unsigned grid_for(uint64_t items) { return (unsigned)((items + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
+                           hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, p, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const InitParams &p, hipStream_t stream) {
+  hipLaunchKernelGGL(init_kernel, dim3(grid_for(p.nchunks)), dim3(kBlock), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream) {
+  if (colour == 0)
+    hipLaunchKernelGGL(half_sweep_kernel<0>, dim3(grid_for(p.nchunks)), dim3(kBlock), 0, stream, p);
+  else
+    hipLaunchKernelGGL(half_sweep_kernel<1>, dim3(grid_for(p.nchunks)), dim3(kBlock), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_measure(const MeasureParams &p, hipStream_t stream) {
+  hipLaunchKernelGGL(measure_kernel, dim3(grid_for(p.nchunks)), dim3(kBlock), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace potts

@@ -1,0 +1,55 @@
+// kernels.hpp -- parameter blocks and launchers of the Potts sweep kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace potts {
+
+struct Thresholds {
+  uint32_t v[4];  // v[d-1] for dE = d = 1..4
+};
+
+struct SweepParams {
+  uint8_t *spins;
+  uint32_t L, q;
+  uint64_t nchunks;               // L*L/4
+  uint32_t t_lo, t_hi;            // sweep index
+  uint32_t k0, k1;                // Philox key = seed
+  Thresholds thr;
+  unsigned long long *rec;        // record of this sweep: [0] e_sat, [1+v] N_v
+  unsigned long long *rec_clear;  // record slot to zero for the next sweep, or null
+};
+
+struct InitParams {
+  uint8_t *spins;
+  uint32_t L, q;
+  uint64_t nchunks;
+  uint32_t k0, k1;
+  int random;
+};
+
+struct MeasureParams {
+  const uint8_t *spins;
+  uint32_t L, q;
+  uint64_t nchunks;
+  unsigned long long *out;  // [0] e_sat, [1+v] N_v; must start zeroed
+};
+
+struct StatsParams {
+  const unsigned long long *ring;  // record ring, cap slots of (1+q) int64
+  int64_t cap, slot0, n;           // window: n records starting at slot0 (wrapping)
+  uint32_t q;
+  uint64_t N;
+  double beta;
+  double *out;                     // e, C, V_L, m, chi
+};
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
+                           hipStream_t stream);
+hipError_t launch_init(const InitParams &p, hipStream_t stream);
+hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream);
+hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
+hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
+
+}  // namespace potts

@@ -1,0 +1,113 @@
+// stats.hip -- derived observables of a window of per-sweep records, computed
+// on the device with exact integer moments and one FP64 evaluation at the end.
+//
+// For records {e_sat_t, hist_t} of n sweeps on N sites with q states:
+//   S1 = sum e,  S2 = sum e^2,  S4 = sum e^4          (H = -e, Eq. 1)
+//   M1 = sum (q nmax - N),  M2 = sum (q nmax - N)^2   (m = (q nmax/N - 1)/(q-1), Eq. 7)
+// S1 and M1 fit in int64, S2 and M2 in 128 bits, S4 in 256 bits for any lattice
+// this library accepts and up to 2^32 records.  The moments are exact, so the
+// large cancellations in <H^2> - <H>^2 cost nothing.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace potts {
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct U256 {
+  u128 lo, hi;
+};
+
+__device__ __forceinline__ void add256(U256 &a, const U256 &b) {
+  const u128 lo = a.lo + b.lo;
+  a.hi += b.hi + (lo < a.lo ? 1 : 0);
+  a.lo = lo;
+}
+
+struct Partial {
+  int64_t s1;
+  u128 s2;
+  U256 s4;
+  int64_t m1;
+  u128 m2;
+};
+
+__device__ __forceinline__ void add_partial(Partial &a, const Partial &b) {
+  a.s1 += b.s1;
+  a.s2 += b.s2;
+  add256(a.s4, b.s4);
+  a.m1 += b.m1;
+  a.m2 += b.m2;
+}
+
+__device__ double u128_to_double(u128 v) {
+  return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
+}
+
+__device__ double u256_to_double(const U256 &v) {
+  return u128_to_double(v.hi) * 340282366920938463463374607431768211456.0 + u128_to_double(v.lo);
+}
+
+// s128 = a - b for a >= 0 representation via two's complement, then to double
+__device__ double i128_to_double(__int128 v) {
+  return v < 0 ? -u128_to_double((u128)(-v)) : u128_to_double((u128)v);
+}
+
+constexpr int kStatsBlock = 256;
+
+__global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams p) {
+  __shared__ Partial part[kStatsBlock];
+  Partial acc = {};
+  for (int64_t i = threadIdx.x; i < p.n; i += kStatsBlock) {
+    const int64_t slot = (p.slot0 + i) % p.cap;
+    const unsigned long long *rec = p.ring + slot * (int64_t)(p.q + 1);
+    const uint64_t e = rec[0];
+    uint64_t nmax = 0;
+    for (uint32_t v = 0; v < p.q; ++v) nmax = rec[1 + v] > nmax ? rec[1 + v] : nmax;
+    const uint64_t e2 = e * e;
+    const u128 e4 = (u128)e2 * e2;
+    acc.s1 += (int64_t)e;
+    acc.s2 += (u128)e2;
+    add256(acc.s4, U256{e4, 0});
+    const int64_t dm = (int64_t)p.q * (int64_t)nmax - (int64_t)p.N;  // >= 0
+    acc.m1 += dm;
+    acc.m2 += (u128)((__int128)dm * dm);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kStatsBlock / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) add_partial(part[threadIdx.x], part[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const Partial s = part[0];
+  const double n = (double)p.n, N = (double)p.N, q1 = (double)(p.q - 1);
+  // e = <H>/N = -S1/(n N)
+  const double e = -(double)s.s1 / (n * N);
+  // C = beta^2 (n S2 - S1^2) / (n^2 N): exact integer numerator
+  const __int128 varnum = (__int128)(p.n) * (__int128)s.s2 - (__int128)s.s1 * (__int128)s.s1;
+  const double heat = p.beta * p.beta * (i128_to_double(varnum) / (n * n * N));
+  // V_L = 1 - n S4 / (3 S2^2)
+  const double s2d = u128_to_double(s.s2);
+  const double vl = s.s2 == 0 ? 0.0 : 1.0 - n * u256_to_double(s.s4) / (3.0 * s2d * s2d);
+  // <m> = M1 / (n N (q-1)); chi = N beta (<m^2> - <m>^2) = beta (n M2 - M1^2) / (n^2 N (q-1)^2)
+  const double m = (double)s.m1 / (n * N * q1);
+  const __int128 mvar = (__int128)(p.n) * (__int128)s.m2 - (__int128)s.m1 * (__int128)s.m1;
+  const double chi = p.beta * (i128_to_double(mvar) / (n * n * N * q1 * q1));
+  p.out[0] = e;
+  p.out[1] = heat;
+  p.out[2] = vl;
+  p.out[3] = m;
+  p.out[4] = chi;
+}
+
+}  // namespace
+
+hipError_t launch_stats(const StatsParams &p, hipStream_t stream) {
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kStatsBlock), 0, stream, p);
+  return hipGetLastError();
+}
+
+}  // namespace potts

@@ -1,0 +1,92 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every
+function include/potts.h declares, validates arguments before touching the
+device, and builds the same threshold table as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from tests.conftest import ROOT
+from tests.inputs import beta_c
+
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+def declared_functions():
+    names = []
+    for path in HEADERS:
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(potts_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1101_0876_amd as p
+
+    return p.load()
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("potts_init", "potts_sweep", "potts_observables", "potts_free", "potts_strerror"):
+        assert core in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1101_0876_amd._native import SIGNATURES
+
+    bound = {name for name, _, _ in SIGNATURES}
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in bound, f"{name} has no Python binding"
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3, beta_c(2), beta_c(6), 1.02 * np.log(4.0), beta_c(15), 3.0, 40.0])
+def test_threshold_table_matches_oracle(oracle_lib, beta):
+    import paper_1101_0876_amd as p
+
+    assert np.array_equal(p.threshold_table(beta), oracle_lib.threshold_table(beta))
+
+
+@pytest.mark.parametrize("L,q", [(0, 3), (3, 3), (6, 3), (8, 1), (8, 257), (-4, 2)])
+def test_init_rejects_bad_shapes_without_device(lib, L, q):
+    h = ctypes.c_void_p()
+    rc = lib.potts_init(L, q, 1, 1, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert lib.potts_last_error()
+
+
+def test_init_rejects_bad_start_and_null(lib):
+    h = ctypes.c_void_p()
+    assert lib.potts_init(8, 3, 1, 7, ctypes.byref(h)) == -1
+    assert lib.potts_init(8, 3, 1, 1, None) == -1
+
+
+def test_bad_beta_and_null_state(lib):
+    thr = (ctypes.c_uint32 * 4)()
+    assert lib.potts_threshold_table(-1.0, thr) == -1
+    assert lib.potts_threshold_table(float("nan"), thr) == -1
+    assert lib.potts_threshold_table(float("inf"), thr) == -1
+    assert lib.potts_sweep(None, 1.0, 1) == -1
+    assert lib.potts_observables(None, None) == -1
+    lib.potts_free(None)
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert lib.potts_strerror(code)
+
+
+def test_product_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1101_0876_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "potts_oracle" not in text and "liboracle" not in text, f

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP sweep through the C ABI against the CPU oracle, bit for bit
+on spins and integer records, to 1e-12 relative on derived FP64 statistics."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests.inputs import PARITY_CASES, beta_c, random_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*args):
+    print(*args, flush=True)
+
+
+@pytest.fixture(scope="module")
+def potts():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_0876_amd as p
+
+    p.load()
+    return p
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n", PARITY_CASES)
+def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
+    _say(f"parity L={L} q={q} seed={seed} start={start} beta={beta} n={n}")
+    want_spins, want_rec = oracle_lib.run(L, q, seed, start, beta, n)
+    with potts.Lattice(L, q, seed, start) as lat:
+        assert np.array_equal(lat.spins(), oracle_lib.init(L, q, seed, start))
+        lat.sweep(beta, n)
+        got_rec = lat.records(0, n)
+        got_spins = lat.spins()
+        obs = lat.observables()
+        meas = lat.measure()
+    assert np.array_equal(got_spins, want_spins)
+    assert np.array_equal(got_rec, want_rec)
+    assert obs["e_sat"] == want_rec[-1, 0] and np.array_equal(obs["hist"], want_rec[-1, 1:])
+    assert meas["e_sat"] == obs["e_sat"] and np.array_equal(meas["hist"], obs["hist"])
+    assert obs["nmax"] == want_rec[-1, 1:].max()
+
+
+@pytest.mark.parametrize("q", [2, 3, 16, 17, 255, 256])
+@pytest.mark.parametrize("start", [0, 1])
+def test_init_matches_oracle(potts, oracle_lib, q, start):
+    L = 68
+    _say(f"init L={L} q={q} start={start}")
+    with potts.Lattice(L, q, 77, start) as lat:
+        assert np.array_equal(lat.spins(), oracle_lib.init(L, q, 77, start))
+        m = lat.measure()
+    e, hist = oracle_lib.observables(oracle_lib.init(L, q, 77, start), q)
+    assert m["e_sat"] == e and np.array_equal(m["hist"], hist) and m["t"] == 0
+
+
+def test_beta_schedule_and_chunked_calls(potts, oracle_lib):
+    L, q, seed = 48, 9, 5
+    schedule = [(beta_c(9) * 0.98, 3), (beta_c(9), 1), (beta_c(9) * 1.02, 4), (0.0, 2), (9.0, 2)]
+    _say(f"schedule L={L} q={q}")
+    s = oracle_lib.init(L, q, seed, 1)
+    want = []
+    t = 0
+    for beta, n in schedule:
+        want.append(oracle_lib.sweeps(s, q, seed, t, n, oracle_lib.threshold_table(beta)))
+        t += n
+    with potts.Lattice(L, q, seed, 1) as lat:
+        for beta, n in schedule:
+            lat.sweep(beta, n)
+        assert lat.t == t
+        assert np.array_equal(lat.records(0, t), np.concatenate(want))
+        assert np.array_equal(lat.spins(), s)
+
+
+def test_caller_threshold_table(potts, oracle_lib):
+    L, q, seed = 16, 4, 3
+    thr = [2**31, 2**30, 12345, 0]
+    s = oracle_lib.init(L, q, seed, 1)
+    want = oracle_lib.sweeps(s, q, seed, 0, 5, thr)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep_thr(thr, 5)
+        assert np.array_equal(lat.records(0, 5), want)
+        assert np.array_equal(lat.spins(), s)
+
+
+def test_set_spins_and_resume(potts, oracle_lib, tmp_path):
+    L, q, seed, beta = 40, 7, 12, 1.1
+    base = random_lattice(L, q, seed=8)
+    s = base.copy()
+    want = oracle_lib.sweeps(s, q, seed, 1000, 6, oracle_lib.threshold_table(beta))
+    with potts.Lattice(L, q, seed, 0) as lat:
+        lat.set_spins(base, 1000)
+        lat.sweep(beta, 3)
+        path = str(tmp_path / "ck.bin")
+        lat.save(path)
+        lat.sweep(beta, 3)
+        assert np.array_equal(lat.records(1000, 6), want)
+        assert np.array_equal(lat.spins(), s)
+        with pytest.raises(potts.PottsError):
+            lat.records(999, 1)
+    with potts.Lattice.load_checkpoint(path) as lat2:
+        assert lat2.t == 1003
+        lat2.sweep(beta, 3)
+        assert np.array_equal(lat2.spins(), s)
+        assert np.array_equal(lat2.records(1003, 3), want[3:])
+
+
+def test_set_spins_rejects_values_ge_q(potts):
+    with potts.Lattice(8, 3, 1, 0) as lat:
+        bad = np.zeros((8, 8), dtype=np.uint8)
+        bad[3, 3] = 3
+        with pytest.raises(potts.PottsError):
+            lat.set_spins(bad, 0)
+
+
+def test_record_ring_wraps(potts, oracle_lib):
+    import torch
+
+    L, q, seed, beta, n, cap = 16, 5, 2, 0.9, 23, 6
+    _, want = oracle_lib.run(L, q, seed, 1, beta, n)
+    lat = potts.Lattice.from_torch(L, q, seed, 1, records_capacity=cap)
+    with lat:
+        for chunk in (4, 1, 7, 11):
+            lat.sweep(beta, chunk)
+        torch.cuda.synchronize()
+        assert np.array_equal(lat.records(n - cap + 1, cap - 1), want[n - cap + 1:])
+        with pytest.raises(potts.PottsError):
+            lat.records(n - cap, 1)
+        with pytest.raises(potts.PottsError):
+            lat.records(n - 1, 2)
+
+
+def test_torch_buffers_and_stream(potts, oracle_lib):
+    import torch
+
+    L, q, seed, beta, n = 64, 9, 1, 1.02 * math.log(4.0), 25
+    want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
+    stream = torch.cuda.Stream()
+    lat = potts.Lattice.from_torch(L, q, seed, 1, stream=stream)
+    with lat:
+        lat.sweep(beta, n)
+        stream.synchronize()
+        a, _, _ = lat._keep
+        assert lat.device_ptr() == a.data_ptr()
+        assert np.array_equal(a.cpu().numpy().reshape(L, L), want_spins)
+        assert np.array_equal(lat.records(0, n), want_rec)
+
+
+@pytest.mark.parametrize("window", [(0, 200), (150, 400), (7, 8)])
+def test_derived_stats_match_oracle(potts, oracle_lib, window):
+    from oracle.stats import derived
+
+    L, q, seed, beta, n = 32, 6, 4, beta_c(6), 400
+    _, rec = oracle_lib.run(L, q, seed, 1, beta, n)
+    t0, t1 = window
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, n)
+        got = lat.stats(t0, t1 - t0, beta)
+    want = derived(rec[t0:t1, 0].tolist(), rec[t0:t1, 1:].max(axis=1).tolist(), L * L, q, beta)
+    for k in ("e", "C", "V_L", "m", "chi"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-300), k
+
+
+def test_large_lattice_sampled_windows(potts, oracle_lib):
+    """L = 32768 (the single-large-lattice workload): sampled windows against the
+    oracle's window restriction, plus whole-lattice invariants."""
+    L, q, seed, beta, n = 32768, 6, 1, beta_c(6), 2
+    _say(f"large L={L} q={q} n={n}")
+    thr = oracle_lib.threshold_table(beta)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, n)
+        rec = lat.records(0, n)
+        spins = lat.spins()
+        meas = lat.measure()
+    N = L * L
+    assert np.all(rec[:, 1:].sum(axis=1) == N)
+    assert np.all((rec[:, 0] >= 0) & (rec[:, 0] <= 2 * N))
+    assert meas["e_sat"] == rec[-1, 0] and np.array_equal(meas["hist"], rec[-1, 1:])
+    r = 2 * n
+    for (x0, y0) in [(0, 0), (L - 20, L - 13), (12345, 777), (L // 2, L - 30), (4096, 0)]:
+        h = w = 48
+        win = oracle_lib.window(L, q, seed, 1, n, thr, x0, y0, h, w)
+        ys = (y0 + np.arange(r, h - r)) % L
+        xs = (x0 + np.arange(r, w - r)) % L
+        assert np.array_equal(win[r:h - r, r:w - r], spins[np.ix_(ys, xs)]), (x0, y0)
+
+
+def test_oracle_observables_of_large_lattice(potts, oracle_lib):
+    L, q, seed, beta = 8192, 15, 3, beta_c(15)
+    with potts.Lattice(L, q, seed, 0) as lat:
+        lat.sweep(beta, 3)
+        rec = lat.records(2, 1)
+        spins = lat.spins()
+    e, hist = oracle_lib.observables(np.ascontiguousarray(spins), q)
+    assert rec[0, 0] == e and np.array_equal(rec[0, 1:], hist)
