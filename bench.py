@@ -1,0 +1,193 @@
+"""Benchmark of the checkerboard Metropolis sweep on one MI355X.
+
+Default workload (single large lattice): q = 6, L = 32768 (2^30 uint8 spins),
+beta = beta_c(6) = ln(1 + sqrt 6), one lattice from the ordered start and one
+from the random start (seed 1), per-sweep int64 energy and q-bin population
+records.  One step = one full sweep (colour 0 then colour 1, records included)
+of both lattices.  The timed region holds exactly --steps sweeps of each
+lattice from its initial condition; warm-up sweeps run on throwaway lattices.
+
+Prints one JSON line: ns per spin flip (whole-job wall time / site updates),
+the roofline of the dominant kernel (the half-sweep kernel, timed with events
+on its own stream), and the serial CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes of full-rate 32-bit VALU issue x 2.4 GHz
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBS = 8000.0
+# one Philox4x32-10 block = 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3_b32) = 40
+# full-rate VALU instructions, and serves two site updates
+ALGO_OPS_PER_SITE = 20.0
+# a sweep reads and writes every uint8 spin once: 2 bytes per site update
+ALGO_BYTES_PER_SITE = 2.0
+KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/kernels.hip", "paper_1101_0876_amd/csrc/device.hpp"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    --pmc summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The oracle (serial C, one thread) on a bounded sample of the workload:
+    an L = 4096 lattice, q = 6, beta_c, random start, sweeps with records."""
+    import oracle
+
+    L, q, seed = 4096, 6, 1
+    beta = math.log1p(math.sqrt(q))
+    thr = oracle.threshold_table(beta)
+    spins = oracle.init(L, q, seed, oracle.RANDOM)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.sweeps(spins, q, seed, n, 1, thr, record=True)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds_target or n >= 64:
+            break
+    return {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+            "sample": f"L={L} q={q} beta_c random start, {n} sweeps with per-sweep records, 1 thread"}
+
+
+def run_large(args):
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    L, q, seed = 32768, 6, 1
+    beta = math.log1p(math.sqrt(q))
+    N = L * L
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+
+    def make():
+        return [potts.Lattice.from_torch(L, q, seed, start, device=dev, stream=stream)
+                for start in (potts.ORDERED, potts.RANDOM)]
+
+    if args.warmup > 0:
+        warm = make()
+        for lat in warm:
+            lat.sweep(beta, args.warmup)
+        stream.synchronize()
+        for lat in warm:
+            lat.close()
+        del warm
+    lats = make()
+    stream.synchronize()
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for lat in lats:
+        lat.sweep(beta, args.steps)
+    ev1.record(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+
+    # sanity on the last records (cheap): populations sum to N
+    for lat in lats:
+        rec = lat.records(args.steps - 1, 1)
+        assert int(rec[0, 1:].sum()) == N, "population sum != N"
+    for lat in lats:
+        lat.close()
+
+    site_updates = 2 * args.steps * N
+    launches = 2 * 2 * args.steps  # two half-sweep launches per sweep per lattice
+    per_launch_s = ev_ms * 1e-3 / launches
+    per_launch_sites = N / 2
+    achieved_ops = ALGO_OPS_PER_SITE * per_launch_sites / per_launch_s
+    traffic = counter_traffic("large")
+    out = {
+        "metric": "ns per spin flip",
+        "value": wall * 1e9 / site_updates,
+        "unit": "ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "single large lattice", "q": q, "L": L, "lattices": 2,
+                   "starts": ["ordered", "random"], "beta": beta, "seed": seed,
+                   "sweeps_per_lattice": args.steps, "records": "every sweep"},
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_ops / 1e12,
+            "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s",
+            "frac": achieved_ops / VALU_PEAK_OPS,
+            "traffic": traffic,
+            "kernel": "half_sweep",
+            "avg_launch_us": per_launch_s * 1e6,
+            "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
+        },
+        "hbm": {
+            "achieved_gbs": ALGO_BYTES_PER_SITE * site_updates / (ev_ms * 1e-3) / 1e9,
+            "peak_gbs": HBM_PEAK_GBS,
+            "frac": ALGO_BYTES_PER_SITE * site_updates / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_site_update": ALGO_BYTES_PER_SITE,
+        },
+        "event_ms": ev_ms,
+        "site_updates_per_s": site_updates / wall,
+        "paper_context": {"ns_per_spin_flip": 0.147, "hardware": "GTX 480 (its fastest card)"},
+    }
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="large", choices=["large"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    out = run_large(args)
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -30,6 +30,7 @@ struct potts_state {
   bool have_thr = false;
   double thr_beta = 0.0;
   uint32_t thr[4] = {0, 0, 0, 0};
+  unsigned max_groups = 2048;  // persistent grid size of the sweep kernels
 };
 
 namespace {
@@ -155,24 +156,54 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
   const int64_t rl = s->q + 1;
-  potts::SweepParams p{};
-  p.spins = s->spins;
-  p.L = (uint32_t)s->L;
-  p.q = (uint32_t)s->q;
-  p.nchunks = n_sites(s) / 4;
-  p.k0 = (uint32_t)s->seed;
-  p.k1 = (uint32_t)(s->seed >> 32);
-  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
-  for (int64_t j = 0; j < nsweeps; ++j) {
-    const int64_t t = s->t + j;
-    p.t_lo = (uint32_t)(uint64_t)t;
-    p.t_hi = (uint32_t)((uint64_t)t >> 32);
-    p.rec = s->records + (t % s->rec_cap) * rl;
-    p.rec_clear = nullptr;
-    HIP_TRY(potts::launch_half_sweep(p, 0, s->stream));
-    p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
-    HIP_TRY(potts::launch_half_sweep(p, 1, s->stream));
+  if (s->L % 16 == 0) {
+    potts::Sweep16Params p{};
+    p.spins = s->spins;
+    p.L = (uint32_t)s->L;
+    p.q = (uint32_t)s->q;
+    p.nitems = (uint32_t)(n_sites(s) / 16);
+    const uint32_t ipr = (uint32_t)s->L / 16;
+    p.row_shift = -1;
+    if ((ipr & (ipr - 1)) == 0) {
+      p.row_shift = 0;
+      while ((1u << p.row_shift) < ipr) ++p.row_shift;
+    } else {
+      // ceil(2^64 / ipr); ipr >= 3 here
+      p.row_magic = (uint64_t)(((unsigned __int128)1 << 64) / ipr) + 1;
+    }
+    p.k0 = (uint32_t)s->seed;
+    p.k1 = (uint32_t)(s->seed >> 32);
+    for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+    for (int64_t j = 0; j < nsweeps; ++j) {
+      const int64_t t = s->t + j;
+      p.t_lo = (uint32_t)(uint64_t)t;
+      p.t_hi = (uint32_t)((uint64_t)t >> 32);
+      p.rec = s->records + (t % s->rec_cap) * rl;
+      p.rec_clear = nullptr;
+      HIP_TRY(potts::launch_half_sweep16(p, 0, s->max_groups, s->stream));
+      p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
+      HIP_TRY(potts::launch_half_sweep16(p, 1, s->max_groups, s->stream));
+    }
+  } else {
+    potts::SweepParams p{};
+    p.spins = s->spins;
+    p.L = (uint32_t)s->L;
+    p.q = (uint32_t)s->q;
+    p.nchunks = n_sites(s) / 4;
+    p.k0 = (uint32_t)s->seed;
+    p.k1 = (uint32_t)(s->seed >> 32);
+    for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+    for (int64_t j = 0; j < nsweeps; ++j) {
+      const int64_t t = s->t + j;
+      p.t_lo = (uint32_t)(uint64_t)t;
+      p.t_hi = (uint32_t)((uint64_t)t >> 32);
+      p.rec = s->records + (t % s->rec_cap) * rl;
+      p.rec_clear = nullptr;
+      HIP_TRY(potts::launch_half_sweep(p, 0, s->stream));
+      p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
+      HIP_TRY(potts::launch_half_sweep(p, 1, s->stream));
+    }
   }
   s->t += nsweeps;
   return POTTS_OK;

@@ -21,6 +21,23 @@ struct SweepParams {
   unsigned long long *rec_clear;  // record slot to zero for the next sweep, or null
 };
 
+// Main path (L % 16 == 0): one work item = 16 bytes of a row.
+struct Sweep16Params {
+  uint8_t *spins;
+  uint32_t L, q;
+  uint32_t nitems;                // L*L/16
+  int32_t row_shift;              // log2(L/16) when L/16 is a power of two, else -1
+  uint64_t row_magic;             // ceil(2^64 / (L/16)) otherwise
+  uint32_t t_lo, t_hi;
+  uint32_t k0, k1;
+  Thresholds thr;
+  unsigned long long *rec;
+  unsigned long long *rec_clear;
+};
+
+// populations are counted in lane-private LDS columns up to this many states
+constexpr uint32_t kPrivateHistMaxQ = 32;
+
 struct InitParams {
   uint8_t *spins;
   uint32_t L, q;
@@ -49,6 +66,9 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
                            hipStream_t stream);
 hipError_t launch_init(const InitParams &p, hipStream_t stream);
 hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream);
+hipError_t launch_half_sweep16(const Sweep16Params &p, int colour, unsigned max_groups,
+                               hipStream_t stream);
+size_t sweep16_lds_bytes(uint32_t q, int colour);
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
 
