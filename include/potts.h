@@ -112,6 +112,14 @@ int potts_sweep(potts_state *s, double beta, int64_t nsweeps);
 /* As potts_sweep with a caller-supplied threshold table thr[0..3] (d = 1..4). */
 int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
 
+/* Launch tuning; results never depend on it (the random numbers are keyed by
+ * site and sweep, not by thread).  kernel: 0 = automatic, 1 = the 16-byte strip
+ * kernel (needs L % 16 == 0 and L <= 65536), 2 = the 4-byte chunk kernel;
+ * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
+ * L); max_groups: persistent grid size in workgroups (0 = automatic).
+ * Errors: EINVAL. */
+int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups);
+
 /* The table potts_sweep uses for beta: thr[d-1] = min(floor(exp(-beta d)
  * 2^32), 2^32-1), computed on the host in FP64.  Errors: EINVAL. */
 int potts_threshold_table(double beta, uint32_t thr[4]);

@@ -79,6 +79,10 @@ class Lattice:
         t = np.ascontiguousarray(thr, dtype=np.uint32)
         check(self._lib.potts_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(nsweeps)))
 
+    def tune(self, kernel: int = 0, strip_rows: int = 0, max_groups: int = 0) -> None:
+        """Launch shape (0 = automatic); results are identical for every choice."""
+        check(self._lib.potts_tune(self._h, int(kernel), int(strip_rows), int(max_groups)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts_time(self._h))

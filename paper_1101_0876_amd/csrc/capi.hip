@@ -30,7 +30,9 @@ struct potts_state {
   bool have_thr = false;
   double thr_beta = 0.0;
   uint32_t thr[4] = {0, 0, 0, 0};
-  unsigned max_groups = 2048;  // persistent grid size of the sweep kernels
+  int kernel = 0;          // 0 automatic, 1 strip, 2 chunk
+  uint32_t rows = 0;       // strip rows per work item, 0 = automatic
+  unsigned max_groups = 0; // persistent grid size, 0 = automatic
 };
 
 namespace {
@@ -150,6 +152,20 @@ int build_table(double beta, uint32_t thr[4]) {
   return POTTS_OK;
 }
 
+bool strip_ok(const potts_state *s) { return s->L % 16 == 0 && s->L <= 65536; }
+
+bool use_strip(const potts_state *s) { return strip_ok(s) && s->kernel != 2; }
+
+// Rows per strip item: the largest even divisor of L up to 32 that still gives
+// enough items to fill the persistent grid (2048 groups x 256 lanes).
+uint32_t strip_rows(const potts_state *s) {
+  if (s->rows) return s->rows;
+  const uint32_t L = (uint32_t)s->L, ipr = L / 16;
+  for (uint32_t r = 32; r > 2; r /= 2)
+    if (L % r == 0 && (uint64_t)(L / r) * ipr >= 2048ull * 256ull) return r;
+  return 2;
+}
+
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
@@ -157,33 +173,36 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps == 0) return POTTS_OK;
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
-  if (s->L % 16 == 0) {
-    potts::Sweep16Params p{};
+  if (use_strip(s)) {
+    potts::StripParams p{};
     p.spins = s->spins;
     p.L = (uint32_t)s->L;
     p.q = (uint32_t)s->q;
-    p.nitems = (uint32_t)(n_sites(s) / 16);
-    const uint32_t ipr = (uint32_t)s->L / 16;
-    p.row_shift = -1;
-    if ((ipr & (ipr - 1)) == 0) {
-      p.row_shift = 0;
-      while ((1u << p.row_shift) < ipr) ++p.row_shift;
+    p.ipr = (uint32_t)s->L / 16;
+    p.rows = strip_rows(s);
+    p.nitems = ((uint32_t)s->L / p.rows) * p.ipr;
+    p.item_shift = -1;
+    if ((p.ipr & (p.ipr - 1)) == 0) {
+      p.item_shift = 0;
+      while ((1u << p.item_shift) < p.ipr) ++p.item_shift;
     } else {
       // ceil(2^64 / ipr); ipr >= 3 here
-      p.row_magic = (uint64_t)(((unsigned __int128)1 << 64) / ipr) + 1;
+      p.item_magic = (uint64_t)(((unsigned __int128)1 << 64) / p.ipr) + 1;
     }
+    p.row_words = (uint32_t)s->L / 4;
     p.k0 = (uint32_t)s->seed;
     p.k1 = (uint32_t)(s->seed >> 32);
     for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+    const unsigned groups = s->max_groups ? s->max_groups : 2048u;
     for (int64_t j = 0; j < nsweeps; ++j) {
       const int64_t t = s->t + j;
       p.t_lo = (uint32_t)(uint64_t)t;
       p.t_hi = (uint32_t)((uint64_t)t >> 32);
       p.rec = s->records + (t % s->rec_cap) * rl;
       p.rec_clear = nullptr;
-      HIP_TRY(potts::launch_half_sweep16(p, 0, s->max_groups, s->stream));
+      HIP_TRY(potts::launch_strip(p, 0, groups, s->stream));
       p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
-      HIP_TRY(potts::launch_half_sweep16(p, 1, s->max_groups, s->stream));
+      HIP_TRY(potts::launch_strip(p, 1, groups, s->stream));
     }
   } else {
     potts::SweepParams p{};
@@ -289,6 +308,19 @@ int potts_sweep(potts_state *s, double beta, int64_t nsweeps) {
 int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
   return run_sweeps(s, thr, nsweeps);
+}
+
+int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (kernel < 0 || kernel > 2) return fail(POTTS_EINVAL, "kernel must be 0, 1 or 2");
+  if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65536");
+  if (strip_rows < 0 || strip_rows % 2 || (strip_rows && s->L % strip_rows))
+    return fail(POTTS_EINVAL, "strip_rows must be 0 or an even divisor of L");
+  if (max_groups < 0) return fail(POTTS_EINVAL, "max_groups must be >= 0");
+  s->kernel = kernel;
+  s->rows = (uint32_t)strip_rows;
+  s->max_groups = (unsigned)max_groups;
+  return POTTS_OK;
 }
 
 int potts_measure(potts_state *s, potts_obs *out) {

@@ -21,13 +21,17 @@ struct SweepParams {
   unsigned long long *rec_clear;  // record slot to zero for the next sweep, or null
 };
 
-// Main path (L % 16 == 0): one work item = 16 bytes of a row.
-struct Sweep16Params {
+// Main path (L % 16 == 0, L <= 65536): a work item is a 16-byte-wide strip of
+// `rows` consecutive rows (rows even, L % rows == 0).
+struct StripParams {
   uint8_t *spins;
   uint32_t L, q;
-  uint32_t nitems;                // L*L/16
-  int32_t row_shift;              // log2(L/16) when L/16 is a power of two, else -1
-  uint64_t row_magic;             // ceil(2^64 / (L/16)) otherwise
+  uint32_t ipr;         // items per row band = L/16
+  uint32_t rows;        // rows per item
+  uint32_t nitems;      // (L/rows) * (L/16)
+  int32_t item_shift;   // log2(ipr) when ipr is a power of two, else -1
+  uint64_t item_magic;  // ceil(2^64 / ipr) otherwise
+  uint32_t row_words;   // L/4: Philox counter stride between rows
   uint32_t t_lo, t_hi;
   uint32_t k0, k1;
   Thresholds thr;
@@ -66,9 +70,8 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
                            hipStream_t stream);
 hipError_t launch_init(const InitParams &p, hipStream_t stream);
 hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream);
-hipError_t launch_half_sweep16(const Sweep16Params &p, int colour, unsigned max_groups,
-                               hipStream_t stream);
-size_t sweep16_lds_bytes(uint32_t q, int colour);
+hipError_t launch_strip(const StripParams &p, int colour, unsigned max_groups, hipStream_t stream);
+size_t strip_lds_bytes(uint32_t q, int colour);
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
 

@@ -196,3 +196,46 @@ def test_oracle_observables_of_large_lattice(potts, oracle_lib):
         spins = lat.spins()
     e, hist = oracle_lib.observables(np.ascontiguousarray(spins), q)
     assert rec[0, 0] == e and np.array_equal(rec[0, 1:], hist)
+
+
+# q at the edges of the kernels' comparison modes (<=16, <=128, <=256) and of
+# the lane-private histogram (<=32); L with power-of-two and other row widths
+@pytest.mark.parametrize("L,q", [(48, 16), (48, 17), (80, 32), (80, 33), (96, 128), (112, 129),
+                                 (208, 256), (1040, 9), (64, 2), (128, 3)])
+def test_strip_kernel_q_edges(potts, oracle_lib, L, q):
+    seed, beta, n = 6, 0.9, 7
+    _say(f"q-edge L={L} q={q}")
+    want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.tune(kernel=1)
+        lat.sweep(beta, n)
+        assert np.array_equal(lat.records(0, n), want_rec)
+        assert np.array_equal(lat.spins(), want_spins)
+
+
+@pytest.mark.parametrize("L", [64, 96, 256, 1024])
+def test_launch_shape_does_not_change_results(potts, oracle_lib, L):
+    """Random numbers are keyed by (seed, site, sweep): every kernel, strip
+    height and grid size must give the same bits."""
+    q, seed, beta, n = 9, 11, 1.4, 6
+    want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
+    shapes = [(2, 0, 0), (1, 0, 0), (1, 2, 1), (1, 2, 7), (1, 4, 0), (1, 8, 3), (1, 16, 64), (1, 32, 0)]
+    for kernel, rows, groups in shapes:
+        if rows and L % rows:
+            continue
+        _say(f"shape L={L} kernel={kernel} rows={rows} groups={groups}")
+        with potts.Lattice(L, q, seed, 1) as lat:
+            lat.tune(kernel, rows, groups)
+            lat.sweep(beta, n)
+            assert np.array_equal(lat.records(0, n), want_rec), (kernel, rows, groups)
+            assert np.array_equal(lat.spins(), want_spins), (kernel, rows, groups)
+
+
+def test_tune_rejects_bad_shapes(potts):
+    with potts.Lattice(20, 3, 1, 1) as lat:
+        with pytest.raises(potts.PottsError):
+            lat.tune(kernel=1)  # 20 % 16 != 0
+        with pytest.raises(potts.PottsError):
+            lat.tune(kernel=3)
+        with pytest.raises(potts.PottsError):
+            lat.tune(kernel=0, strip_rows=3)
