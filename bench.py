@@ -171,12 +171,36 @@ def run_large(args):
     return out
 
 
+def run_copy(args):
+    """A plain device copy of 1 GiB (torch), the calibration for HBM counters
+    and the practical bandwidth ceiling."""
+    import torch
+
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    return {"metric": "copy bandwidth", "value": 2 * n / (ms * 1e-3) / 1e9, "unit": "GB/s (read+write)",
+            "bytes_read_per_launch": n, "bytes_written_per_launch": n, "ms_per_launch": ms, "reps": reps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large"])
+    ap.add_argument("--workload", default="large", choices=["large", "copy"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -184,6 +208,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "copy":
+        print(json.dumps(run_copy(args)), flush=True)
+        return
     out = run_large(args)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -40,7 +40,7 @@ struct StripParams {
 };
 
 // populations are counted in lane-private LDS columns up to this many states
-constexpr uint32_t kPrivateHistMaxQ = 32;
+constexpr uint32_t kPrivateHistMaxQ = 64;
 
 struct InitParams {
   uint8_t *spins;

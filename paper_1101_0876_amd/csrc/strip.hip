@@ -43,6 +43,82 @@ __device__ __forceinline__ uint32_t alignbyte(uint32_t hi, uint32_t lo, uint32_t
   return __builtin_amdgcn_alignbyte(hi, lo, shift);
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer access with 32-bit byte offsets (lattices below 2^32 bytes): no
+// 64-bit address arithmetic per load.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lattice_rsrc(uint8_t *spins) {
+  return __builtin_amdgcn_make_buffer_rsrc(spins, 0, (int)0xFFFFFFFFu, 0x00020000);
+}
+__device__ __forceinline__ u32x4 load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+}
+__device__ __forceinline__ uint32_t load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ void store16(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+}
+
+// Byte J of idx, scaled to a table offset (idx.byte_J << SHIFT), in one SDWA op.
+template <int J, int SHIFT>
+__device__ __forceinline__ uint32_t table_offset(uint32_t idx) {
+  uint32_t r;
+  if (J == 0)
+    asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(idx), "n"(SHIFT));
+  else if (J == 1)
+    asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(idx), "n"(SHIFT));
+  else if (J == 2)
+    asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(idx), "n"(SHIFT));
+  else
+    asm("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(idx), "n"(SHIFT));
+  return r;
+}
+
+// dst.byte_J = (w <= t) ? if_acc.byte_J : if_rej.byte_J, other bytes of dst
+// kept: one v_cmp and one SDWA v_cndmask.
+template <int J>
+__device__ __forceinline__ void accept_byte(uint32_t &dst, uint32_t w, uint32_t t, uint32_t if_rej,
+                                            uint32_t if_acc) {
+  if (J == 0)
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_0 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_0 src1_sel:BYTE_0"
+        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
+  else if (J == 1)
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_1"
+        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
+  else if (J == 2)
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_2 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_2 src1_sel:BYTE_2"
+        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
+  else
+    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_3 src1_sel:BYTE_3"
+        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
+}
+
+// As accept_byte, selecting byte J of two pairs with one compare.
+#define POTTS_ACCEPT2(J)                                                                        \
+  asm("v_cmp_le_u32 vcc, %2, %3\n\t"                                                           \
+      "v_cndmask_b32_sdwa %0, %4, %5, vcc dst_sel:BYTE_" #J                                     \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J "\n\t"              \
+      "v_cndmask_b32_sdwa %1, %6, %7, vcc dst_sel:BYTE_" #J                                     \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J                      \
+      : "+v"(dst1), "+v"(dst2)                                                                  \
+      : "v"(w), "v"(t), "v"(rej1), "v"(acc1), "v"(rej2), "v"(acc2)                              \
+      : "vcc")
+template <int J>
+__device__ __forceinline__ void accept_byte2(uint32_t &dst1, uint32_t &dst2, uint32_t w, uint32_t t,
+                                             uint32_t rej1, uint32_t acc1, uint32_t rej2, uint32_t acc2) {
+  if (J == 0) POTTS_ACCEPT2(0);
+  else if (J == 1) POTTS_ACCEPT2(1);
+  else if (J == 2) POTTS_ACCEPT2(2);
+  else POTTS_ACCEPT2(3);
+}
+#undef POTTS_ACCEPT2
+
+// Four 8-bit values (each < 256) packed into one dword, a in byte 0.
+__device__ __forceinline__ uint32_t pack4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  return perm(b, a, 0x0C0C0400u) | perm(d, c, 0x04000C0Cu);
+}
+
 // selector of the bytes at offset o and o+2 of two dwords (lo dword first)
 template <int O>
 constexpr uint32_t kSel = 0x06040200u + (uint32_t)O * 0x01010101u;
@@ -85,36 +161,36 @@ struct Sums {
   uint32_t sites;  // colour-1 sites seen
 };
 
-// One row: y is the row index, O = (colour + y) & 1 is the byte offset of the
-// active sites inside every dword.
-template <int COLOUR, int O, int CMP, bool PRIV>
-__device__ __forceinline__ void do_row(const StripParams &p, const uint64_t *table, uint8_t *hist_base,
-                                       uint32_t lane_off, uint32_t y, uint32_t col, uint32_t ctr,
-                                       Carry &cy, Sums &sums) {
-  const uint32_t L = p.L;
-  const uint32_t ro = y * L;
-  const uint32_t rn = y + 1 == L ? 0u : ro + L;
-  const uint4 nxt = *reinterpret_cast<const uint4 *>(p.spins + rn + col);
-  uint32_t side;
-  if (O == 0)  // left neighbour of the first site: byte 3 of the dword before
-    side = *reinterpret_cast<const uint32_t *>(p.spins + ro + (col == 0 ? L - 4 : col - 4));
-  else  // right neighbour of the last site: byte 0 of the dword after
-    side = *reinterpret_cast<const uint32_t *>(p.spins + ro + (col + 16 == L ? 0u : col + 16));
+// One row at byte offset ro (next row at rn).  O = (colour + y) & 1 is the
+// byte offset of the active sites inside every dword; side_col is the column
+// of the dword holding the one horizontal neighbour outside the strip.
+//
+// Acceptance table in LDS, indexed by (proposal pattern << 4 | current
+// pattern): narrow form (all thresholds >= 1) holds thr[dE-1] - 1, or
+// 2^32 - 1 when dE <= 0, and a move is accepted iff w <= entry; the wide form
+// (some threshold is 0) holds thr[dE-1], or 2^32, as u64 and accepts iff w < entry.
+template <int COLOUR, int O, int CMP, bool PRIV, bool WIDE>
+__device__ __forceinline__ void do_row(const StripParams &p, __amdgpu_buffer_rsrc_t rs,
+                                       const uint8_t *table, uint8_t *hist, uint32_t lane_off,
+                                       uint32_t ro, uint32_t rn, uint32_t col, uint32_t side_col,
+                                       uint32_t ctr, Carry &cy, Sums &sums) {
+  const u32x4 nxt = load16(rs, rn + col);
+  const uint32_t side = load4(rs, ro + side_col);
 
   const uint32_t d_lo = perm(nxt.y, nxt.x, kSel<O>), d_hi = perm(nxt.w, nxt.z, kSel<O>);
+  // horizontal neighbours: one is the passive byte at the same packed index,
+  // the other the passive byte one site over (left when O == 0, right when O == 1)
   const uint32_t x_lo = O == 0 ? alignbyte(cy.p_lo, side, 3) : alignbyte(cy.p_hi, cy.p_lo, 1);
   const uint32_t x_hi = O == 0 ? alignbyte(cy.p_hi, cy.p_lo, 3) : alignbyte(side, cy.p_hi, 1);
 
+  // block m serves dword m: (w0, w1) for its site at byte O, (w2, w3) at byte O+2
   const Words b0 = philox4x32_10(ctr + 0, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
   const Words b1 = philox4x32_10(ctr + 1, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
   const Words b2 = philox4x32_10(ctr + 2, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
   const Words b3 = philox4x32_10(ctr + 3, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
   const uint32_t q = p.q;
-  const uint32_t k_lo = scale_to_q(b0.w0, q) | (scale_to_q(b0.w2, q) << 8) |
-                        (scale_to_q(b1.w0, q) << 16) | (scale_to_q(b1.w2, q) << 24);
-  const uint32_t k_hi = scale_to_q(b2.w0, q) | (scale_to_q(b2.w2, q) << 8) |
-                        (scale_to_q(b3.w0, q) << 16) | (scale_to_q(b3.w2, q) << 24);
-  const uint32_t acc_w[8] = {b0.w1, b0.w3, b1.w1, b1.w3, b2.w1, b2.w3, b3.w1, b3.w3};
+  const uint32_t k_lo = pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
+  const uint32_t k_hi = pack4(scale_to_q(b2.w0, q), scale_to_q(b2.w2, q), scale_to_q(b3.w0, q), scale_to_q(b3.w2, q));
 
   const uint32_t ps_lo = diff_pattern<CMP>(cy.s_lo, cy.u_lo, d_lo, cy.p_lo, x_lo);
   const uint32_t ps_hi = diff_pattern<CMP>(cy.s_hi, cy.u_hi, d_hi, cy.p_hi, x_hi);
@@ -123,29 +199,67 @@ __device__ __forceinline__ void do_row(const StripParams &p, const uint64_t *tab
   const uint32_t idx_lo = bfi(0xF0F0F0F0u, pk_lo, ps_lo >> 4);
   const uint32_t idx_hi = bfi(0xF0F0F0F0u, pk_hi, ps_hi >> 4);
 
-  uint32_t sel_lo = 0x03020100u, sel_hi = 0x03020100u;
+  uint32_t ns_lo, ns_hi;  // new active bytes
+  uint32_t nz_lo = 0, nz_hi = 0;  // colour 1: flag patterns of the new spins
+  if (!WIDE) {
+    const uint32_t *t32 = reinterpret_cast<const uint32_t *>(table);
+#define POTTS_T(J, IDX) *reinterpret_cast<const uint32_t *>(table + table_offset<J, 2>(IDX))
+    const uint32_t t0 = POTTS_T(0, idx_lo), t1 = POTTS_T(1, idx_lo), t2 = POTTS_T(2, idx_lo), t3 = POTTS_T(3, idx_lo);
+    const uint32_t t4 = POTTS_T(0, idx_hi), t5 = POTTS_T(1, idx_hi), t6 = POTTS_T(2, idx_hi), t7 = POTTS_T(3, idx_hi);
+#undef POTTS_T
+    (void)t32;
+    ns_lo = cy.s_lo;
+    ns_hi = cy.s_hi;
+    if (COLOUR == 0) {
+      accept_byte<0>(ns_lo, b0.w1, t0, cy.s_lo, k_lo);
+      accept_byte<1>(ns_lo, b0.w3, t1, cy.s_lo, k_lo);
+      accept_byte<2>(ns_lo, b1.w1, t2, cy.s_lo, k_lo);
+      accept_byte<3>(ns_lo, b1.w3, t3, cy.s_lo, k_lo);
+      accept_byte<0>(ns_hi, b2.w1, t4, cy.s_hi, k_hi);
+      accept_byte<1>(ns_hi, b2.w3, t5, cy.s_hi, k_hi);
+      accept_byte<2>(ns_hi, b3.w1, t6, cy.s_hi, k_hi);
+      accept_byte<3>(ns_hi, b3.w3, t7, cy.s_hi, k_hi);
+    } else {
+      nz_lo = ps_lo;
+      nz_hi = ps_hi;
+      accept_byte2<0>(ns_lo, nz_lo, b0.w1, t0, cy.s_lo, k_lo, ps_lo, pk_lo);
+      accept_byte2<1>(ns_lo, nz_lo, b0.w3, t1, cy.s_lo, k_lo, ps_lo, pk_lo);
+      accept_byte2<2>(ns_lo, nz_lo, b1.w1, t2, cy.s_lo, k_lo, ps_lo, pk_lo);
+      accept_byte2<3>(ns_lo, nz_lo, b1.w3, t3, cy.s_lo, k_lo, ps_lo, pk_lo);
+      accept_byte2<0>(ns_hi, nz_hi, b2.w1, t4, cy.s_hi, k_hi, ps_hi, pk_hi);
+      accept_byte2<1>(ns_hi, nz_hi, b2.w3, t5, cy.s_hi, k_hi, ps_hi, pk_hi);
+      accept_byte2<2>(ns_hi, nz_hi, b3.w1, t6, cy.s_hi, k_hi, ps_hi, pk_hi);
+      accept_byte2<3>(ns_hi, nz_hi, b3.w3, t7, cy.s_hi, k_hi, ps_hi, pk_hi);
+    }
+  } else {
+    const uint64_t *t64 = reinterpret_cast<const uint64_t *>(table);
+    const uint32_t acc_w[8] = {b0.w1, b0.w3, b1.w1, b1.w3, b2.w1, b2.w3, b3.w1, b3.w3};
+    uint32_t sel_lo = 0x03020100u, sel_hi = 0x03020100u;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint64_t t_lo = table[(idx_lo >> (8 * j)) & 0xFFu];
-    const uint64_t t_hi = table[(idx_hi >> (8 * j)) & 0xFFu];
-    if ((uint64_t)acc_w[j] < t_lo) sel_lo |= 4u << (8 * j);
-    if ((uint64_t)acc_w[4 + j] < t_hi) sel_hi |= 4u << (8 * j);
+    for (int j = 0; j < 4; ++j) {
+      if ((uint64_t)acc_w[j] < t64[(idx_lo >> (8 * j)) & 0xFFu]) sel_lo |= 4u << (8 * j);
+      if ((uint64_t)acc_w[4 + j] < t64[(idx_hi >> (8 * j)) & 0xFFu]) sel_hi |= 4u << (8 * j);
+    }
+    ns_lo = perm(k_lo, cy.s_lo, sel_lo);
+    ns_hi = perm(k_hi, cy.s_hi, sel_hi);
+    if (COLOUR == 1) {
+      nz_lo = perm(pk_lo, ps_lo, sel_lo);
+      nz_hi = perm(pk_hi, ps_hi, sel_hi);
+    }
   }
-  const uint32_t ns_lo = perm(k_lo, cy.s_lo, sel_lo);
-  const uint32_t ns_hi = perm(k_hi, cy.s_hi, sel_hi);
   // interleave the new active bytes with the unchanged passive ones
   constexpr uint32_t sel_w0 = O ? 0x05010400u : 0x01050004u;
   constexpr uint32_t sel_w1 = O ? 0x07030602u : 0x03070206u;
-  uint4 out;
+  u32x4 out;
   out.x = perm(ns_lo, cy.p_lo, sel_w0);
   out.y = perm(ns_lo, cy.p_lo, sel_w1);
   out.z = perm(ns_hi, cy.p_hi, sel_w0);
   out.w = perm(ns_hi, cy.p_hi, sel_w1);
-  *reinterpret_cast<uint4 *>(p.spins + ro + col) = out;
+  store16(rs, ro + col, out);
 
   if (COLOUR == 1) {
-    sums.nz += __popc(perm(pk_lo, ps_lo, sel_lo) & 0xF0F0F0F0u) +
-               __popc(perm(pk_hi, ps_hi, sel_hi) & 0xF0F0F0F0u);
+    // differing neighbours of the new spins, 8 sites
+    sums.nz += __popc(nz_lo & 0xF0F0F0F0u) + __popc(nz_hi & 0xF0F0F0F0u);
     sums.sites += 8;
     const uint32_t words[4] = {out.x, out.y, out.z, out.w};
 #pragma unroll
@@ -153,18 +267,19 @@ __device__ __forceinline__ void do_row(const StripParams &p, const uint64_t *tab
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         if (PRIV) {
-          // byte address (value << 8) | lane*4 of this lane's counter, one v_perm
+          // counter of (value, lane) at byte (value << 8) | lane*4: one v_perm;
+          // the four waves share the lane columns (LDS atomics)
           const uint32_t addr = perm(words[m], lane_off, 0x0C0C0000u | ((4u + b) << 8));
-          atomicAdd(reinterpret_cast<uint32_t *>(hist_base + addr), 1u);
+          atomicAdd(reinterpret_cast<uint32_t *>(hist + addr), 1u);
         } else {
-          atomicAdd(reinterpret_cast<uint32_t *>(hist_base) + ((words[m] >> (8 * b)) & 0xFFu), 1u);
+          atomicAdd(reinterpret_cast<uint32_t *>(hist) + ((words[m] >> (8 * b)) & 0xFFu), 1u);
         }
       }
     }
   }
 
-  // the row below becomes current: its active bytes at the other offset, its
-  // passive bytes are exactly d; this row's passive bytes are the next "up"
+  // the row below becomes current: its active bytes sit at the other offset,
+  // its passive bytes are exactly d; this row's passive bytes are the next "up"
   cy.u_lo = cy.p_lo;
   cy.u_hi = cy.p_hi;
   cy.p_lo = d_lo;
@@ -173,38 +288,46 @@ __device__ __forceinline__ void do_row(const StripParams &p, const uint64_t *tab
   cy.s_hi = perm(nxt.w, nxt.z, kSel<O ^ 1>);
 }
 
-__device__ __forceinline__ void fill_accept_table(uint64_t *table, const Thresholds &thr) {
+template <bool WIDE>
+__device__ __forceinline__ void fill_accept_table(uint8_t *table, const Thresholds &thr) {
   // entry (k_pattern << 4 | s_pattern): dE = popcount(k_pattern) - popcount(s_pattern)
   for (uint32_t i = threadIdx.x; i < 256; i += kBlock) {
     const int de = __popc(i >> 4) - __popc(i & 15u);
-    table[i] = de <= 0 ? (1ull << 32)
-                       : (uint64_t)(de == 1 ? thr.v[0] : de == 2 ? thr.v[1] : de == 3 ? thr.v[2] : thr.v[3]);
+    const uint32_t t = de == 1 ? thr.v[0] : de == 2 ? thr.v[1] : de == 3 ? thr.v[2] : thr.v[3];
+    if (WIDE)
+      reinterpret_cast<uint64_t *>(table)[i] = de <= 0 ? (1ull << 32) : (uint64_t)t;
+    else
+      reinterpret_cast<uint32_t *>(table)[i] = de <= 0 ? 0xFFFFFFFFu : t - 1u;
   }
 }
 
-template <int COLOUR, int CMP, bool PRIV>
+template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 __global__ __launch_bounds__(kBlock) void strip_kernel(StripParams p) {
+  // acceptance table in static LDS, so its address folds into the ds_read offset
+  __shared__ __align__(16) uint32_t table_words[512];
   extern __shared__ uint32_t lds[];
-  uint64_t *table = reinterpret_cast<uint64_t *>(lds);  // 256 x u64
-  uint32_t *hist = lds + 512;  // PRIV: kWaves regions of q x 64 lane columns; else q bins
+  uint8_t *table = reinterpret_cast<uint8_t *>(table_words);  // 2 KB
+  uint32_t *hist = lds;  // PRIV: q x 64 lane columns; else q bins
   const uint32_t q = p.q;
-  uint32_t *partial = hist + (PRIV ? kWaves * 64 * q : q);  // kWaves x q, then the bond sum
+  uint32_t *partial = hist + (PRIV ? 64 * q : q);  // q totals, then the bond sum
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = threadIdx.x >> 6;
 
-  fill_accept_table(table, p.thr);
+  fill_accept_table<WIDE>(table, p.thr);
   if (COLOUR == 1) {
-    const uint32_t nh = PRIV ? kWaves * 64 * q : q;
+    const uint32_t nh = PRIV ? 64 * q : q;
     for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-    if (threadIdx.x == 0) partial[kWaves * q] = 0;
+    if (threadIdx.x == 0) partial[q] = 0;
     if (blockIdx.x == 0 && p.rec_clear)
       for (uint32_t i = threadIdx.x; i < q + 1; i += kBlock) p.rec_clear[i] = 0;
   }
   __syncthreads();
 
-  uint8_t *hist_base = reinterpret_cast<uint8_t *>(hist + (PRIV ? wave * 64u * q : 0u));
+  const __amdgpu_buffer_rsrc_t rs = lattice_rsrc(p.spins);
+  uint8_t *hist_bytes = reinterpret_cast<uint8_t *>(hist);
   const uint32_t lane_off = lane * 4u;
   const uint32_t L = p.L;
+  const uint32_t rows = p.rows;
   Sums sums{0, 0};
 
   for (uint32_t item = blockIdx.x * kBlock + threadIdx.x; item < p.nitems;
@@ -213,10 +336,14 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripParams p) {
                                           : (uint32_t)__umul64hi((uint64_t)item, p.item_magic);
     const uint32_t xi = item - rb * p.ipr;
     const uint32_t col = xi * 16u;
-    const uint32_t r0 = rb * p.rows;  // even, so row r0 has active offset COLOUR
+    const uint32_t left_col = col == 0 ? L - 4 : col - 4;       // dword left of the strip
+    const uint32_t right_col = col + 16 == L ? 0u : col + 16;   // dword right of the strip
+    const uint32_t r0 = rb * rows;  // even, so row r0 has active offset COLOUR
     const uint32_t rp = (r0 == 0 ? L - 1 : r0 - 1) * L;
-    const uint4 prev = *reinterpret_cast<const uint4 *>(p.spins + rp + col);
-    const uint4 cur = *reinterpret_cast<const uint4 *>(p.spins + r0 * L + col);
+    const uint32_t last_next = r0 + rows == L ? 0u : (r0 + rows) * L;
+    uint32_t ro = r0 * L;
+    const u32x4 prev = load16(rs, rp + col);
+    const u32x4 cur = load16(rs, ro + col);
     Carry cy;
     cy.s_lo = perm(cur.y, cur.x, kSel<COLOUR>);
     cy.s_hi = perm(cur.w, cur.z, kSel<COLOUR>);
@@ -225,64 +352,68 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripParams p) {
     cy.u_lo = perm(prev.y, prev.x, kSel<COLOUR>);
     cy.u_hi = perm(prev.w, prev.z, kSel<COLOUR>);
     uint32_t ctr = r0 * p.row_words + xi * 4u;
-    for (uint32_t k = 0; k < p.rows; k += 2) {
-      do_row<COLOUR, COLOUR, CMP, PRIV>(p, table, hist_base, lane_off, r0 + k, col, ctr, cy, sums);
+    constexpr uint32_t kSideA = COLOUR == 0 ? 0 : 1;  // row parity 0: side dword on the left
+    for (uint32_t k = 0; k < rows; k += 2) {
+      do_row<COLOUR, COLOUR, CMP, PRIV, WIDE>(p, rs, table, hist_bytes, lane_off, ro, ro + L, col,
+                                              kSideA ? right_col : left_col, ctr, cy, sums);
+      ro += L;
       ctr += p.row_words;
-      do_row<COLOUR, COLOUR ^ 1, CMP, PRIV>(p, table, hist_base, lane_off, r0 + k + 1, col, ctr, cy,
-                                            sums);
+      const uint32_t rn = k + 2 == rows ? last_next : ro + L;
+      do_row<COLOUR, COLOUR ^ 1, CMP, PRIV, WIDE>(p, rs, table, hist_bytes, lane_off, ro, rn, col,
+                                                  kSideA ? left_col : right_col, ctr, cy, sums);
+      ro += L;
       ctr += p.row_words;
     }
   }
 
   if (COLOUR == 1) {
-    uint32_t *esum = partial + kWaves * q;
+    uint32_t *esum = partial + q;
     const uint32_t e = wave_sum(4u * sums.sites - sums.nz);
     if (lane == 0 && e) atomicAdd(esum, e);
     __syncthreads();
     if (PRIV) {
-      const uint32_t *mine = hist + wave * 64u * q;
-      for (uint32_t v = 0; v < q; ++v) {
-        const uint32_t s = wave_sum(mine[v * 64u + lane]);
-        if (lane == 0) partial[wave * q + v] = s;
+      for (uint32_t v = wave; v < q; v += kWaves) {
+        const uint32_t s = wave_sum(hist[v * 64u + lane]);
+        if (lane == 0) partial[v] = s;
       }
       __syncthreads();
     }
     for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
-      uint32_t s = 0;
-      if (PRIV) {
-        for (int w = 0; w < kWaves; ++w) s += partial[w * q + v];
-      } else {
-        s = hist[v];
-      }
+      const uint32_t s = PRIV ? partial[v] : hist[v];
       if (s) atomicAdd(&p.rec[1 + v], (unsigned long long)s);
     }
     if (threadIdx.x == 0 && *esum) atomicAdd(&p.rec[0], (unsigned long long)*esum);
   }
 }
 
-template <int COLOUR, int CMP, bool PRIV>
+template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 hipError_t launch_t(const StripParams &p, unsigned grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV>), dim3(grid), dim3(kBlock), lds, stream, p);
+  hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE>), dim3(grid), dim3(kBlock), lds, stream, p);
   return hipGetLastError();
+}
+
+template <int COLOUR, bool WIDE>
+hipError_t launch_w(const StripParams &p, unsigned grid, size_t lds, hipStream_t stream) {
+  if (p.q <= 16) return launch_t<COLOUR, 0, true, WIDE>(p, grid, lds, stream);
+  if (p.q <= kPrivateHistMaxQ) return launch_t<COLOUR, 1, true, WIDE>(p, grid, lds, stream);
+  if (p.q <= 128) return launch_t<COLOUR, 1, false, WIDE>(p, grid, lds, stream);
+  return launch_t<COLOUR, 2, false, WIDE>(p, grid, lds, stream);
 }
 
 template <int COLOUR>
 hipError_t launch_c(const StripParams &p, unsigned grid, size_t lds, hipStream_t stream) {
-  const bool priv = p.q <= kPrivateHistMaxQ;
-  if (p.q <= 16)
-    return priv ? launch_t<COLOUR, 0, true>(p, grid, lds, stream) : launch_t<COLOUR, 0, false>(p, grid, lds, stream);
-  if (p.q <= 128)
-    return priv ? launch_t<COLOUR, 1, true>(p, grid, lds, stream) : launch_t<COLOUR, 1, false>(p, grid, lds, stream);
-  return launch_t<COLOUR, 2, false>(p, grid, lds, stream);
+  const bool wide = p.thr.v[0] == 0 || p.thr.v[1] == 0 || p.thr.v[2] == 0 || p.thr.v[3] == 0;
+  return wide ? launch_w<COLOUR, true>(p, grid, lds, stream) : launch_w<COLOUR, false>(p, grid, lds, stream);
 }
 
 }  // namespace
 
+// dynamic LDS: the population counters and totals (the table is static)
 size_t strip_lds_bytes(uint32_t q, int colour) {
-  if (colour == 0) return 256 * 8;  // acceptance table only
+  if (colour == 0) return 0;
   const bool priv = q <= kPrivateHistMaxQ;
-  const size_t hist_words = priv ? (size_t)kWaves * 64 * q : q;
-  return 256 * 8 + hist_words * 4 + ((size_t)kWaves * q + 1) * 4;
+  const size_t hist_words = priv ? (size_t)64 * q : q;
+  return hist_words * 4 + ((size_t)q + 1) * 4;
 }
 
 hipError_t launch_strip(const StripParams &p, int colour, unsigned max_groups, hipStream_t stream) {
