@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 ALGO_OPS_PER_SITE = 20.0
 # a sweep reads and writes every uint8 spin once: 2 bytes per site update
 ALGO_BYTES_PER_SITE = 2.0
-KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/kernels.hip", "paper_1101_0876_amd/csrc/device.hpp"]
+KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/strip.hip", "paper_1101_0876_amd/csrc/device.hpp"]
 
 
 def kernel_hash() -> str:

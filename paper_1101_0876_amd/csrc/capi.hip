@@ -157,7 +157,7 @@ bool strip_ok(const potts_state *s) { return s->L % 16 == 0 && s->L <= 65536; }
 bool use_strip(const potts_state *s) { return strip_ok(s) && s->kernel != 2; }
 
 // Rows per strip item: the largest even divisor of L up to 32 that still gives
-// enough items to fill the persistent grid (2048 groups x 256 lanes).
+// at least 2048 x 256 items (eight workgroups of 256 lanes per CU).
 uint32_t strip_rows(const potts_state *s) {
   if (s->rows) return s->rows;
   const uint32_t L = (uint32_t)s->L, ipr = L / 16;
@@ -193,7 +193,7 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     p.k0 = (uint32_t)s->seed;
     p.k1 = (uint32_t)(s->seed >> 32);
     for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
-    const unsigned groups = s->max_groups ? s->max_groups : 2048u;
+    const unsigned groups = s->max_groups ? s->max_groups : 8192u;
     for (int64_t j = 0; j < nsweeps; ++j) {
       const int64_t t = s->t + j;
       p.t_lo = (uint32_t)(uint64_t)t;
