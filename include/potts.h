@@ -87,7 +87,8 @@ typedef struct {
 } potts_summary;
 
 /* Creates a state: allocates the lattice, a second lattice buffer and a ring of
- * records_capacity per-sweep records (0 selects 4096) on the current HIP
+ * per-sweep records (4096 slots; potts_init_ex: records_capacity rounded up to
+ * a power of two, 0 selects 4096; at most 2^40) on the current HIP
  * device, creates a stream, and writes the initial condition (Sec. 3:
  * heating starts ordered, cooling starts random).
  * Errors: EINVAL (L < 4, L % 4 != 0, q outside 2..256, bad start, out NULL),
@@ -114,7 +115,9 @@ int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
 
 /* Launch tuning; results never depend on it (the random numbers are keyed by
  * site and sweep, not by thread).  kernel: 0 = automatic, 1 = the 16-byte strip
- * kernel (needs L % 16 == 0 and L <= 65536), 2 = the 4-byte chunk kernel;
+ * kernel (needs L % 16 == 0 and L <= 65536), 2 = the 4-byte chunk kernel,
+ * 3 = the LDS-resident kernel (L % 16 == 0, L <= 256: one workgroup keeps the
+ * lattice in LDS and runs all sweeps of a call in one launch);
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
  * L); max_groups: persistent grid size in workgroups (0 = automatic).
  * Errors: EINVAL. */
@@ -141,6 +144,23 @@ int potts_records(potts_state *s, int64_t t0, int64_t n, int64_t *out);
  * temperature beta (synchronizes).  Errors: ERANGE as potts_records, EINVAL
  * for n < 1. */
 int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summary *out);
+
+/* Grows (or shrinks) the record ring to `capacity` sweeps (2 .. 2^40, rounded
+ * up to a power of two).  Records held before the call are discarded.  Synchronizes.  Errors: EINVAL, ENOMEM. */
+int potts_reserve_records(potts_state *s, int64_t capacity);
+
+/* Temperature ramp (the simulation protocol of Sec. 3): for k = 0..npoints-1,
+ * runs t_equil sweeps and then t_meas sweeps at betas[k], the configuration
+ * carrying over from point to point, and writes the derived statistics of the
+ * t_meas measurement sweeps to out[k] (caller-owned, npoints entries).
+ * Heating starts from the ordered state with beta descending, cooling from the
+ * random state with beta ascending; the caller picks the start and order.
+ * All work is queued on the state's stream and the call synchronizes once at
+ * the end.  The record ring is grown to hold t_meas records when needed.
+ * Errors: EINVAL (NULL, npoints < 1, t_equil < 0, t_meas < 1 or > 2^24, bad
+ * beta), ENOMEM, EDEVICE. */
+int potts_ramp(potts_state *s, const double *betas, int32_t npoints, int64_t t_equil, int64_t t_meas,
+               potts_summary *out);
 
 /* Host copies of the lattice (synchronize).  set_spins also sets the sweep
  * counter t; values must be < q (EINVAL otherwise). */

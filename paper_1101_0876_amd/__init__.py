@@ -110,6 +110,18 @@ class Lattice:
         check(self._lib.potts_stats(self._h, int(t0), int(n), float(beta), ctypes.byref(s)))
         return {"n": s.n, "e": s.e, "C": s.C, "V_L": s.V_L, "m": s.m, "chi": s.chi}
 
+    def reserve_records(self, capacity: int) -> None:
+        check(self._lib.potts_reserve_records(self._h, int(capacity)))
+
+    def ramp(self, betas, t_equil: int, t_meas: int) -> list:
+        """Runs t_equil + t_meas sweeps at each beta in turn (state carried over)
+        and returns the derived statistics of each point's last t_meas sweeps."""
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        out = (PottsSummary * len(b))()
+        check(self._lib.potts_ramp(self._h, b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(b),
+                                   int(t_equil), int(t_meas), out))
+        return [{"n": o.n, "e": o.e, "C": o.C, "V_L": o.V_L, "m": o.m, "chi": o.chi} for o in out]
+
     # -- lattice access -----------------------------------------------------------
     def spins(self) -> np.ndarray:
         out = np.zeros(self.L * self.L, dtype=np.uint8)

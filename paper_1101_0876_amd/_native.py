@@ -59,6 +59,9 @@ SIGNATURES = [
     ("potts_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
     ("potts_stats", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                    ctypes.POINTER(PottsSummary)]),
+    ("potts_reserve_records", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("potts_ramp", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.POINTER(PottsSummary)]),
     ("potts_get_spins", ctypes.c_int, [_VP, _U8P]),
     ("potts_set_spins", ctypes.c_int, [_VP, _U8P, ctypes.c_int64]),
     ("potts_device_spins", _VP, [_VP]),

@@ -30,7 +30,7 @@ struct potts_state {
   bool have_thr = false;
   double thr_beta = 0.0;
   uint32_t thr[4] = {0, 0, 0, 0};
-  int kernel = 0;          // 0 automatic, 1 strip, 2 chunk
+  int kernel = 0;          // 0 automatic, 1 strip, 2 chunk, 3 LDS-resident
   uint32_t rows = 0;       // strip rows per work item, 0 = automatic
   unsigned max_groups = 0; // persistent grid size, 0 = automatic
 };
@@ -53,6 +53,14 @@ int hip_fail(hipError_t e, const char *what) {
     hipError_t hip_err_ = (call);                      \
     if (hip_err_ != hipSuccess) return hip_fail(hip_err_, #call); \
   } while (0)
+
+// The ring holds a power-of-two number of slots (>= the capacity asked for),
+// so kernels find a sweep's slot with a mask.
+int64_t ring_slots(int64_t capacity) {
+  int64_t n = 2;
+  while (n < capacity) n <<= 1;
+  return n;
+}
 
 bool valid_shape(int32_t L, int32_t q) { return L >= 4 && L % 4 == 0 && q >= 2 && q <= POTTS_QMAX; }
 
@@ -94,7 +102,8 @@ int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spi
   if ((uint64_t)L * (uint64_t)L / 4 >= (1ull << 32))
     return fail(POTTS_ERANGE, "L*L/4 must be below 2^32 (Philox counter word)");
   if (rec_cap == 0) rec_cap = 4096;
-  if (rec_cap < 2) return fail(POTTS_EINVAL, "records_capacity must be >= 2");
+  if (rec_cap < 2 || rec_cap > (1ll << 40)) return fail(POTTS_EINVAL, "records_capacity must be in 2 .. 2^40");
+  rec_cap = ring_slots(rec_cap);
   const size_t nbytes = (size_t)L * (size_t)L;
   if (external && (!dev_spins || !dev_spins2 || bytes < nbytes))
     return fail(POTTS_EINVAL, "external buffers missing or smaller than L*L bytes");
@@ -154,16 +163,86 @@ int build_table(double beta, uint32_t thr[4]) {
 
 bool strip_ok(const potts_state *s) { return s->L % 16 == 0 && s->L <= 65536; }
 
-bool use_strip(const potts_state *s) { return strip_ok(s) && s->kernel != 2; }
+bool resident_ok(const potts_state *s) { return potts::resident_fits((uint32_t)s->L, (uint32_t)s->q); }
 
-// Rows per strip item: the largest even divisor of L up to 32 that still gives
-// at least 2048 x 256 items (eight workgroups of 256 lanes per CU).
-uint32_t strip_rows(const potts_state *s) {
-  if (s->rows) return s->rows;
-  const uint32_t L = (uint32_t)s->L, ipr = L / 16;
+bool use_resident(const potts_state *s) {
+  return resident_ok(s) && (s->kernel == 3 || s->kernel == 0);
+}
+
+bool use_strip(const potts_state *s) { return strip_ok(s) && (s->kernel == 1 || s->kernel == 0); }
+
+bool wide_table(const uint32_t thr[4]) { return !thr[0] || !thr[1] || !thr[2] || !thr[3]; }
+
+}  // namespace
+
+namespace potts {
+
+// Fills the per-lattice descriptor of the strip kernel (not t0/nsweeps/ring).
+void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, uint64_t seed,
+                       const uint32_t thr[4], uint32_t rows) {
+  p.spins = spins;
+  p.L = L;
+  p.q = q;
+  p.ipr = L / 16;
+  p.rows = rows;
+  p.nitems = (L / rows) * p.ipr;
+  p.item_shift = -1;
+  p.item_magic = 0;
+  if ((p.ipr & (p.ipr - 1)) == 0) {
+    p.item_shift = 0;
+    while ((1u << p.item_shift) < p.ipr) ++p.item_shift;
+  } else {
+    // ceil(2^64 / ipr); ipr >= 3 here
+    p.item_magic = (uint64_t)(((unsigned __int128)1 << 64) / p.ipr) + 1;
+  }
+  p.row_words = L / 4;
+  p.k0 = (uint32_t)seed;
+  p.k1 = (uint32_t)(seed >> 32);
+  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+}
+
+// Rows per strip item: the largest even divisor of L up to 32 that still
+// gives at least `want` items.
+uint32_t auto_strip_rows(uint32_t L, uint64_t want) {
+  const uint32_t ipr = L / 16;
   for (uint32_t r = 32; r > 2; r /= 2)
-    if (L % r == 0 && (uint64_t)(L / r) * ipr >= 2048ull * 256ull) return r;
+    if (L % r == 0 && (uint64_t)(L / r) * ipr >= want) return r;
   return 2;
+}
+
+}  // namespace potts
+
+namespace {
+
+using potts::fill_strip_params;
+
+// Sweeps whose records the resident kernel writes whole: no slot clearing.
+int run_resident(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  potts::ResidentLaunch p{};
+  p.jobs = nullptr;
+  potts::ResidentJob &j = p.single;
+  j.spins = s->spins;
+  j.L = (uint32_t)s->L;
+  j.q = (uint32_t)s->q;
+  j.k0 = (uint32_t)s->seed;
+  j.k1 = (uint32_t)(s->seed >> 32);
+  for (int i = 0; i < 4; ++i) j.thr.v[i] = thr[i];
+  j.ring = s->records;
+  j.cap = (uint64_t)s->rec_cap;
+  const int64_t chunk = 4096;  // bounds one launch's duration
+  for (int64_t done = 0; done < nsweeps; done += chunk) {
+    j.t0 = (uint64_t)(s->t + done);
+    j.nsweeps = (uint32_t)std::min<int64_t>(chunk, nsweeps - done);
+    HIP_TRY(potts::launch_resident(p, 1, j.L, j.q, wide_table(thr), s->stream));
+  }
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
+// rows per strip item: at least 2048 x 256 items (eight workgroups of 256
+// lanes per CU) when the lattice allows it
+uint32_t strip_rows(const potts_state *s) {
+  return s->rows ? s->rows : potts::auto_strip_rows((uint32_t)s->L, 2048ull * 256ull);
 }
 
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
@@ -171,38 +250,25 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
+  if (use_resident(s)) return run_resident(s, thr, nsweeps);
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
   if (use_strip(s)) {
-    potts::StripParams p{};
-    p.spins = s->spins;
-    p.L = (uint32_t)s->L;
-    p.q = (uint32_t)s->q;
-    p.ipr = (uint32_t)s->L / 16;
-    p.rows = strip_rows(s);
-    p.nitems = ((uint32_t)s->L / p.rows) * p.ipr;
-    p.item_shift = -1;
-    if ((p.ipr & (p.ipr - 1)) == 0) {
-      p.item_shift = 0;
-      while ((1u << p.item_shift) < p.ipr) ++p.item_shift;
-    } else {
-      // ceil(2^64 / ipr); ipr >= 3 here
-      p.item_magic = (uint64_t)(((unsigned __int128)1 << 64) / p.ipr) + 1;
-    }
-    p.row_words = (uint32_t)s->L / 4;
-    p.k0 = (uint32_t)s->seed;
-    p.k1 = (uint32_t)(s->seed >> 32);
-    for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+    potts::StripLaunch l{};
+    potts::StripParams &p = l.single;
+    fill_strip_params(p, s->spins, (uint32_t)s->L, (uint32_t)s->q, s->seed, thr, strip_rows(s));
+    p.t0 = (uint64_t)s->t;
+    p.nsweeps = (uint64_t)nsweeps;
+    p.ring = s->records;
+    p.cap = (uint64_t)s->rec_cap;
     const unsigned groups = s->max_groups ? s->max_groups : 8192u;
+    const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
+    const unsigned grid = (unsigned)(need < groups ? need : groups);
+    const bool wide = wide_table(thr);
     for (int64_t j = 0; j < nsweeps; ++j) {
-      const int64_t t = s->t + j;
-      p.t_lo = (uint32_t)(uint64_t)t;
-      p.t_hi = (uint32_t)((uint64_t)t >> 32);
-      p.rec = s->records + (t % s->rec_cap) * rl;
-      p.rec_clear = nullptr;
-      HIP_TRY(potts::launch_strip(p, 0, groups, s->stream));
-      p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
-      HIP_TRY(potts::launch_strip(p, 1, groups, s->stream));
+      l.sweep = (uint32_t)j;
+      HIP_TRY(potts::launch_strip(l, 0, grid, p.q, wide, s->stream));
+      HIP_TRY(potts::launch_strip(l, 1, grid, p.q, wide, s->stream));
     }
   } else {
     potts::SweepParams p{};
@@ -312,8 +378,10 @@ int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
 
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
-  if (kernel < 0 || kernel > 2) return fail(POTTS_EINVAL, "kernel must be 0, 1 or 2");
+  if (kernel < 0 || kernel > 3) return fail(POTTS_EINVAL, "kernel must be 0, 1, 2 or 3");
   if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65536");
+  if (kernel == 3 && !resident_ok(s))
+    return fail(POTTS_EINVAL, "LDS-resident kernel needs L % 16 == 0, L*L <= 65536 and LDS for q");
   if (strip_rows < 0 || strip_rows % 2 || (strip_rows && s->L % strip_rows))
     return fail(POTTS_EINVAL, "strip_rows must be 0 or an even divisor of L");
   if (max_groups < 0) return fail(POTTS_EINVAL, "max_groups must be >= 0");
@@ -382,6 +450,82 @@ int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summar
   out->V_L = v[2];
   out->m = v[3];
   out->chi = v[4];
+  return POTTS_OK;
+}
+
+int potts_reserve_records(potts_state *s, int64_t capacity) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (capacity < 2 || capacity > (1ll << 40)) return fail(POTTS_EINVAL, "capacity must be in 2 .. 2^40");
+  capacity = ring_slots(capacity);
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  unsigned long long *ring = nullptr;
+  const size_t bytes = (size_t)capacity * (size_t)(s->q + 1) * sizeof(unsigned long long);
+  if (hipMalloc(&ring, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(POTTS_ENOMEM, "hipMalloc of the record ring failed");
+  }
+  HIP_TRY(hipFree(s->records));
+  s->records = ring;
+  s->rec_cap = capacity;
+  s->rec_from = s->t;
+  return POTTS_OK;
+}
+
+int potts_ramp(potts_state *s, const double *betas, int32_t npoints, int64_t t_equil, int64_t t_meas,
+               potts_summary *out) {
+  if (!s || !betas || !out) return fail(POTTS_EINVAL, "NULL argument");
+  if (npoints < 1 || t_equil < 0 || t_meas < 1 || t_meas > (1ll << 24))
+    return fail(POTTS_EINVAL, "need npoints >= 1, t_equil >= 0, 1 <= t_meas <= 2^24");
+  if ((t_equil + t_meas) * (int64_t)npoints > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
+  std::vector<uint32_t> tables((size_t)npoints * 4);
+  for (int32_t k = 0; k < npoints; ++k) {
+    int rc = build_table(betas[k], &tables[(size_t)k * 4]);
+    if (rc) return rc;
+  }
+  if (s->rec_cap < t_meas + 1) {
+    int rc = potts_reserve_records(s, t_meas + 1);
+    if (rc) return rc;
+  }
+  double *dev_out = nullptr;
+  if (hipMalloc(&dev_out, (size_t)npoints * 8 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(POTTS_ENOMEM, "hipMalloc of the ramp results failed");
+  }
+  int rc = POTTS_OK;
+  for (int32_t k = 0; k < npoints && rc == POTTS_OK; ++k) {
+    rc = run_sweeps(s, &tables[(size_t)k * 4], t_equil + t_meas);
+    if (rc) break;
+    potts::StatsParams p{};
+    p.ring = s->records;
+    p.cap = s->rec_cap;
+    p.slot0 = (s->t - t_meas) % s->rec_cap;
+    p.n = t_meas;
+    p.q = (uint32_t)s->q;
+    p.N = n_sites(s);
+    p.beta = betas[k];
+    p.out = dev_out + (size_t)k * 8;
+    hipError_t e = potts::launch_stats(p, s->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "launch_stats");
+  }
+  std::vector<double> host((size_t)npoints * 8);
+  if (rc == POTTS_OK) {
+    hipError_t e = hipMemcpyAsync(host.data(), dev_out, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "ramp results copy");
+  } else {
+    (void)hipStreamSynchronize(s->stream);
+  }
+  (void)hipFree(dev_out);
+  if (rc) return rc;
+  for (int32_t k = 0; k < npoints; ++k) {
+    const double *v = &host[(size_t)k * 8];
+    out[k].n = t_meas;
+    out[k].e = v[0];
+    out[k].C = v[1];
+    out[k].V_L = v[2];
+    out[k].m = v[3];
+    out[k].chi = v[4];
+  }
   return POTTS_OK;
 }
 

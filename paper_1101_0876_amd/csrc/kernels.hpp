@@ -22,7 +22,9 @@ struct SweepParams {
 };
 
 // Main path (L % 16 == 0, L <= 65536): a work item is a 16-byte-wide strip of
-// `rows` consecutive rows (rows even, L % rows == 0).
+// `rows` consecutive rows (rows even, L % rows == 0).  One StripParams per
+// lattice ("job"); it does not change between sweeps, so one table serves
+// every launch of a captured graph.
 struct StripParams {
   uint8_t *spins;
   uint32_t L, q;
@@ -32,15 +34,49 @@ struct StripParams {
   int32_t item_shift;   // log2(ipr) when ipr is a power of two, else -1
   uint64_t item_magic;  // ceil(2^64 / ipr) otherwise
   uint32_t row_words;   // L/4: Philox counter stride between rows
-  uint32_t t_lo, t_hi;
-  uint32_t k0, k1;
+  uint32_t k0, k1;      // Philox key = seed
   Thresholds thr;
-  unsigned long long *rec;
-  unsigned long long *rec_clear;
+  uint64_t t0;          // sweep index of launch sweep 0
+  uint64_t nsweeps;     // launches with sweep >= nsweeps leave this job alone
+  unsigned long long *ring;  // records of sweep t in slot t % cap
+  uint64_t cap;              // a power of two
+};
+
+// Workgroup -> (job, item range) for launches that sweep many lattices.
+struct StripTile {
+  uint32_t job;
+  uint32_t first;  // first item of the range
+  uint32_t count;  // items in the range (<= 256: one per lane)
+  uint32_t lead;   // 1 for one tile per job: it clears the next record slot
+};
+
+struct StripLaunch {
+  const StripParams *jobs;  // null: run `single` over a grid-stride loop
+  const StripTile *tiles;
+  StripParams single;
+  uint32_t sweep;           // this launch updates sweep t = t0 + sweep of every job
 };
 
 // populations are counted in lane-private LDS columns up to this many states
 constexpr uint32_t kPrivateHistMaxQ = 64;
+
+// One lattice run entirely in LDS by one workgroup (resident.hip).
+struct ResidentJob {
+  uint8_t *spins;                 // L*L bytes, updated in place
+  uint32_t L, q;
+  uint32_t k0, k1;                // Philox key = seed
+  uint64_t t0;                    // sweep index of the first sweep
+  uint32_t nsweeps;
+  Thresholds thr;
+  unsigned long long *ring;       // records of sweep t go to slot t % cap
+  uint64_t cap;                   // a power of two
+};
+
+// A launch: jobs[blockIdx.x] from device memory, or `single` when jobs is null.
+struct ResidentLaunch {
+  const ResidentJob *jobs;
+  ResidentJob single;
+};
 
 struct InitParams {
   uint8_t *spins;
@@ -59,19 +95,31 @@ struct MeasureParams {
 
 struct StatsParams {
   const unsigned long long *ring;  // record ring, cap slots of (1+q) int64
-  int64_t cap, slot0, n;           // window: n records starting at slot0 (wrapping)
+  int64_t cap, slot0, n;           // window: n records from slot0 (wrapping; cap a power of two)
   uint32_t q;
   uint64_t N;
   double beta;
   double *out;                     // e, C, V_L, m, chi
 };
 
+void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, uint64_t seed,
+                       const uint32_t thr[4], uint32_t rows);
+uint32_t auto_strip_rows(uint32_t L, uint64_t want);
+
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
                            hipStream_t stream);
 hipError_t launch_init(const InitParams &p, hipStream_t stream);
 hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream);
-hipError_t launch_strip(const StripParams &p, int colour, unsigned max_groups, hipStream_t stream);
+// grid: number of workgroups (tiles when l.jobs is set); max_q/wide: the
+// comparison mode and table form covering every job of the launch
+hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
+                        hipStream_t stream);
 size_t strip_lds_bytes(uint32_t q, int colour);
+size_t resident_lds_bytes(uint32_t L, uint32_t q);
+bool resident_fits(uint32_t L, uint32_t q);
+// n jobs (n workgroups); LDS sized for the largest L and q among them
+hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max_L, uint32_t max_q,
+                           bool wide, hipStream_t stream);
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
 

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams p) {
   __shared__ Partial part[kStatsBlock];
   Partial acc = {};
   for (int64_t i = threadIdx.x; i < p.n; i += kStatsBlock) {
-    const int64_t slot = (p.slot0 + i) % p.cap;
+    const int64_t slot = (p.slot0 + i) & (p.cap - 1);
     const unsigned long long *rec = p.ring + slot * (int64_t)(p.q + 1);
     const uint64_t e = rec[0];
     uint64_t nmax = 0;

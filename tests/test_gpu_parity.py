@@ -116,21 +116,26 @@ def test_set_spins_rejects_values_ge_q(potts):
             lat.set_spins(bad, 0)
 
 
-def test_record_ring_wraps(potts, oracle_lib):
+@pytest.mark.parametrize("asked,slots", [(6, 8), (8, 8), (2, 2)])
+def test_record_ring_wraps(potts, oracle_lib, asked, slots):
+    """The ring keeps a power-of-two number of slots (>= the capacity asked
+    for); the last slots - 1 records survive any chunking of the sweeps."""
     import torch
 
-    L, q, seed, beta, n, cap = 16, 5, 2, 0.9, 23, 6
+    L, q, seed, beta, n = 16, 5, 2, 0.9, 23
     _, want = oracle_lib.run(L, q, seed, 1, beta, n)
-    lat = potts.Lattice.from_torch(L, q, seed, 1, records_capacity=cap)
-    with lat:
-        for chunk in (4, 1, 7, 11):
-            lat.sweep(beta, chunk)
-        torch.cuda.synchronize()
-        assert np.array_equal(lat.records(n - cap + 1, cap - 1), want[n - cap + 1:])
-        with pytest.raises(potts.PottsError):
-            lat.records(n - cap, 1)
-        with pytest.raises(potts.PottsError):
-            lat.records(n - 1, 2)
+    for kernel in (2, 3):  # records cleared per sweep (chunk kernel) / written whole (resident)
+        lat = potts.Lattice.from_torch(L, q, seed, 1, records_capacity=asked)
+        with lat:
+            lat.tune(kernel=kernel)
+            for chunk in (4, 1, 7, 11):
+                lat.sweep(beta, chunk)
+            torch.cuda.synchronize()
+            assert np.array_equal(lat.records(n - slots + 1, slots - 1), want[n - slots + 1:])
+            with pytest.raises(potts.PottsError):
+                lat.records(n - slots, 1)
+            with pytest.raises(potts.PottsError):
+                lat.records(n - 1, 2)
 
 
 def test_torch_buffers_and_stream(potts, oracle_lib):
@@ -200,16 +205,42 @@ def test_oracle_observables_of_large_lattice(potts, oracle_lib):
 
 # q at the edges of the kernels' comparison modes (<=16, <=128, <=256) and of
 # the lane-private histogram (<=32); L with power-of-two and other row widths
-@pytest.mark.parametrize("L,q", [(48, 16), (48, 17), (80, 32), (80, 33), (96, 128), (112, 129),
-                                 (208, 256), (1040, 9), (64, 2), (128, 3)])
-def test_strip_kernel_q_edges(potts, oracle_lib, L, q):
+@pytest.mark.parametrize("L,q", [(48, 16), (48, 17), (80, 32), (80, 33), (96, 64), (96, 65), (96, 128),
+                                 (112, 129), (208, 256), (1040, 9), (64, 2), (128, 3), (16, 7)])
+@pytest.mark.parametrize("kernel", [1, 3])
+def test_kernel_q_edges(potts, oracle_lib, L, q, kernel):
+    if kernel == 3 and L > 256:
+        pytest.skip("LDS-resident kernel holds L <= 256")
     seed, beta, n = 6, 0.9, 7
-    _say(f"q-edge L={L} q={q}")
+    _say(f"q-edge L={L} q={q} kernel={kernel}")
     want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
     with potts.Lattice(L, q, seed, 1) as lat:
-        lat.tune(kernel=1)
+        lat.tune(kernel=kernel)
         lat.sweep(beta, n)
         assert np.array_equal(lat.records(0, n), want_rec)
+        assert np.array_equal(lat.spins(), want_spins)
+
+
+def test_resident_long_run_plain_method(potts, oracle_lib):
+    """The plain-method workload (q=9, L=64, random start, seed 1,
+    beta = 1.02 ln 4, 1000 sweeps) in full, on the default (LDS-resident) path."""
+    L, q, seed, beta, n = 64, 9, 1, 1.02 * math.log(4.0), 1000
+    want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, n)
+        assert np.array_equal(lat.records(0, n), want_rec)
+        assert np.array_equal(lat.spins(), want_spins)
+
+
+def test_resident_chunked_launches(potts, oracle_lib):
+    """More sweeps than one resident launch holds (4096) and a ring smaller
+    than the run."""
+    L, q, seed, beta, n = 16, 3, 8, 1.0, 5000
+    want_spins, want_rec = oracle_lib.run(L, q, seed, 0, beta, n)
+    lat = potts.Lattice.from_torch(L, q, seed, 0, records_capacity=1000)
+    with lat:
+        lat.sweep(beta, n)
+        assert np.array_equal(lat.records(n - 999, 999), want_rec[n - 999:])
         assert np.array_equal(lat.spins(), want_spins)
 
 
@@ -219,9 +250,12 @@ def test_launch_shape_does_not_change_results(potts, oracle_lib, L):
     height and grid size must give the same bits."""
     q, seed, beta, n = 9, 11, 1.4, 6
     want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
-    shapes = [(2, 0, 0), (1, 0, 0), (1, 2, 1), (1, 2, 7), (1, 4, 0), (1, 8, 3), (1, 16, 64), (1, 32, 0)]
+    shapes = [(2, 0, 0), (1, 0, 0), (1, 2, 1), (1, 2, 7), (1, 4, 0), (1, 8, 3), (1, 16, 64), (1, 32, 0),
+              (3, 0, 0)]
     for kernel, rows, groups in shapes:
         if rows and L % rows:
+            continue
+        if kernel == 3 and L > 256:
             continue
         _say(f"shape L={L} kernel={kernel} rows={rows} groups={groups}")
         with potts.Lattice(L, q, seed, 1) as lat:
@@ -236,6 +270,49 @@ def test_tune_rejects_bad_shapes(potts):
         with pytest.raises(potts.PottsError):
             lat.tune(kernel=1)  # 20 % 16 != 0
         with pytest.raises(potts.PottsError):
-            lat.tune(kernel=3)
+            lat.tune(kernel=3)  # 20 % 16 != 0
+        with pytest.raises(potts.PottsError):
+            lat.tune(kernel=4)
         with pytest.raises(potts.PottsError):
             lat.tune(kernel=0, strip_rows=3)
+
+
+@pytest.mark.parametrize("L,start", [(64, 0), (64, 1), (512, 1), (100, 0)])
+def test_ramp_matches_oracle(potts, oracle_lib, L, start):
+    """Temperature ramp (protocol of Sec. 3): heating from the ordered state with
+    beta descending, cooling from the random state with beta ascending; state
+    carried over; derived statistics of each point's measurement window."""
+    from oracle.stats import derived
+
+    q, seed, t_equil, t_meas = 9, 1, 10, 25
+    k = np.arange(6)
+    betas = beta_c(q) * (0.98 + 0.04 * k / 5)
+    if start == 0:
+        betas = betas[::-1]
+    _say(f"ramp L={L} start={start}")
+    s = oracle_lib.init(L, q, seed, start)
+    t, want = 0, []
+    for b in betas:
+        rec = oracle_lib.sweeps(s, q, seed, t, t_equil + t_meas, oracle_lib.threshold_table(b))
+        t += t_equil + t_meas
+        w = rec[t_equil:]
+        want.append(derived(w[:, 0].tolist(), w[:, 1:].max(axis=1).tolist(), L * L, q, float(b)))
+    lat = potts.Lattice.from_torch(L, q, seed, start, records_capacity=4)
+    with lat:
+        got = lat.ramp(betas, t_equil, t_meas)
+        assert np.array_equal(lat.spins(), s)
+        assert lat.t == t
+    for g, w in zip(got, want):
+        assert g["n"] == t_meas
+        for key in ("e", "C", "V_L", "m", "chi"):
+            assert g[key] == pytest.approx(w[key], rel=1e-12, abs=1e-300), key
+
+
+def test_ramp_rejects_bad_arguments(potts):
+    with potts.Lattice(16, 3, 1, 1) as lat:
+        with pytest.raises(potts.PottsError):
+            lat.ramp([1.0], 5, 0)
+        with pytest.raises(potts.PottsError):
+            lat.ramp([1.0, -1.0], 5, 5)
+        with pytest.raises(potts.PottsError):
+            lat.ramp([], 5, 5)
