@@ -176,6 +176,68 @@ int64_t potts_time(const potts_state *s);
 int potts_save(potts_state *s, const char *path);
 int potts_load(const char *path, potts_state **out);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent lattices (replicas, temperatures, sizes) swept
+ * together.  Each job gives exactly the spins and records it gives alone
+ * (same seed, start, beta, sweeps): the random numbers depend on the site
+ * and sweep only.  Jobs with L <= 256 run in the LDS-resident kernel (one
+ * workgroup each, all sweeps in one launch); larger jobs share one strip
+ * launch per colour and sweep through a workgroup tile table.  The remaining
+ * launches of a run are captured in one hipGraph (resident and strip work as
+ * two overlapping branches) and replayed.
+ */
+typedef struct {
+    int32_t L, q;        /* L % 16 == 0, 16 <= L <= 65536; 2 <= q <= 256       */
+    uint64_t seed;
+    int32_t start;       /* potts_start                                        */
+    int32_t _pad;
+    double beta;         /* one inverse temperature per job                    */
+    int64_t nsweeps;     /* sweeps per run, 0 .. 2^31                          */
+} potts_job;
+
+typedef struct {
+    int64_t t;           /* sweeps done                                        */
+    int64_t e_sat;       /* after the last sweep                               */
+    int64_t nmax;
+    potts_summary stats; /* over the last `window` sweeps (all when window 0)  */
+} potts_job_result;
+
+typedef struct {
+    int32_t graph;       /* 1: capture the run in a hipGraph and launch it      */
+    int32_t tune;        /* 1: time strip heights on the first sweeps, keep the best */
+    int32_t window;      /* summary window in sweeps, 0 = every sweep of the job */
+    int32_t strip_rows;  /* fixed strip height (even divisor of L), 0 = automatic */
+    void *hip_stream;    /* hipStream_t, NULL = the batch's own stream          */
+} potts_batch_opts;
+
+typedef struct potts_batch potts_batch;
+
+/* Allocates one arena for all lattices and record rings (every sweep of a run
+ * is kept), writes the initial conditions and synchronizes.  opts may be NULL
+ * (no graph, no tuning, window 0).  Errors: EINVAL (bad job fields; the message
+ * names the job), ENOMEM, EDEVICE. */
+int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts *opts, potts_batch **out);
+
+/* Runs every job for its nsweeps sweeps and waits for the end.  Calling it
+ * again continues every job for nsweeps more. Errors: EINVAL, EDEVICE. */
+int potts_batch_run(potts_batch *b);
+
+/* Per-job results (caller-owned array of n).  Synchronizes. */
+int potts_batch_results(potts_batch *b, potts_job_result *out);
+
+/* Records of sweeps t0 .. t0+n-1 of one job ({e_sat, hist[q]} each) and its
+ * lattice (L*L bytes).  Synchronize.  Errors: EINVAL, ERANGE. */
+int potts_batch_records(potts_batch *b, int32_t job, int64_t t0, int64_t n, int64_t *out);
+int potts_batch_spins(potts_batch *b, int32_t job, uint8_t *host_out);
+
+/* Device time of the last run in ms (HIP events on the batch's stream), and
+ * the strip heights the tuner chose ("L=<L>:rows=<r> ..."). */
+double potts_batch_elapsed_ms(const potts_batch *b);
+const char *potts_batch_tuning(const potts_batch *b);
+
+/* Releases the batch (synchronizes first).  NULL is a no-op. */
+void potts_batch_free(potts_batch *b);
+
 /* Releases the state (synchronizes its stream first).  NULL is a no-op. */
 void potts_free(potts_state *s);
 

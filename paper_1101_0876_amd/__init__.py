@@ -13,12 +13,13 @@ from typing import Optional
 
 import numpy as np
 
-from ._native import PottsError, PottsObs, PottsSummary, check, load
+from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, PottsObs, PottsSummary,
+                      check, load)
 
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
+__all__ = ["Lattice", "Batch", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
 
 
 def threshold_table(beta: float) -> np.ndarray:
@@ -143,6 +144,69 @@ class Lattice:
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
             self._lib.potts_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many independent lattices swept together (potts_batch_*).  jobs: dicts
+    with L, q, seed, start, beta, nsweeps.  Each job gives exactly the bits it
+    gives alone."""
+
+    def __init__(self, jobs, graph: bool = True, tune: bool = True, window: int = 0, strip_rows: int = 0,
+                 stream=None):
+        self._lib = load()
+        arr = (PottsJob * len(jobs))()
+        for a, j in zip(arr, jobs):
+            a.L, a.q, a.seed, a.start = int(j["L"]), int(j["q"]), int(j["seed"]), int(j["start"])
+            a.beta, a.nsweeps = float(j["beta"]), int(j["nsweeps"])
+        self.jobs = [dict(j) for j in jobs]
+        opts = PottsBatchOpts(int(graph), int(tune), int(window), int(strip_rows),
+                              ctypes.c_void_p(stream.cuda_stream) if stream is not None else None)
+        self._h = ctypes.c_void_p()
+        check(self._lib.potts_batch_create(arr, len(jobs), ctypes.byref(opts), ctypes.byref(self._h)))
+
+    def run(self) -> float:
+        """Runs every job for its nsweeps (more) sweeps; returns the device time in ms."""
+        check(self._lib.potts_batch_run(self._h))
+        return float(self._lib.potts_batch_elapsed_ms(self._h))
+
+    def results(self) -> list:
+        out = (PottsJobResult * len(self.jobs))()
+        check(self._lib.potts_batch_results(self._h, out))
+        return [{"t": r.t, "e_sat": r.e_sat, "nmax": r.nmax, "e": r.stats.e, "C": r.stats.C,
+                 "V_L": r.stats.V_L, "m": r.stats.m, "chi": r.stats.chi, "n": r.stats.n} for r in out]
+
+    def records(self, job: int, t0: int, n: int) -> np.ndarray:
+        q = int(self.jobs[job]["q"])
+        out = np.zeros((n, 1 + q), dtype=np.int64)
+        check(self._lib.potts_batch_records(self._h, int(job), int(t0), int(n),
+                                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return out
+
+    def spins(self, job: int) -> np.ndarray:
+        L = int(self.jobs[job]["L"])
+        out = np.zeros(L * L, dtype=np.uint8)
+        check(self._lib.potts_batch_spins(self._h, int(job), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.reshape(L, L)
+
+    def tuning(self) -> str:
+        return (self._lib.potts_batch_tuning(self._h) or b"").decode()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.potts_batch_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -39,6 +39,37 @@ class PottsSummary(ctypes.Structure):
     ]
 
 
+class PottsJob(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("start", ctypes.c_int32),
+        ("_pad", ctypes.c_int32),
+        ("beta", ctypes.c_double),
+        ("nsweeps", ctypes.c_int64),
+    ]
+
+
+class PottsJobResult(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int64),
+        ("e_sat", ctypes.c_int64),
+        ("nmax", ctypes.c_int64),
+        ("stats", PottsSummary),
+    ]
+
+
+class PottsBatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("graph", ctypes.c_int32),
+        ("tune", ctypes.c_int32),
+        ("window", ctypes.c_int32),
+        ("strip_rows", ctypes.c_int32),
+        ("hip_stream", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 # (name, restype, argtypes) for every exported symbol declared in include/potts.h
@@ -68,6 +99,15 @@ SIGNATURES = [
     ("potts_time", ctypes.c_int64, [_VP]),
     ("potts_save", ctypes.c_int, [_VP, ctypes.c_char_p]),
     ("potts_load", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
+    ("potts_batch_create", ctypes.c_int, [ctypes.POINTER(PottsJob), ctypes.c_int32,
+                                          ctypes.POINTER(PottsBatchOpts), ctypes.POINTER(_VP)]),
+    ("potts_batch_run", ctypes.c_int, [_VP]),
+    ("potts_batch_results", ctypes.c_int, [_VP, ctypes.POINTER(PottsJobResult)]),
+    ("potts_batch_records", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    ("potts_batch_spins", ctypes.c_int, [_VP, ctypes.c_int32, _U8P]),
+    ("potts_batch_elapsed_ms", ctypes.c_double, [_VP]),
+    ("potts_batch_tuning", ctypes.c_char_p, [_VP]),
+    ("potts_batch_free", None, [_VP]),
     ("potts_free", None, [_VP]),
     ("potts_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("potts_last_error", ctypes.c_char_p, []),

@@ -44,6 +44,17 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
+}  // namespace
+
+namespace potts {
+int record_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+}  // namespace potts
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what) {
   return fail(POTTS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -151,6 +162,16 @@ int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spi
   *out = s;
   return POTTS_OK;
 }
+
+int build_table(double beta, uint32_t thr[4]);
+
+}  // namespace
+
+namespace potts {
+int build_threshold_table(double beta, uint32_t thr[4]) { return build_table(beta, thr); }
+}  // namespace potts
+
+namespace {
 
 int build_table(double beta, uint32_t thr[4]) {
   if (!(beta >= 0.0) || !isfinite(beta)) return fail(POTTS_EINVAL, "beta must be finite and >= 0");

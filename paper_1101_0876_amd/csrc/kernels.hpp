@@ -122,5 +122,7 @@ hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max
                            bool wide, hipStream_t stream);
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
+// one workgroup per window, params in device memory
+hipError_t launch_stats_many(const StatsParams *dev_params, unsigned n, hipStream_t stream);
 
 }  // namespace potts

@@ -57,7 +57,8 @@ __device__ double i128_to_double(__int128 v) {
 
 constexpr int kStatsBlock = 256;
 
-__global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams p) {
+__global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams single, const StatsParams *many) {
+  const StatsParams p = many ? many[blockIdx.x] : single;
   __shared__ Partial part[kStatsBlock];
   Partial acc = {};
   for (int64_t i = threadIdx.x; i < p.n; i += kStatsBlock) {
@@ -106,7 +107,13 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams p) {
 }  // namespace
 
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream) {
-  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kStatsBlock), 0, stream, p);
+  hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kStatsBlock), 0, stream, p, (const StatsParams *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_many(const StatsParams *dev_params, unsigned n, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(stats_kernel, dim3(n), dim3(kStatsBlock), 0, stream, StatsParams{}, dev_params);
   return hipGetLastError();
 }
 

@@ -72,42 +72,20 @@ __device__ __forceinline__ void do_row(const StripParams &p, uint32_t t_lo, uint
   cy.s_hi = perm(nxt.w, nxt.z, kSel<O ^ 1>);
 }
 
-// The job descriptor is the same for the whole workgroup; reading it back
-// through readfirstlane keeps it in scalar registers after the branch that
-// picks its source.
-__device__ __forceinline__ StripParams wave_uniform(const StripParams &in) {
-  static_assert(sizeof(StripParams) % 4 == 0, "descriptor is dword-sized");
-  uint32_t w[sizeof(StripParams) / 4];
-  __builtin_memcpy(w, &in, sizeof(StripParams));
-#pragma unroll
-  for (unsigned i = 0; i < sizeof(StripParams) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  StripParams out;
-  __builtin_memcpy(&out, w, sizeof(StripParams));
-  return out;
-}
-
-template <int COLOUR, int CMP, bool PRIV, bool WIDE>
+// TILED: workgroup -> (job, item range) from the tile table (batched
+// lattices); otherwise the single descriptor in the kernel arguments with a
+// grid-stride loop.  Two instantiations keep the descriptor in scalar
+// registers in both cases.
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
 __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   // acceptance table in static LDS, so its address folds into the ds_read offset
   __shared__ __align__(16) uint32_t table_words[512];
-  StripParams p;
-  uint32_t first, end, stride;
-  bool lead;
-  if (launch.tiles) {
-    const StripTile tile = launch.tiles[blockIdx.x];
-    p = launch.jobs[tile.job];
-    first = tile.first + threadIdx.x;
-    end = tile.first + tile.count;
-    stride = kBlock;
-    lead = tile.lead != 0;
-  } else {
-    p = launch.single;
-    first = blockIdx.x * kBlock + threadIdx.x;
-    end = p.nitems;
-    stride = gridDim.x * kBlock;
-    lead = blockIdx.x == 0;
-  }
-  p = wave_uniform(p);
+  const StripTile tile = TILED ? launch.tiles[blockIdx.x] : StripTile{0, 0, 0, 0};
+  const StripParams &p = TILED ? launch.jobs[tile.job] : launch.single;
+  const uint32_t first = TILED ? tile.first + threadIdx.x : blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t end = TILED ? tile.first + tile.count : p.nitems;
+  const uint32_t stride = TILED ? (uint32_t)kBlock : gridDim.x * kBlock;
+  const bool lead = TILED ? tile.lead != 0 : blockIdx.x == 0;
   if (launch.sweep >= p.nsweeps) return;  // the whole workgroup: this job is done
   const uint64_t t = p.t0 + launch.sweep;
   const uint32_t t_lo = (uint32_t)t, t_hi = (uint32_t)(t >> 32);
@@ -197,7 +175,10 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
 
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 hipError_t launch_t(const StripLaunch &l, unsigned grid, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE>), dim3(grid), dim3(kBlock), lds, stream, l);
+  if (l.tiles)
+    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, true>), dim3(grid), dim3(kBlock), lds, stream, l);
+  else
+    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, false>), dim3(grid), dim3(kBlock), lds, stream, l);
   return hipGetLastError();
 }
 
