@@ -195,12 +195,63 @@ def run_copy(args):
             "bytes_read_per_launch": n, "bytes_written_per_launch": n, "ms_per_launch": ms, "reps": reps}
 
 
+def run_batch(args):
+    """Batched replicas: 1024 lattices of mixed L (128..4096), q (3..12) and beta
+    near beta_c, 500 sweeps each, random starts; one batch (tile table, resident
+    launches, hipGraph, in-run tuning) against the plain loop of one lattice at a
+    time through the single-lattice path on the same GPU."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+    from paper_1101_0876_amd.workloads import batch_jobs
+
+    jobs = batch_jobs(n=args.batch_jobs, sweeps=args.steps)
+    torch.cuda.set_device(0)
+    site_updates = sum(j["L"] ** 2 * j["nsweeps"] for j in jobs)
+    # warm-up: a small batch touches every kernel variant used below
+    with potts.Batch(jobs[:16], graph=True, tune=False) as w:
+        w.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with potts.Batch(jobs, graph=True, tune=True) as b:
+        t_create = time.perf_counter()
+        dev_ms = b.run()
+        t_run = time.perf_counter()
+        tuning = b.tuning()
+        res = b.results()
+    wall = t_run - t_create
+    assert all(r["t"] == j["nsweeps"] for r, j in zip(res, jobs))
+    out = {
+        "metric": "jobs/s", "value": len(jobs) / wall, "unit": "jobs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 0, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "batched replicas", "jobs": len(jobs), "L": "2^U{7..12}", "q": "U{3..12}",
+                   "beta": "beta_c(q) U[0.98,1.02]", "sweeps": args.steps, "list_seed": 1101},
+        "ns_per_spin_flip": wall * 1e9 / site_updates,
+        "device_ms": dev_ms, "setup_s": t_create - t0, "tuning": tuning,
+    }
+    if not args.no_plain:
+        # the plain loop: one lattice at a time, single-lattice path, same stream order
+        tp = time.perf_counter()
+        for j in jobs:
+            with potts.Lattice(j["L"], j["q"], j["seed"], j["start"]) as lat:
+                lat.sweep(j["beta"], j["nsweeps"])
+                lat.observables()
+        plain = time.perf_counter() - tp
+        out["plain_loop"] = {"jobs_per_s": len(jobs) / plain, "wall_s": plain,
+                             "speedup_of_batch": plain / wall}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "copy"])
+    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch"])
+    ap.add_argument("--batch-jobs", type=int, default=1024)
+    ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-lattice-at-a-time loop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -210,6 +261,11 @@ def main():
         sys.exit(2)
     if args.workload == "copy":
         print(json.dumps(run_copy(args)), flush=True)
+        return
+    if args.workload == "batch":
+        if args.steps == 2000:  # the batch workload's own default
+            args.steps = 500
+        print(json.dumps(run_batch(args)), flush=True)
         return
     out = run_large(args)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
