@@ -238,6 +238,76 @@ const char *potts_batch_tuning(const potts_batch *b);
 /* Releases the batch (synchronizes first).  NULL is a no-op. */
 void potts_batch_free(potts_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Serving: a server thread admits simulation jobs as they arrive (in arrival
+ * order, while a slot is free and the job's lattice and record ring fit in the
+ * HBM budget), keeps every admitted lattice and its sweep counter resident on
+ * the device, and runs iterations that advance every active job by up to
+ * `quantum` sweeps of its current beta point in shared launches (continuous
+ * batching): jobs arriving while others run join the next iteration.  Each job
+ * gives exactly the bits it gives alone.
+ */
+typedef struct {
+    int64_t hbm_budget;  /* bytes of lattices + record rings held at once (<= 0: 200 GiB) */
+    int32_t max_slots;   /* jobs on the device at once (<= 0: 256)              */
+    int32_t quantum;     /* sweeps per job per iteration (<= 0: 32)             */
+    void *hip_stream;    /* hipStream_t, NULL = the server's own stream         */
+} potts_server_cfg;
+
+/* A job: a beta schedule (Sec. 3 protocol), point k run for sweeps[k] sweeps
+ * at betas[k] with the configuration carried over.  Point k's summary covers
+ * its last ceil(sweeps[k]/2) sweeps (the first half equilibrates). */
+typedef struct {
+    int32_t L, q;            /* L % 16 == 0, 16 <= L <= 65536; 2 <= q <= 256  */
+    uint64_t seed;
+    int32_t start;           /* potts_start                                   */
+    int32_t npoints;         /* 1 .. 4096                                     */
+    const double *betas;     /* npoints, copied at submit                     */
+    const int64_t *sweeps;   /* npoints, each 1 .. 2^30, copied at submit     */
+    int32_t keep_spins;      /* 1: keep the final lattice for collect         */
+    int32_t _pad;
+} potts_request;
+
+typedef struct {
+    int64_t ticket;
+    int32_t L, q, npoints;
+    int32_t status;          /* 0, or the negative code that ended the job    */
+    int64_t sweeps;          /* sweeps done                                   */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock      */
+    int64_t e_sat, nmax;     /* after the last sweep                          */
+} potts_served;
+
+typedef struct potts_server potts_server;
+
+int potts_server_start(const potts_server_cfg *cfg, potts_server **out);
+
+/* Queues a job (thread-safe); *ticket identifies it.  Errors: EINVAL (bad
+ * fields), ENOMEM (larger than the budget), or the code that stopped a failed
+ * server. */
+int potts_server_submit(potts_server *srv, const potts_request *req, int64_t *ticket);
+
+/* Up to max tickets of finished jobs not reported before; waits up to
+ * timeout_ms (< 0: until one finishes or every job submitted so far is done). */
+int potts_server_wait(potts_server *srv, int64_t *tickets, int32_t max, int32_t timeout_ms, int32_t *n);
+
+/* Takes a finished job's results: info, points (npoints summaries, may be
+ * NULL) and, when kept, the final lattice (L*L bytes, may be NULL).  Returns
+ * the job's status.  Errors: ERANGE (unknown or unfinished ticket). */
+int potts_server_collect(potts_server *srv, int64_t ticket, potts_served *info, potts_summary *points,
+                         uint8_t *spins);
+
+/* Waits until every submitted job has finished (timeout_ms < 0: no limit).
+ * Errors: ERANGE on time-out, or the code that stopped a failed server. */
+int potts_server_drain(potts_server *srv, int32_t timeout_ms);
+
+/* The server's clock (seconds since start) and the number of iterations run. */
+double potts_server_now(const potts_server *srv);
+int64_t potts_server_iterations(const potts_server *srv);
+
+/* Finishes every queued and running job, stops the thread and releases the
+ * server; returns 0 or the code that failed it.  NULL is a no-op. */
+int potts_server_stop(potts_server *srv);
+
 /* Releases the state (synchronizes its stream first).  NULL is a no-op. */
 void potts_free(potts_state *s);
 

@@ -13,13 +13,13 @@ from typing import Optional
 
 import numpy as np
 
-from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, PottsObs, PottsSummary,
-                      check, load)
+from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, PottsObs, PottsRequest,
+                      PottsServed, PottsServerCfg, PottsSummary, check, load)
 
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "Batch", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
+__all__ = ["Lattice", "Batch", "Server", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
 
 
 def threshold_table(beta: float) -> np.ndarray:
@@ -220,3 +220,80 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Server:
+    """Serving loop with continuous batching (potts_server_*): submit jobs (a
+    beta schedule each) while earlier ones run; results are bit-identical to
+    the same job run alone."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 0, quantum: int = 0, stream=None):
+        self._lib = load()
+        cfg = PottsServerCfg(int(hbm_budget), int(max_slots), int(quantum),
+                             ctypes.c_void_p(stream.cuda_stream) if stream is not None else None)
+        self._h = ctypes.c_void_p()
+        check(self._lib.potts_server_start(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._npoints = {}
+        self._L = {}
+
+    def submit(self, L: int, q: int, seed: int, start: int, betas, sweeps, keep_spins: bool = False) -> int:
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        n = np.ascontiguousarray(sweeps, dtype=np.int64)
+        if b.size != n.size:
+            raise ValueError("one sweep count per beta")
+        req = PottsRequest(int(L), int(q), int(seed), int(start), int(b.size),
+                           b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(keep_spins), 0)
+        t = ctypes.c_int64()
+        check(self._lib.potts_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._npoints[t.value] = int(b.size)
+        self._L[t.value] = int(L)
+        return int(t.value)
+
+    def wait(self, max_n: int = 256, timeout_ms: int = -1) -> list:
+        buf = (ctypes.c_int64 * max_n)()
+        n = ctypes.c_int32()
+        check(self._lib.potts_server_wait(self._h, buf, int(max_n), int(timeout_ms), ctypes.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
+    def collect(self, ticket: int, spins: bool = False) -> dict:
+        info = PottsServed()
+        npts = self._npoints.pop(ticket)
+        L = self._L.pop(ticket)
+        pts = (PottsSummary * npts)()
+        sp = np.zeros(L * L, dtype=np.uint8) if spins else None
+        rc = self._lib.potts_server_collect(self._h, int(ticket), ctypes.byref(info), pts,
+                                            sp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if spins else None)
+        check(rc)
+        return {"ticket": info.ticket, "L": info.L, "q": info.q, "status": info.status, "sweeps": info.sweeps,
+                "t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done,
+                "e_sat": info.e_sat, "nmax": info.nmax,
+                "points": [{"n": p.n, "e": p.e, "C": p.C, "V_L": p.V_L, "m": p.m, "chi": p.chi} for p in pts],
+                "spins": sp.reshape(L, L) if spins else None}
+
+    def drain(self, timeout_ms: int = -1) -> None:
+        check(self._lib.potts_server_drain(self._h, int(timeout_ms)))
+
+    def now(self) -> float:
+        return float(self._lib.potts_server_now(self._h))
+
+    def iterations(self) -> int:
+        return int(self._lib.potts_server_iterations(self._h))
+
+    def stop(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            rc = self._lib.potts_server_stop(self._h)
+            self._h = ctypes.c_void_p()
+            check(rc)
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

@@ -70,6 +70,45 @@ class PottsBatchOpts(ctypes.Structure):
     ]
 
 
+class PottsServerCfg(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("quantum", ctypes.c_int32),
+        ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+class PottsRequest(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("start", ctypes.c_int32),
+        ("npoints", ctypes.c_int32),
+        ("betas", ctypes.POINTER(ctypes.c_double)),
+        ("sweeps", ctypes.POINTER(ctypes.c_int64)),
+        ("keep_spins", ctypes.c_int32),
+        ("_pad", ctypes.c_int32),
+    ]
+
+
+class PottsServed(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_int64),
+        ("L", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("npoints", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("sweeps", ctypes.c_int64),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("e_sat", ctypes.c_int64),
+        ("nmax", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 # (name, restype, argtypes) for every exported symbol declared in include/potts.h
@@ -108,6 +147,15 @@ SIGNATURES = [
     ("potts_batch_elapsed_ms", ctypes.c_double, [_VP]),
     ("potts_batch_tuning", ctypes.c_char_p, [_VP]),
     ("potts_batch_free", None, [_VP]),
+    ("potts_server_start", ctypes.c_int, [ctypes.POINTER(PottsServerCfg), ctypes.POINTER(_VP)]),
+    ("potts_server_submit", ctypes.c_int, [_VP, ctypes.POINTER(PottsRequest), ctypes.POINTER(ctypes.c_int64)]),
+    ("potts_server_wait", ctypes.c_int, [_VP, _I64P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    ("potts_server_collect", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(PottsServed),
+                                            ctypes.POINTER(PottsSummary), _U8P]),
+    ("potts_server_drain", ctypes.c_int, [_VP, ctypes.c_int32]),
+    ("potts_server_now", ctypes.c_double, [_VP]),
+    ("potts_server_iterations", ctypes.c_int64, [_VP]),
+    ("potts_server_stop", ctypes.c_int, [_VP]),
     ("potts_free", None, [_VP]),
     ("potts_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("potts_last_error", ctypes.c_char_p, []),
