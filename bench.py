@@ -244,14 +244,69 @@ def run_batch(args):
     return out
 
 
+def run_serve(args):
+    """Serving: a burst of Poisson arrivals (200 jobs/s) of ramp jobs (L up to
+    8192, q 3..15, 8..32 beta points), submitted at their arrival times while
+    the server runs; reports completed jobs/s and p50/p99 latency (completion
+    minus submission).  Sweep counts are scaled by --serve-scale (the full
+    10^3..10^5 sweeps per job offer ~100x one GPU's throughput)."""
+    import numpy as np
+    import torch
+
+    import paper_1101_0876_amd as potts
+    from paper_1101_0876_amd.workloads import serve_jobs
+
+    torch.cuda.set_device(0)
+    jobs = serve_jobs(n=args.serve_jobs, rate=args.serve_rate, sweep_scale=args.serve_scale)
+    site_updates = sum(j["L"] ** 2 * sum(j["sweeps"]) for j in jobs)
+    with potts.Server(quantum=args.serve_quantum) as warm:  # loads every kernel variant once
+        t = warm.submit(512, 6, 1, 1, [1.0, 1.2], [4, 4])
+        t2 = warm.submit(256, 15, 1, 0, [1.0], [4])
+        warm.drain()
+        warm.collect(t)
+        warm.collect(t2)
+    with potts.Server(quantum=args.serve_quantum, max_slots=args.serve_slots) as srv:
+        start = time.perf_counter()
+        tickets = []
+        for j in jobs:
+            delay = j["arrival"] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"]))
+        srv.drain()
+        got = [srv.collect(t) for t in tickets]
+        iterations = srv.iterations()
+    lat = np.array([g["t_done"] - g["t_submit"] for g in got])
+    span = max(g["t_done"] for g in got) - min(g["t_submit"] for g in got)
+    assert all(g["status"] == 0 for g in got)
+    return {
+        "metric": "served jobs/s", "value": len(got) / span, "unit": "jobs/s", "n_gpus": 1,
+        "steps": iterations, "warmup": 0, "ms_per_step": span * 1e3 / max(iterations, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "serving loop", "jobs": len(got), "arrival_rate_per_s": args.serve_rate,
+                   "L": "2^U{8..13}", "q": "U{3..15}", "points": "U{8..32}",
+                   "sweeps": f"round(10^U[3,5] x {args.serve_scale})", "quantum": args.serve_quantum,
+                   "slots": args.serve_slots, "hbm_budget_GiB": 200, "list_seed": 1101},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "ns_per_spin_flip": span * 1e9 / site_updates,
+        "span_s": span,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch"])
+    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve"])
     ap.add_argument("--batch-jobs", type=int, default=1024)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-lattice-at-a-time loop")
+    ap.add_argument("--serve-jobs", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-scale", type=float, default=0.01)
+    ap.add_argument("--serve-quantum", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -261,6 +316,9 @@ def main():
         sys.exit(2)
     if args.workload == "copy":
         print(json.dumps(run_copy(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
         return
     if args.workload == "batch":
         if args.steps == 2000:  # the batch workload's own default
