@@ -31,10 +31,10 @@
  *     a move with dE <= 0 is always accepted;
  *   - random numbers come from Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
  *     SC'11, "Parallel random numbers: as easy as 1, 2, 3"), one block per
- *     (4-byte row chunk, sweep, colour): counter = (y*(L/4) + x/4, t_lo, t_hi,
+ *     (4-byte row chunk, sweep, colour): counter = (t_lo, y*(L/4) + x/4, t_hi,
  *     colour), key = (seed_lo, seed_hi); a site at column x takes the word pair
  *     (w[2b], w[2b+1]) with b = (x/2) & 1 as (proposal, acceptance).  The random
- *     start uses counter (y*(L/4) + x/4, 0, 0, 2) and value floor(w[x&3]*q/2^32).
+ *     start uses counter (0, y*(L/4) + x/4, 0, 2) and value floor(w[x&3]*q/2^32).
  */
 #include <math.h>
 #include <stdint.h>
@@ -104,12 +104,13 @@ static uint32_t word_to_value(uint32_t w, int q)
     return (uint32_t)(((uint64_t)w * (uint64_t)(uint32_t)q) >> 32);
 }
 
-/* Philox words for the chunk holding column x of row y. */
-static void chunk_words(int L, int x, int y, uint64_t seed, uint32_t c1, uint32_t c2,
+/* Philox words for the chunk holding column x of row y: counter
+ * (c0, chunk index, c2, c3). */
+static void chunk_words(int L, int x, int y, uint64_t seed, uint32_t c0, uint32_t c2,
                         uint32_t c3, uint32_t w[4])
 {
-    const uint32_t ctr[4] = {(uint32_t)((uint64_t)y * (uint64_t)(L / 4) + (uint64_t)(x / 4)),
-                             c1, c2, c3};
+    const uint32_t ctr[4] = {c0, (uint32_t)((uint64_t)y * (uint64_t)(L / 4) + (uint64_t)(x / 4)),
+                             c2, c3};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     oracle_philox4x32_10(ctr, key, w);
 }

@@ -27,11 +27,30 @@ struct Words {
   uint32_t w0, w1, w2, w3;
 };
 
-// Ten rounds; round r uses key (k0 + r*W0, k1 + r*W1).
-__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+// Ten rounds; round r uses key (k0 + r*W0, k1 + r*W1).  The first round is
+// split off: PhiloxHead holds its outputs for counter words 0, 2, 3 and key
+// (k0, k1), with output word 0 still missing the XOR of counter word 1.  The
+// sweep kernels put the per-lane chunk index in word 1 and the sweep and
+// colour in words 0, 2, 3, so the head is wave-uniform (scalar unit) and each
+// block costs one XOR plus nine rounds of vector work.
+struct PhiloxHead {
+  uint32_t a0, x1, x2, x3;  // round-1 outputs (a0 before ^ counter word 1)
+  uint32_t k0, k1;          // key of round 2
+};
+
+__device__ __forceinline__ PhiloxHead philox_head(uint32_t c0, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+  return PhiloxHead{(uint32_t)(p1 >> 32) ^ k0, (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c3, k1),
+                    (uint32_t)p0, k0 + kWeyl0, k1 + kWeyl1};
+}
+
+// Rounds 2..10 from the head and x0 = h.a0 ^ counter word 1.
+__device__ __forceinline__ Words philox_tail(uint32_t x0, const PhiloxHead &h) {
+  uint32_t c0 = x0, c1 = h.x1, c2 = h.x2, c3 = h.x3, k0 = h.k0, k1 = h.k1;
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
+  for (int r = 1; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
     const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
@@ -44,6 +63,12 @@ __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     k1 += kWeyl1;
   }
   return Words{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+  const PhiloxHead h = philox_head(c0, c2, c3, k0, k1);
+  return philox_tail(h.a0 ^ c1, h);
 }
 
 // floor(w * q / 2^32): a 32-bit word onto 0..q-1.

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void sweep4_kernel(SweepParams p) {
     const uint32_t left = (cur << 8) | (lf >> 24);   // byte i: spin at x-1
     const uint32_t right = (cur >> 8) | (rt << 24);  // byte i: spin at x+1
 
-    const Words w = philox4x32_10((uint32_t)g, p.t_lo, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
+    const Words w = philox4x32_10(p.t_lo, (uint32_t)g, p.t_hi, (uint32_t)COLOUR, p.k0, p.k1);
     const uint32_t o = (COLOUR + y) & 1u;  // byte offset of the first active site
     const uint32_t ka = scale_to_q(w.w0, p.q);
     const uint32_t kb = scale_to_q(w.w2, p.q);
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitParams p) {
   if (g >= p.nchunks) return;
   uint32_t out = 0;
   if (p.random) {
-    const Words w = philox4x32_10((uint32_t)g, 0u, 0u, 2u, p.k0, p.k1);
+    const Words w = philox4x32_10(0u, (uint32_t)g, 0u, 2u, p.k0, p.k1);
     out = scale_to_q(w.w0, p.q) | (scale_to_q(w.w1, p.q) << 8) | (scale_to_q(w.w2, p.q) << 16) |
           (scale_to_q(w.w3, p.q) << 24);
   }

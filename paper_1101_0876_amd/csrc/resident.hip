@@ -37,7 +37,7 @@ __device__ __forceinline__ uint32_t lds4(const uint8_t *lat, uint32_t off) {
 // One 16-byte row item of the LDS lattice (row y, byte column col).
 template <int COLOUR, int O, int CMP, bool PRIV, bool WIDE>
 __device__ __forceinline__ uint32_t item_update(uint8_t *lat, const ResidentJob &j, uint32_t y,
-                                                uint32_t col, uint32_t t_lo, uint32_t t_hi,
+                                                uint32_t col, const PhiloxHead &h,
                                                 const uint8_t *table, uint8_t *hist,
                                                 uint32_t lane_off) {
   const uint32_t L = j.L;
@@ -54,7 +54,7 @@ __device__ __forceinline__ uint32_t item_update(uint8_t *lat, const ResidentJob 
       perm(cur.y, cur.x, kSel<O ^ 1>), perm(cur.w, cur.z, kSel<O ^ 1>),
       perm(up.y, up.x, kSel<O>), perm(up.w, up.z, kSel<O>),
       perm(dn.y, dn.x, kSel<O>), perm(dn.w, dn.z, kSel<O>), side,
-      y * (L >> 2) + (col >> 2), t_lo, t_hi, j.k0, j.k1, j.q, table);
+      y * (L >> 2) + (col >> 2), h, j.q, table);
   *reinterpret_cast<u32x4 *>(lat + ro + col) = r.out;
   if (COLOUR == 1) {
     if (PRIV)
@@ -67,9 +67,9 @@ __device__ __forceinline__ uint32_t item_update(uint8_t *lat, const ResidentJob 
 }
 
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
-__device__ __forceinline__ uint32_t half_sweep(uint8_t *lat, const ResidentJob &j, uint32_t t_lo,
-                                               uint32_t t_hi, const uint8_t *table, uint8_t *hist,
-                                               uint32_t lane_off) {
+__device__ __forceinline__ uint32_t half_sweep(uint8_t *lat, const ResidentJob &j, uint64_t t,
+                                               const uint8_t *table, uint8_t *hist, uint32_t lane_off) {
+  const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, j.k0, j.k1);
   const uint32_t L = j.L;
   const uint32_t cpr = L >> 4;                  // 16-byte items per row
   const uint32_t per_parity = (L >> 1) * cpr;   // items in the rows of one parity
@@ -81,9 +81,9 @@ __device__ __forceinline__ uint32_t half_sweep(uint8_t *lat, const ResidentJob &
     const uint32_t y = 2 * rr + par;
     const uint32_t col = (k - rr * cpr) * 16u;
     if (((COLOUR + y) & 1u) == 0)
-      nz += item_update<COLOUR, 0, CMP, PRIV, WIDE>(lat, j, y, col, t_lo, t_hi, table, hist, lane_off);
+      nz += item_update<COLOUR, 0, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
     else
-      nz += item_update<COLOUR, 1, CMP, PRIV, WIDE>(lat, j, y, col, t_lo, t_hi, table, hist, lane_off);
+      nz += item_update<COLOUR, 1, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
   }
   return nz;
 }
@@ -109,11 +109,10 @@ __global__ __launch_bounds__(kBlock) void resident_kernel(ResidentLaunch p) {
   const uint32_t nh = PRIV ? 64 * q : q;
   for (uint32_t s = 0; s < j.nsweeps; ++s) {
     const uint64_t t = j.t0 + s;
-    const uint32_t t_lo = (uint32_t)t, t_hi = (uint32_t)(t >> 32);
     for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-    half_sweep<0, CMP, PRIV, WIDE>(lat, j, t_lo, t_hi, table, reinterpret_cast<uint8_t *>(hist), lane_off);
+    half_sweep<0, CMP, PRIV, WIDE>(lat, j, t, table, reinterpret_cast<uint8_t *>(hist), lane_off);
     __syncthreads();
-    const uint32_t nz = half_sweep<1, CMP, PRIV, WIDE>(lat, j, t_lo, t_hi, table,
+    const uint32_t nz = half_sweep<1, CMP, PRIV, WIDE>(lat, j, t, table,
                                                       reinterpret_cast<uint8_t *>(hist), lane_off);
     const uint32_t nz_w = wave_sum(nz);
     __syncthreads();

@@ -167,22 +167,26 @@ struct Row8 {
 // Update of the 8 active sites of one 16-byte row.  s/p: active/passive bytes
 // of the row, u/d: bytes of the rows above/below at the active offset (all
 // packed, lo = first 8 bytes); side: the dword left of the row when O == 0,
-// right of it when O == 1.  ctr: Philox counter of the row's first 4-byte chunk.
+// right of it when O == 1.  ctr: chunk index (Philox counter word 1) of the
+// row's first 4-byte chunk, a multiple of 4 since L % 16 == 0; h: the head of
+// this half sweep's Philox blocks.
 template <int COLOUR, int O, int CMP, bool WIDE>
 __device__ __forceinline__ Row8 update8(uint32_t s_lo, uint32_t s_hi, uint32_t p_lo, uint32_t p_hi,
                                         uint32_t u_lo, uint32_t u_hi, uint32_t d_lo, uint32_t d_hi,
-                                        uint32_t side, uint32_t ctr, uint32_t t_lo, uint32_t t_hi,
-                                        uint32_t k0, uint32_t k1, uint32_t q, const uint8_t *table) {
+                                        uint32_t side, uint32_t ctr, const PhiloxHead &h, uint32_t q,
+                                        const uint8_t *table) {
   // horizontal neighbours: one is the passive byte at the same packed index,
   // the other the passive byte one site over (left when O == 0, right when O == 1)
   const uint32_t x_lo = O == 0 ? alignbyte(p_lo, side, 3) : alignbyte(p_hi, p_lo, 1);
   const uint32_t x_hi = O == 0 ? alignbyte(p_hi, p_lo, 3) : alignbyte(side, p_hi, 1);
 
   // block m serves dword m: (w0, w1) for its site at byte O, (w2, w3) at byte O+2
-  const Words b0 = philox4x32_10(ctr + 0, t_lo, t_hi, (uint32_t)COLOUR, k0, k1);
-  const Words b1 = philox4x32_10(ctr + 1, t_lo, t_hi, (uint32_t)COLOUR, k0, k1);
-  const Words b2 = philox4x32_10(ctr + 2, t_lo, t_hi, (uint32_t)COLOUR, k0, k1);
-  const Words b3 = philox4x32_10(ctr + 3, t_lo, t_hi, (uint32_t)COLOUR, k0, k1);
+  // ctr + m == ctr ^ m for m < 4
+  const uint32_t x0 = h.a0 ^ ctr;
+  const Words b0 = philox_tail(x0, h);
+  const Words b1 = philox_tail(x0 ^ 1u, h);
+  const Words b2 = philox_tail(x0 ^ 2u, h);
+  const Words b3 = philox_tail(x0 ^ 3u, h);
   const uint32_t k_lo = pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
   const uint32_t k_hi = pack4(scale_to_q(b2.w0, q), scale_to_q(b2.w2, q), scale_to_q(b3.w0, q), scale_to_q(b3.w2, q));
 

@@ -56,7 +56,7 @@ def test_random_start_layout_and_uniformity(oracle_lib, q):
     key = [seed & 0xFFFFFFFF, seed >> 32]
     for y in (0, 1, 31, 63):
         for x in (0, 1, 2, 3, 4, 61, 63):
-            w = oracle_lib.philox4x32_10([y * (L // 4) + x // 4, 0, 0, 2], key)
+            w = oracle_lib.philox4x32_10([0, y * (L // 4) + x // 4, 0, 2], key)
             assert s[y, x] == (int(w[x & 3]) * q) >> 32
     counts = np.bincount(s.ravel(), minlength=q)
     assert counts.size == q
@@ -79,7 +79,7 @@ def test_beta_zero_writes_proposals(oracle_lib, colour, t):
             if (x + y) & 1 != colour:
                 assert s[y, x] == base[y, x]
                 continue
-            w = oracle_lib.philox4x32_10([y * (L // 4) + x // 4, t & 0xFFFFFFFF, t >> 32, colour], key)
+            w = oracle_lib.philox4x32_10([t & 0xFFFFFFFF, y * (L // 4) + x // 4, t >> 32, colour], key)
             b = (x >> 1) & 1
             if int(w[2 * b + 1]) == 2**32 - 1:  # the one rejecting word
                 continue
