@@ -14,11 +14,11 @@
  *  - One sweep (one MCS, N = L*L trials, Sec. 2.2) updates every site with
  *    (x+y) even, then every site with (x+y) odd (checkerboard, Sec. 3).
  *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed, one
- *    block per (4-byte row chunk, sweep, colour): counter = (y*(L/4) + x/4,
- *    t_lo, t_hi, colour).  Site x uses words (w[2b], w[2b+1]), b = (x/2) & 1,
+ *    block per (4-byte row chunk, sweep, colour): counter = (t_lo,
+ *    y*(L/4) + x/4, t_hi, colour).  Site x uses words (w[2b], w[2b+1]), b = (x/2) & 1,
  *    as (proposal, acceptance).  The proposal is k = floor(w*q / 2^32), uniform
  *    over all q values (Sec. 3.2: one integer in 0..q-1 and one acceptance
- *    number).  Random start: counter (y*(L/4) + x/4, 0, 0, 2), spin =
+ *    number).  Random start: counter (0, y*(L/4) + x/4, 0, 2), spin =
  *    floor(w[x&3]*q / 2^32).  t counts the sweeps this state has done.
  *    Results are therefore a pure function of (L, q, seed, start, beta
  *    schedule) and do not depend on how kernels are launched.
@@ -126,6 +126,31 @@ int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_g
 /* The table potts_sweep uses for beta: thr[d-1] = min(floor(exp(-beta d)
  * 2^32), 2^32-1), computed on the host in FP64.  Errors: EINVAL. */
 int potts_threshold_table(double beta, uint32_t thr[4]);
+
+/* One colour half of sweep t (Sec. 3: checkerboard update, Sec. 3.2: one
+ * proposal and one acceptance number per site) over a row slab of an L x L
+ * lattice: the share of one device when the lattice is split into horizontal
+ * slabs.  Because the random words are keyed by global (x, y, t), a lattice
+ * swept slab by slab gives the bits of potts_sweep for any slab count.
+ *   dev_slab: device, (h+2) x L bytes, row-major.  Row 0 holds global row
+ *     (y0-1) mod L, rows 1..h global rows y0 .. y0+h-1, row h+1 global row
+ *     (y0+h) mod L.  Rows 1..h are updated in place (sites with (x+y) & 1 ==
+ *     colour); rows 0 and h+1 (halos) are only read, and the caller refreshes
+ *     them from the neighbouring slabs before every half sweep.
+ *   thr: the threshold table of the sweep's beta (potts_threshold_table).
+ *   dev_ring (colour 1 only; may be NULL for colour 0): device, ring_slots
+ *     (a power of two >= 2) slots of 1+q int64.  Colour 1 adds this slab's
+ *     share of the record of sweep t into slot t mod ring_slots -- [0] the
+ *     satisfied bonds with their colour-1 end in the slab, [1+v] the slab's
+ *     sites in state v; summed over the slabs, the sweep's {e_sat, hist} --
+ *     and zeroes slot (t+1) mod ring_slots for the next sweep.  Slot t must be
+ *     zero before the first colour-1 call of sweep t.
+ *   hip_stream: hipStream_t (NULL = default stream); asynchronous.
+ * Needs L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256, h and y0 even,
+ * h >= 2, y0 + h <= L.  Errors: EINVAL, EDEVICE. */
+int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, int32_t q, uint64_t seed,
+                          int64_t t, int32_t colour, const uint32_t thr[4], int64_t *dev_ring,
+                          int64_t ring_slots, void *hip_stream);
 
 /* Observables of the current configuration (synchronizes the stream).  Uses
  * the last sweep's record, or measures the lattice if no sweep has run. */

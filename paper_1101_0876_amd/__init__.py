@@ -19,7 +19,8 @@ from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, Pott
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "Batch", "Server", "PottsError", "threshold_table", "ORDERED", "RANDOM", "load"]
+__all__ = ["Lattice", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
+           "ORDERED", "RANDOM", "load"]
 
 
 def threshold_table(beta: float) -> np.ndarray:
@@ -297,3 +298,6 @@ class Server:
 
     def __exit__(self, *exc):
         self.stop()
+
+
+from .slabs import Slabs, slab_half_sweep  # noqa: E402

@@ -435,7 +435,7 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
       b->strip_groups[sg[key]].jobs.push_back(i);
       b->rows[i] = b->opts.strip_rows && j.L % b->opts.strip_rows == 0 && b->opts.strip_rows % 2 == 0
                        ? (uint32_t)b->opts.strip_rows
-                       : potts::auto_strip_rows((uint32_t)j.L, 64 * 256);
+                       : potts::auto_strip_rows((uint32_t)j.L, (uint32_t)j.L, 64 * 256);
       ++nstrip_desc;
       ntiles_max += ((size_t)j.L / 2) * ((size_t)j.L / 16) / 256 + 1;  // rows = 2 is the most tiles
     }

@@ -207,6 +207,11 @@ void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, u
   p.ipr = L / 16;
   p.rows = rows;
   p.nitems = (L / rows) * p.ipr;
+  p.nrows = L;
+  p.first_row = 0;
+  p.up_row = L - 1;
+  p.down_row = 0;
+  p.ctr0 = 0;
   p.item_shift = -1;
   p.item_magic = 0;
   if ((p.ipr & (p.ipr - 1)) == 0) {
@@ -222,12 +227,21 @@ void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, u
   for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
 }
 
-// Rows per strip item: the largest even divisor of L up to 32 that still
-// gives at least `want` items.
-uint32_t auto_strip_rows(uint32_t L, uint64_t want) {
+void fill_slab_params(StripParams &p, uint8_t *slab, uint32_t L, uint32_t h, uint32_t y0, uint32_t q,
+                      uint64_t seed, const uint32_t thr[4], uint32_t rows) {
+  fill_strip_params(p, slab, L, q, seed, thr, rows);
+  p.nitems = (h / rows) * p.ipr;
+  p.nrows = h;
+  p.first_row = 1;
+  p.up_row = 0;
+  p.down_row = h + 1;
+  p.ctr0 = y0 * (L / 4);
+}
+
+uint32_t auto_strip_rows(uint32_t L, uint32_t nrows, uint64_t want) {
   const uint32_t ipr = L / 16;
   for (uint32_t r = 32; r > 2; r /= 2)
-    if (L % r == 0 && (uint64_t)(L / r) * ipr >= want) return r;
+    if (nrows % r == 0 && (uint64_t)(nrows / r) * ipr >= want) return r;
   return 2;
 }
 
@@ -263,7 +277,7 @@ int run_resident(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
 // rows per strip item: at least 2048 x 256 items (eight workgroups of 256
 // lanes per CU) when the lattice allows it
 uint32_t strip_rows(const potts_state *s) {
-  return s->rows ? s->rows : potts::auto_strip_rows((uint32_t)s->L, 2048ull * 256ull);
+  return s->rows ? s->rows : potts::auto_strip_rows((uint32_t)s->L, (uint32_t)s->L, 2048ull * 256ull);
 }
 
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
@@ -395,6 +409,33 @@ int potts_sweep(potts_state *s, double beta, int64_t nsweeps) {
 int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
   return run_sweeps(s, thr, nsweeps);
+}
+
+int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, int32_t q, uint64_t seed,
+                          int64_t t, int32_t colour, const uint32_t thr[4], int64_t *dev_ring,
+                          int64_t ring_slots, void *hip_stream) {
+  if (!dev_slab || !thr) return fail(POTTS_EINVAL, "dev_slab or thr is NULL");
+  if (L < 16 || L % 16 || L > 65536 || q < 2 || q > POTTS_QMAX)
+    return fail(POTTS_EINVAL, "need L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256");
+  if (h < 2 || h % 2 || y0 < 0 || y0 % 2 || y0 + h > L)
+    return fail(POTTS_EINVAL, "need h even >= 2, y0 even >= 0 and y0 + h <= L");
+  if (colour != 0 && colour != 1) return fail(POTTS_EINVAL, "colour must be 0 or 1");
+  if (t < 0) return fail(POTTS_EINVAL, "t must be >= 0");
+  if (colour == 1 && (!dev_ring || ring_slots < 2 || (ring_slots & (ring_slots - 1))))
+    return fail(POTTS_EINVAL, "colour 1 needs dev_ring with a power-of-two ring_slots >= 2");
+  potts::StripLaunch l{};
+  potts::StripParams &p = l.single;
+  const uint32_t rows = potts::auto_strip_rows((uint32_t)L, (uint32_t)h, 2048ull * 256ull);
+  potts::fill_slab_params(p, dev_slab, (uint32_t)L, (uint32_t)h, (uint32_t)y0, (uint32_t)q, seed, thr, rows);
+  p.t0 = (uint64_t)t;
+  p.nsweeps = 1;
+  p.ring = reinterpret_cast<unsigned long long *>(dev_ring);
+  p.cap = colour == 1 ? (uint64_t)ring_slots : 1;
+  l.sweep = 0;
+  const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
+  const unsigned grid = (unsigned)(need < 8192 ? need : 8192);
+  HIP_TRY(potts::launch_strip(l, colour, grid, p.q, wide_table(thr), static_cast<hipStream_t>(hip_stream)));
+  return POTTS_OK;
 }
 
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {

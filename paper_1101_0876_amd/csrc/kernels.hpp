@@ -22,15 +22,21 @@ struct SweepParams {
 };
 
 // Main path (L % 16 == 0, L <= 65536): a work item is a 16-byte-wide strip of
-// `rows` consecutive rows (rows even, L % rows == 0).  One StripParams per
+// `rows` consecutive rows (rows even, nrows % rows == 0).  One StripParams per
 // lattice ("job"); it does not change between sweeps, so one table serves
-// every launch of a captured graph.
+// every launch of a captured graph.  The updated rows are storage rows
+// first_row .. first_row + nrows - 1 of `spins`: the whole lattice (0, L,
+// periodic: up_row = L-1, down_row = 0), or a row slab with its two halo
+// rows stored inline (1, h, up_row = 0, down_row = h+1).  Updated row 0 is
+// global row y0 (even), whose first chunk has Philox word ctr0 = y0 * L/4.
 struct StripParams {
   uint8_t *spins;
   uint32_t L, q;
   uint32_t ipr;         // items per row band = L/16
   uint32_t rows;        // rows per item
-  uint32_t nitems;      // (L/rows) * (L/16)
+  uint32_t nitems;      // (nrows/rows) * (L/16)
+  uint32_t nrows, first_row, up_row, down_row;
+  uint32_t ctr0;
   int32_t item_shift;   // log2(ipr) when ipr is a power of two, else -1
   uint64_t item_magic;  // ceil(2^64 / ipr) otherwise
   uint32_t row_words;   // L/4: Philox counter stride between rows
@@ -104,7 +110,12 @@ struct StatsParams {
 
 void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, uint64_t seed,
                        const uint32_t thr[4], uint32_t rows);
-uint32_t auto_strip_rows(uint32_t L, uint64_t want);
+// the same for a slab of h rows (global rows y0 ..) stored between its halos
+void fill_slab_params(StripParams &p, uint8_t *slab, uint32_t L, uint32_t h, uint32_t y0, uint32_t q,
+                      uint64_t seed, const uint32_t thr[4], uint32_t rows);
+// rows per item for `nrows` rows of width L: the largest even divisor of
+// nrows up to 32 that still gives at least `want` items
+uint32_t auto_strip_rows(uint32_t L, uint32_t nrows, uint64_t want);
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long value,
                            hipStream_t stream);

@@ -180,7 +180,7 @@ bool admit(potts_server *s, Job &j, std::string &err) {
     return false;
   }
   j.resident = potts::resident_fits((uint32_t)j.req.L, (uint32_t)j.req.q);
-  j.rows = j.resident ? 0 : potts::auto_strip_rows((uint32_t)j.req.L, 64 * 256);
+  j.rows = j.resident ? 0 : potts::auto_strip_rows((uint32_t)j.req.L, (uint32_t)j.req.L, 64 * 256);
   j.point = 0;
   j.left = j.sweeps[0];
   j.t = 0;

@@ -43,7 +43,7 @@ struct Sums {
 // byte offset of the active sites inside every dword; side_col is the column
 // of the dword holding the one horizontal neighbour outside the strip.
 template <int COLOUR, int O, int CMP, bool PRIV, bool WIDE>
-__device__ __forceinline__ void do_row(const StripParams &p, uint32_t t_lo, uint32_t t_hi,
+__device__ __forceinline__ void do_row(const StripParams &p, const PhiloxHead &h,
                                        __amdgpu_buffer_rsrc_t rs, const uint8_t *table, uint8_t *hist,
                                        uint32_t lane_off, uint32_t ro, uint32_t rn, uint32_t col,
                                        uint32_t side_col, uint32_t ctr, Carry &cy, Sums &sums) {
@@ -51,8 +51,7 @@ __device__ __forceinline__ void do_row(const StripParams &p, uint32_t t_lo, uint
   const uint32_t side = load4(rs, ro + side_col);
   const uint32_t d_lo = perm(nxt.y, nxt.x, kSel<O>), d_hi = perm(nxt.w, nxt.z, kSel<O>);
   const Row8 r = update8<COLOUR, O, CMP, WIDE>(cy.s_lo, cy.s_hi, cy.p_lo, cy.p_hi, cy.u_lo, cy.u_hi,
-                                               d_lo, d_hi, side, ctr, t_lo, t_hi, p.k0, p.k1,
-                                               p.q, table);
+                                               d_lo, d_hi, side, ctr, h, p.q, table);
   store16(rs, ro + col, r.out);
   if (COLOUR == 1) {
     sums.nz += __popc(r.nz_lo & 0xF0F0F0F0u) + __popc(r.nz_hi & 0xF0F0F0F0u);
@@ -88,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   const bool lead = TILED ? tile.lead != 0 : blockIdx.x == 0;
   if (launch.sweep >= p.nsweeps) return;  // the whole workgroup: this job is done
   const uint64_t t = p.t0 + launch.sweep;
-  const uint32_t t_lo = (uint32_t)t, t_hi = (uint32_t)(t >> 32);
+  const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, p.k0, p.k1);
 
   extern __shared__ uint32_t lds[];
   uint8_t *table = reinterpret_cast<uint8_t *>(table_words);  // 2 KB
@@ -124,10 +123,10 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
     const uint32_t col = xi * 16u;
     const uint32_t left_col = col == 0 ? L - 4 : col - 4;       // dword left of the strip
     const uint32_t right_col = col + 16 == L ? 0u : col + 16;   // dword right of the strip
-    const uint32_t r0 = rb * rows;  // even, so row r0 has active offset COLOUR
-    const uint32_t rp = (r0 == 0 ? L - 1 : r0 - 1) * L;
-    const uint32_t last_next = r0 + rows == L ? 0u : (r0 + rows) * L;
-    uint32_t ro = r0 * L;
+    const uint32_t r0 = rb * rows;  // even (as is y0), so row r0 has active offset COLOUR
+    const uint32_t rp = (r0 == 0 ? p.up_row : p.first_row + r0 - 1) * L;
+    const uint32_t last_next = (r0 + rows == p.nrows ? p.down_row : p.first_row + r0 + rows) * L;
+    uint32_t ro = (p.first_row + r0) * L;
     const u32x4 prev = load16(rs, rp + col);
     const u32x4 cur = load16(rs, ro + col);
     Carry cy;
@@ -137,15 +136,15 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
     cy.p_hi = perm(cur.w, cur.z, kSel<COLOUR ^ 1>);
     cy.u_lo = perm(prev.y, prev.x, kSel<COLOUR>);
     cy.u_hi = perm(prev.w, prev.z, kSel<COLOUR>);
-    uint32_t ctr = r0 * p.row_words + xi * 4u;
+    uint32_t ctr = p.ctr0 + r0 * p.row_words + xi * 4u;
     constexpr uint32_t kSideA = COLOUR == 0 ? 0 : 1;  // row parity 0: side dword on the left
     for (uint32_t k = 0; k < rows; k += 2) {
-      do_row<COLOUR, COLOUR, CMP, PRIV, WIDE>(p, t_lo, t_hi, rs, table, hist_bytes, lane_off, ro,
+      do_row<COLOUR, COLOUR, CMP, PRIV, WIDE>(p, h, rs, table, hist_bytes, lane_off, ro,
                                               ro + L, col, kSideA ? right_col : left_col, ctr, cy, sums);
       ro += L;
       ctr += p.row_words;
       const uint32_t rn = k + 2 == rows ? last_next : ro + L;
-      do_row<COLOUR, COLOUR ^ 1, CMP, PRIV, WIDE>(p, t_lo, t_hi, rs, table, hist_bytes, lane_off, ro,
+      do_row<COLOUR, COLOUR ^ 1, CMP, PRIV, WIDE>(p, h, rs, table, hist_bytes, lane_off, ro,
                                                   rn, col, kSideA ? left_col : right_col, ctr, cy, sums);
       ro += L;
       ctr += p.row_words;

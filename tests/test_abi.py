@@ -77,6 +77,22 @@ def test_bad_beta_and_null_state(lib):
     lib.potts_free(None)
 
 
+@pytest.mark.parametrize("bad", [dict(L=20), dict(L=8), dict(L=65552), dict(q=1), dict(q=257), dict(h=0),
+                                 dict(h=3), dict(y0=1), dict(y0=-2), dict(y0=240, h=32), dict(colour=2),
+                                 dict(t=-1), dict(slab=None), dict(thr=None), dict(ring=None),
+                                 dict(slots=3), dict(slots=1)])
+def test_slab_half_sweep_rejects_bad_arguments(lib, bad):
+    """Every check happens on the host, before anything reaches the device (the
+    pointers below are never dereferenced)."""
+    a = dict(slab=ctypes.c_void_p(0x1000), L=256, h=32, y0=64, q=5, seed=1, t=0, colour=1,
+             thr=(ctypes.c_uint32 * 4)(1, 2, 3, 4), ring=ctypes.c_void_p(0x2000), slots=4, stream=None)
+    a.update(bad)
+    rc = lib.potts_slab_half_sweep(a["slab"], a["L"], a["h"], a["y0"], a["q"], a["seed"], a["t"], a["colour"],
+                                   a["thr"], a["ring"], a["slots"], a["stream"])
+    assert rc == -1
+    assert lib.potts_last_error()
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert lib.potts_strerror(code)
