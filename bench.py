@@ -294,12 +294,123 @@ def run_serve(args):
     }
 
 
+def run_plain(args):
+    """Plain method: q=9, L=64, random start, seed 1, beta = 1.02 ln 4, 1000
+    sweeps with a record every sweep, repeated --steps times on fresh states
+    (one LDS-resident launch per run)."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    torch.cuda.set_device(0)
+    L, q, seed, n = 64, 9, 1, 1000
+    beta = 1.02 * math.log(4.0)
+    reps = max(1, args.steps if args.steps != 2000 else 20)
+    with potts.Lattice(L, q, seed, potts.RANDOM) as w:
+        w.sweep(beta, n)
+        w.observables()
+    times = []
+    for _ in range(reps):
+        with potts.Lattice(L, q, seed, potts.RANDOM) as lat:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.sweep(beta, n)
+            obs = lat.observables()  # synchronizes
+            times.append(time.perf_counter() - t0)
+    best = min(times)
+    med = sorted(times)[len(times) // 2]
+    return {"metric": "ns per spin flip", "value": med * 1e9 / (n * L * L), "unit": "ns", "n_gpus": 1,
+            "steps": reps, "warmup": 1, "ms_per_step": med * 1e3, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "plain method", "q": q, "L": L, "beta": beta, "seed": seed,
+                       "sweeps": n, "records": "every sweep"},
+            "best_ms": best * 1e3, "e_sat_last": obs["e_sat"]}
+
+
+def run_ramp(args):
+    """Metastability ramp: q in {6,9,12,15}, L=8192, 64 beta points within
+    +-2% of beta_c(q), heating (ordered start, beta descending) and cooling
+    (random start, beta ascending), --ramp-sweeps sweeps per point (the full
+    workload has 10^4; stats over the second half of each point)."""
+    import numpy as np
+    import torch
+
+    import paper_1101_0876_amd as potts
+    from paper_1101_0876_amd.workloads import beta_c
+
+    torch.cuda.set_device(0)
+    L, per = 8192, args.ramp_sweeps
+    half = per // 2
+    k = np.arange(64)
+    total = 0
+    t_all = 0.0
+    curves = {}
+    for q in (6, 9, 12, 15):
+        grid = beta_c(q) * (0.98 + 0.04 * k / 63)
+        for name, start, betas in (("heating", potts.ORDERED, grid[::-1]), ("cooling", potts.RANDOM, grid)):
+            with potts.Lattice(L, q, 1, start) as lat:
+                lat.sweep(float(betas[0]), 1)  # first launch outside the timing
+                lat.observables()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pts = lat.ramp(betas, per - half, half)
+                t_all += time.perf_counter() - t0
+                total += 64 * per
+            curves[f"q{q}_{name}"] = {"beta": [float(b) for b in betas[:: 21]],
+                                      "e": [p["e"] for p in pts[:: 21]], "C": [p["C"] for p in pts[:: 21]]}
+    return {"metric": "ns per spin flip", "value": t_all * 1e9 / (total * L * L), "unit": "ns", "n_gpus": 1,
+            "steps": total, "warmup": 1, "ms_per_step": t_all * 1e3 / total, "higher_is_better": False,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "metastability ramp", "q": [6, 9, 12, 15], "L": L, "points": 64,
+                       "sweeps_per_point": per, "window": half, "directions": ["heating", "cooling"]},
+            "wall_s": t_all, "sample_points": curves}
+
+
+def run_slabs(args):
+    """The single large lattice (L=32768, q=6, beta_c, random start) split into
+    8 row slabs of 4096 rows, the share of each of 8 devices, all swept on this
+    one: halos refreshed by device copies before every half sweep, then one
+    potts_slab_half_sweep per slab.  --steps sweeps (default 200)."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    L, q, seed, G = 32768, 6, 1, 8
+    beta = math.log1p(math.sqrt(q))
+    torch.cuda.set_device(0)
+    steps = args.steps if args.steps != 2000 else 200
+    sl = potts.Slabs(L, q, seed, potts.RANDOM, nslabs=G, ring_slots=4)
+    sl.sweep(beta, max(1, args.warmup))
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    sl.sweep(beta, steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    rec = sl.records(sl.t - 1, 1)
+    assert int(rec[0, 1:].sum()) == L * L, "population sum != N"
+    site_updates = steps * L * L
+    return {"metric": "ns per spin flip", "value": wall * 1e9 / site_updates, "unit": "ns", "n_gpus": 1,
+            "steps": steps, "warmup": max(1, args.warmup), "ms_per_step": wall * 1e3 / steps,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "row slabs of the single large lattice", "q": q, "L": L, "slabs": G,
+                       "slab_rows": L // G, "beta": beta, "seed": seed, "start": "random"},
+            "event_ms": ev_ms,
+            "per_device_share_ms_per_sweep": ev_ms / steps / G,
+            "launches_per_sweep": 2 * G, "halo_copies_per_sweep": 4 * G}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve"])
+    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs"])
+    ap.add_argument("--ramp-sweeps", type=int, default=100)
     ap.add_argument("--batch-jobs", type=int, default=1024)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-lattice-at-a-time loop")
     ap.add_argument("--serve-jobs", type=int, default=1000)
@@ -316,6 +427,15 @@ def main():
         sys.exit(2)
     if args.workload == "copy":
         print(json.dumps(run_copy(args)), flush=True)
+        return
+    if args.workload == "plain":
+        print(json.dumps(run_plain(args)), flush=True)
+        return
+    if args.workload == "ramp":
+        print(json.dumps(run_ramp(args)), flush=True)
+        return
+    if args.workload == "slabs":
+        print(json.dumps(run_slabs(args)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args)), flush=True)
