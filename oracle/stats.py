@@ -50,3 +50,42 @@ def derived(e_sat: Sequence[int], nmax: Sequence[int], N: int, q: int, beta: flo
         "S2": s2,
         "S4": s4,
     }
+
+
+def reweight(e_sat: Sequence[int], nmax: Sequence[int], N: int, q: int, beta0: float, beta: float,
+             digits: int = 50) -> Dict[str, float]:
+    """Single-histogram temperature reweighting (Ferrenberg and Swendsen, 1989;
+    named in Sec. 7): a series recorded at beta0 gives canonical averages at
+    beta as <X>_beta = sum_t X_t w_t / sum_t w_t with w_t = exp(-(beta - beta0)
+    H_t) = exp((beta - beta0) e_sat_t).  The observables are those of
+    `derived`, evaluated with the weighted averages at beta.  Arithmetic in
+    `digits`-digit decimal with an unbounded exponent range; beta0 and beta
+    enter as the exact values of the FP64 numbers passed."""
+    from decimal import MAX_EMAX, MIN_EMIN, Decimal, localcontext
+
+    n = len(e_sat)
+    if n == 0 or len(nmax) != n:
+        raise ValueError("need a non-empty window with one nmax per record")
+    with localcontext() as ctx:
+        ctx.prec = digits
+        ctx.Emax = MAX_EMAX
+        ctx.Emin = MIN_EMIN
+        b = Decimal(beta)
+        db = b - Decimal(beta0)
+        w = [(db * int(e)).exp() for e in e_sat]
+        W = sum(w)
+
+        def avg(xs):
+            return sum(wi * x for wi, x in zip(w, xs)) / W
+
+        E = [Decimal(int(e)) for e in e_sat]
+        e1, e2, e4 = avg(E), avg([x * x for x in E]), avg([x ** 4 for x in E])
+        ms = [Decimal(q * int(k) - N) / Decimal(N * (q - 1)) for k in nmax]
+        m1, m2 = avg(ms), avg([m * m for m in ms])
+        return {
+            "e": float(-e1 / N),
+            "C": float(b * b * (e2 - e1 * e1) / N),
+            "V_L": float(1 - e4 / (3 * e2 * e2)) if e2 != 0 else 0.0,
+            "m": float(m1),
+            "chi": float(N * b * (m2 - m1 * m1)),
+        }
