@@ -9,11 +9,12 @@
 //
 // The per-row update itself is in sweep_row.hpp.
 //
-// The colour-1 pass sees every site's final value of the sweep, so it alone
-// accumulates the population histogram (lane-private LDS columns) and the
-// number of satisfied bonds (sum over colour-1 sites of equal neighbours);
-// each workgroup then adds its totals to the sweep's record with one 64-bit
-// atomic per bin.
+// Each pass counts the final values of the sites it updates into the
+// population histogram (lane-private LDS columns), which spreads that work
+// over both passes; the colour-1 pass, which sees every site's final value,
+// also counts the satisfied bonds (sum over colour-1 sites of equal
+// neighbours).  Each workgroup then adds its totals to the sweep's record with
+// one 64-bit atomic per bin.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -56,11 +57,11 @@ __device__ __forceinline__ void do_row(const StripParams &p, const PhiloxHead &h
   if (COLOUR == 1) {
     sums.nz += __popc(r.nz_lo & 0xF0F0F0F0u) + __popc(r.nz_hi & 0xF0F0F0F0u);
     sums.sites += 8;
-    if (PRIV)
-      count_row_private(hist, lane_off, r.out);
-    else
-      count_row_shared(reinterpret_cast<uint32_t *>(hist), r.out);
   }
+  if (PRIV)
+    count_active_private(hist, lane_off, r.ns_lo, r.ns_hi);
+  else
+    count_active_shared(reinterpret_cast<uint32_t *>(hist), r.ns_lo, r.ns_hi);
   // the row below becomes current: its active bytes sit at the other offset,
   // its passive bytes are exactly d; this row's passive bytes are the next "up"
   cy.u_lo = cy.p_lo;
@@ -79,29 +80,36 @@ template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
 __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   // acceptance table in static LDS, so its address folds into the ds_read offset
   __shared__ __align__(16) uint32_t table_words[512];
-  const StripTile tile = TILED ? launch.tiles[blockIdx.x] : StripTile{0, 0, 0, 0};
+  // colour 1 walks the lattice bottom-up, so it starts on the rows colour 0
+  // wrote last (still in the memory-side cache), and the next colour 0 starts
+  // on the rows colour 1 wrote last
+  const uint32_t bid = COLOUR == 1 ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const StripTile tile = TILED ? launch.tiles[bid] : StripTile{0, 0, 0, 0};
   const StripParams &p = TILED ? launch.jobs[tile.job] : launch.single;
-  const uint32_t first = TILED ? tile.first + threadIdx.x : blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * kBlock + threadIdx.x;
   const uint32_t end = TILED ? tile.first + tile.count : p.nitems;
   const uint32_t stride = TILED ? (uint32_t)kBlock : gridDim.x * kBlock;
-  const bool lead = TILED ? tile.lead != 0 : blockIdx.x == 0;
+  const bool lead = TILED ? tile.lead != 0 : bid == 0;
   if (launch.sweep >= p.nsweeps) return;  // the whole workgroup: this job is done
   const uint64_t t = p.t0 + launch.sweep;
   const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, p.k0, p.k1);
 
-  extern __shared__ uint32_t lds[];
+  // population counters (PRIV: q x 64 lane columns; else q bins) and totals
+  // (q bins, then the bond sum), static so that their addresses fold into
+  // the LDS instructions' offsets
+  constexpr uint32_t kHistWords = PRIV ? 64u * (CMP == 0 ? 16u : kPrivateHistMaxQ) : 256u;
+  __shared__ __align__(16) uint32_t hist[kHistWords];
+  __shared__ uint32_t partial[257];
   uint8_t *table = reinterpret_cast<uint8_t *>(table_words);  // 2 KB
-  uint32_t *hist = lds;  // PRIV: q x 64 lane columns; else q bins
   const uint32_t q = p.q;
-  uint32_t *partial = hist + (PRIV ? 64 * q : q);  // q totals, then the bond sum
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = threadIdx.x >> 6;
 
   fill_accept_table<WIDE>(table, p.thr);
+  const uint32_t nh = PRIV ? 64 * q : q;
+  for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
+  if (threadIdx.x == 0) partial[q] = 0;
   if (COLOUR == 1) {
-    const uint32_t nh = PRIV ? 64 * q : q;
-    for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-    if (threadIdx.x == 0) partial[q] = 0;
     // the slot of sweep t+1, zeroed before the next colour-0 launch starts
     unsigned long long *rec_next = p.ring + ((t + 1) & (p.cap - 1)) * (uint64_t)(q + 1);
     if (lead)
@@ -151,25 +159,25 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
     }
   }
 
+  unsigned long long *rec = p.ring + (t & (p.cap - 1)) * (uint64_t)(q + 1);
+  uint32_t *esum = partial + q;
   if (COLOUR == 1) {
-    unsigned long long *rec = p.ring + (t & (p.cap - 1)) * (uint64_t)(q + 1);
-    uint32_t *esum = partial + q;
     const uint32_t e = wave_sum(4u * sums.sites - sums.nz);
     if (lane == 0 && e) atomicAdd(esum, e);
-    __syncthreads();
-    if (PRIV) {
-      for (uint32_t v = wave; v < q; v += kWaves) {
-        const uint32_t s = wave_sum(hist[v * 64u + lane]);
-        if (lane == 0) partial[v] = s;
-      }
-      __syncthreads();
-    }
-    for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
-      const uint32_t s = PRIV ? partial[v] : hist[v];
-      if (s) atomicAdd(&rec[1 + v], (unsigned long long)s);
-    }
-    if (threadIdx.x == 0 && *esum) atomicAdd(&rec[0], (unsigned long long)*esum);
   }
+  __syncthreads();
+  if (PRIV) {
+    for (uint32_t v = wave; v < q; v += kWaves) {
+      const uint32_t s = wave_sum(hist[v * 64u + lane]);
+      if (lane == 0) partial[v] = s;
+    }
+    __syncthreads();
+  }
+  for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
+    const uint32_t s = PRIV ? partial[v] : hist[v];
+    if (s) atomicAdd(&rec[1 + v], (unsigned long long)s);
+  }
+  if (COLOUR == 1 && threadIdx.x == 0 && *esum) atomicAdd(&rec[0], (unsigned long long)*esum);
 }
 
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
@@ -197,20 +205,11 @@ hipError_t launch_c(const StripLaunch &l, unsigned grid, uint32_t q, bool wide, 
 
 }  // namespace
 
-// dynamic LDS: the population counters and totals (the table is static)
-size_t strip_lds_bytes(uint32_t q, int colour) {
-  if (colour == 0) return 0;
-  const bool priv = q <= kPrivateHistMaxQ;
-  const size_t hist_words = priv ? (size_t)64 * q : q;
-  return hist_words * 4 + ((size_t)q + 1) * 4;
-}
-
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
                         hipStream_t stream) {
   if (grid == 0) return hipSuccess;
-  const size_t lds = strip_lds_bytes(max_q, colour);
-  return colour == 0 ? launch_c<0>(l, grid, max_q, wide, lds, stream)
-                     : launch_c<1>(l, grid, max_q, wide, lds, stream);
+  return colour == 0 ? launch_c<0>(l, grid, max_q, wide, 0, stream)
+                     : launch_c<1>(l, grid, max_q, wide, 0, stream);
 }
 
 }  // namespace potts

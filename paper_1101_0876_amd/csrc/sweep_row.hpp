@@ -161,6 +161,7 @@ __device__ __forceinline__ void fill_accept_table(uint8_t *table, const Threshol
 
 struct Row8 {
   u32x4 out;               // the 16 bytes after the update
+  uint32_t ns_lo, ns_hi;   // the 8 updated bytes, packed
   uint32_t nz_lo, nz_hi;   // colour 1: differing-neighbour flags of the new spins
 };
 
@@ -251,6 +252,8 @@ __device__ __forceinline__ Row8 update8(uint32_t s_lo, uint32_t s_hi, uint32_t p
   r.out.y = perm(ns_lo, p_lo, sel_w1);
   r.out.z = perm(ns_hi, p_hi, sel_w0);
   r.out.w = perm(ns_hi, p_hi, sel_w1);
+  r.ns_lo = ns_lo;
+  r.ns_hi = ns_hi;
   r.nz_lo = nz_lo;
   r.nz_hi = nz_hi;
   return r;
@@ -268,6 +271,29 @@ __device__ __forceinline__ void count_row_private(uint8_t *hist, uint32_t lane_o
       const uint32_t addr = perm(words[m], lane_off, 0x0C0C0000u | ((4u + b) << 8));
       atomicAdd(reinterpret_cast<uint32_t *>(hist + addr), 1u);
     }
+  }
+}
+
+// The same for the 8 updated values of a row (two packed dwords).
+__device__ __forceinline__ void count_active_private(uint8_t *hist, uint32_t lane_off, uint32_t lo,
+                                                     uint32_t hi) {
+  const uint32_t words[2] = {lo, hi};
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t addr = perm(words[m], lane_off, 0x0C0C0000u | ((4u + b) << 8));
+      atomicAdd(reinterpret_cast<uint32_t *>(hist + addr), 1u);
+    }
+  }
+}
+
+__device__ __forceinline__ void count_active_shared(uint32_t *bins, uint32_t lo, uint32_t hi) {
+  const uint32_t words[2] = {lo, hi};
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) atomicAdd(&bins[(words[m] >> (8 * b)) & 0xFFu], 1u);
   }
 }
 
