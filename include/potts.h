@@ -138,13 +138,14 @@ int potts_threshold_table(double beta, uint32_t thr[4]);
  *     colour); rows 0 and h+1 (halos) are only read, and the caller refreshes
  *     them from the neighbouring slabs before every half sweep.
  *   thr: the threshold table of the sweep's beta (potts_threshold_table).
- *   dev_ring (colour 1 only; may be NULL for colour 0): device, ring_slots
- *     (a power of two >= 2) slots of 1+q int64.  Colour 1 adds this slab's
- *     share of the record of sweep t into slot t mod ring_slots -- [0] the
- *     satisfied bonds with their colour-1 end in the slab, [1+v] the slab's
- *     sites in state v; summed over the slabs, the sweep's {e_sat, hist} --
- *     and zeroes slot (t+1) mod ring_slots for the next sweep.  Slot t must be
- *     zero before the first colour-1 call of sweep t.
+ *   dev_ring: device, ring_slots (a power of two >= 2) slots of 1+q int64.
+ *     Both calls of sweep t add this slab's share of the sweep's record into
+ *     slot t mod ring_slots: colour 0 the populations of its updated sites,
+ *     colour 1 those of its own sites and [0] the satisfied bonds with their
+ *     colour-1 end in the slab ([1+v]: sites in state v; summed over the
+ *     slabs, the sweep's {e_sat, hist}).  Colour 1 also zeroes slot (t+1) mod
+ *     ring_slots for the next sweep.  Slot t must be zero before the colour-0
+ *     call of sweep t.
  *   hip_stream: hipStream_t (NULL = default stream); asynchronous.
  * Needs L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256, h and y0 even,
  * h >= 2, y0 + h <= L.  Errors: EINVAL, EDEVICE. */
@@ -169,6 +170,21 @@ int potts_records(potts_state *s, int64_t t0, int64_t n, int64_t *out);
  * temperature beta (synchronizes).  Errors: ERANGE as potts_records, EINVAL
  * for n < 1. */
 int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summary *out);
+
+/* Temperature reweighting (Sec. 7 names it; Ferrenberg and Swendsen's
+ * single-histogram method): the records of sweeps t0 .. t0+n-1, sampled at
+ * inverse temperature beta0, give estimates of the potts_stats observables at
+ * each of betas[0..npoints).  Record t gets the weight
+ * exp(-(beta - beta0) H_t) = exp((beta - beta0) e_sat_t); out[i] holds the
+ * weighted e, C, V_L, m, chi at betas[i] (n = the window length).  FP64 on
+ * the device, with the weights and moments taken relative to the window's
+ * extreme energy and smallest order parameter (no overflow, no cancellation
+ * in the variances); estimates are reliable only where the sampled energy
+ * histogram covers the target's.  Synchronizes.
+ * Errors: EINVAL (NULL pointer, n < 1, npoints outside 1..65535, a beta < 0
+ * or not finite), ERANGE as potts_records, EDEVICE. */
+int potts_reweight(potts_state *s, int64_t t0, int64_t n, double beta0, const double *betas, int32_t npoints,
+                   potts_summary *out);
 
 /* Grows (or shrinks) the record ring to `capacity` sweeps (2 .. 2^40, rounded
  * up to a power of two).  Records held before the call are discarded.  Synchronizes.  Errors: EINVAL, ENOMEM. */

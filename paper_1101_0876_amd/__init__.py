@@ -112,6 +112,15 @@ class Lattice:
         check(self._lib.potts_stats(self._h, int(t0), int(n), float(beta), ctypes.byref(s)))
         return {"n": s.n, "e": s.e, "C": s.C, "V_L": s.V_L, "m": s.m, "chi": s.chi}
 
+    def reweight(self, t0: int, n: int, beta0: float, betas) -> list:
+        """Observables at each of `betas` from the records of sweeps t0 .. t0+n-1
+        sampled at beta0 (temperature reweighting)."""
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        out = (PottsSummary * len(b))()
+        check(self._lib.potts_reweight(self._h, int(t0), int(n), float(beta0),
+                                       b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(b), out))
+        return [{"n": s.n, "e": s.e, "C": s.C, "V_L": s.V_L, "m": s.m, "chi": s.chi} for s in out]
+
     def reserve_records(self, capacity: int) -> None:
         check(self._lib.potts_reserve_records(self._h, int(capacity)))
 

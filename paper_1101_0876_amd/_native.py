@@ -132,6 +132,9 @@ SIGNATURES = [
     ("potts_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
     ("potts_stats", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                    ctypes.POINTER(PottsSummary)]),
+    ("potts_reweight", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.POINTER(PottsSummary)]),
     ("potts_reserve_records", ctypes.c_int, [_VP, ctypes.c_int64]),
     ("potts_ramp", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.POINTER(PottsSummary)]),

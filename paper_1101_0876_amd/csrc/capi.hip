@@ -421,8 +421,8 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
     return fail(POTTS_EINVAL, "need h even >= 2, y0 even >= 0 and y0 + h <= L");
   if (colour != 0 && colour != 1) return fail(POTTS_EINVAL, "colour must be 0 or 1");
   if (t < 0) return fail(POTTS_EINVAL, "t must be >= 0");
-  if (colour == 1 && (!dev_ring || ring_slots < 2 || (ring_slots & (ring_slots - 1))))
-    return fail(POTTS_EINVAL, "colour 1 needs dev_ring with a power-of-two ring_slots >= 2");
+  if (!dev_ring || ring_slots < 2 || (ring_slots & (ring_slots - 1)))
+    return fail(POTTS_EINVAL, "need dev_ring with a power-of-two ring_slots >= 2");
   potts::StripLaunch l{};
   potts::StripParams &p = l.single;
   const uint32_t rows = potts::auto_strip_rows((uint32_t)L, (uint32_t)h, 2048ull * 256ull);
@@ -430,7 +430,7 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
   p.t0 = (uint64_t)t;
   p.nsweeps = 1;
   p.ring = reinterpret_cast<unsigned long long *>(dev_ring);
-  p.cap = colour == 1 ? (uint64_t)ring_slots : 1;
+  p.cap = (uint64_t)ring_slots;
   l.sweep = 0;
   const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
   const unsigned grid = (unsigned)(need < 8192 ? need : 8192);
@@ -512,6 +512,49 @@ int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summar
   out->V_L = v[2];
   out->m = v[3];
   out->chi = v[4];
+  return POTTS_OK;
+}
+
+int potts_reweight(potts_state *s, int64_t t0, int64_t n, double beta0, const double *betas, int32_t npoints,
+                   potts_summary *out) {
+  if (!s || !betas || !out) return fail(POTTS_EINVAL, "NULL argument");
+  if (n < 1 || n > (1ll << 24)) return fail(POTTS_EINVAL, "window must hold 1 .. 2^24 records");
+  if (npoints < 1 || npoints > 65535) return fail(POTTS_EINVAL, "npoints must be 1 .. 65535");
+  if (!(beta0 >= 0.0) || !isfinite(beta0)) return fail(POTTS_EINVAL, "beta0 must be finite and >= 0");
+  for (int32_t i = 0; i < npoints; ++i)
+    if (!(betas[i] >= 0.0) || !isfinite(betas[i])) return fail(POTTS_EINVAL, "betas must be finite and >= 0");
+  int64_t slot0 = 0;
+  int rc = ring_window(s, t0, n, &slot0);
+  if (rc) return rc;
+  double *dev = nullptr;  // npoints targets, then 5 results per target
+  const size_t bytes = (size_t)npoints * 6 * sizeof(double);
+  HIP_TRY(hipMalloc(&dev, bytes));
+  std::vector<double> host((size_t)npoints * 5);
+  potts::ReweightParams p{};
+  p.ring = s->records;
+  p.cap = s->rec_cap;
+  p.slot0 = slot0;
+  p.n = n;
+  p.q = (uint32_t)s->q;
+  p.N = n_sites(s);
+  p.beta0 = beta0;
+  p.betas = dev;
+  p.out = dev + npoints;
+  hipError_t e = hipMemcpyAsync(dev, betas, (size_t)npoints * sizeof(double), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = potts::launch_reweight(p, (unsigned)npoints, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), p.out, host.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(dev);
+  if (e != hipSuccess) return hip_fail(e, "potts_reweight");
+  for (int32_t i = 0; i < npoints; ++i) {
+    out[i].n = n;
+    out[i].e = host[5 * i + 0];
+    out[i].C = host[5 * i + 1];
+    out[i].V_L = host[5 * i + 2];
+    out[i].m = host[5 * i + 3];
+    out[i].chi = host[5 * i + 4];
+  }
   return POTTS_OK;
 }
 

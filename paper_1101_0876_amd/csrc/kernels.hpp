@@ -99,6 +99,18 @@ struct MeasureParams {
   unsigned long long *out;  // [0] e_sat, [1+v] N_v; must start zeroed
 };
 
+// Temperature reweighting of a record window sampled at beta0 to betas[b],
+// one workgroup per target (stats.hip).
+struct ReweightParams {
+  const unsigned long long *ring;
+  int64_t cap, slot0, n;           // window as in StatsParams
+  uint32_t q;
+  uint64_t N;
+  double beta0;
+  const double *betas;             // device, one per workgroup
+  double *out;                     // device, 5 per workgroup: e, C, V_L, m, chi
+};
+
 struct StatsParams {
   const unsigned long long *ring;  // record ring, cap slots of (1+q) int64
   int64_t cap, slot0, n;           // window: n records from slot0 (wrapping; cap a power of two)
@@ -125,7 +137,6 @@ hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t strea
 // comparison mode and table form covering every job of the launch
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
                         hipStream_t stream);
-size_t strip_lds_bytes(uint32_t q, int colour);
 size_t resident_lds_bytes(uint32_t L, uint32_t q);
 bool resident_fits(uint32_t L, uint32_t q);
 // n jobs (n workgroups); LDS sized for the largest L and q among them
@@ -133,6 +144,7 @@ hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max
                            bool wide, hipStream_t stream);
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
+hipError_t launch_reweight(const ReweightParams &p, unsigned npoints, hipStream_t stream);
 // one workgroup per window, params in device memory
 hipError_t launch_stats_many(const StatsParams *dev_params, unsigned n, hipStream_t stream);
 

@@ -104,7 +104,91 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams single, 
   p.out[4] = chi;
 }
 
+// Reweighting (Sec. 7 names the method: Ferrenberg-Swendsen single-histogram
+// reweighting).  Record t of the window gets the weight
+// w_t = exp((beta - beta0) (e_t - e_ref)), with e_ref the extreme of the
+// window that makes every exponent <= 0 (a common factor, so the averages do
+// not change and nothing overflows).  Moments are taken of the shifted
+// integers d = e - e_ref and u = M - M_min (M = q nmax - N), so the variances
+// lose no digits to cancellation; <E^2> and <E^4> are rebuilt from them.
+__global__ __launch_bounds__(kStatsBlock) void reweight_kernel(ReweightParams p) {
+  __shared__ int64_t ext[3][kStatsBlock];
+  __shared__ double sums[7][kStatsBlock];
+  const double beta = p.betas[blockIdx.x];
+  const double db = beta - p.beta0;
+  const uint32_t tid = threadIdx.x;
+  int64_t emin = INT64_MAX, emax = INT64_MIN, mmin = INT64_MAX;
+  for (int64_t i = tid; i < p.n; i += kStatsBlock) {
+    const unsigned long long *rec = p.ring + ((p.slot0 + i) & (p.cap - 1)) * (int64_t)(p.q + 1);
+    uint64_t nmax = 0;
+    for (uint32_t v = 0; v < p.q; ++v) nmax = rec[1 + v] > nmax ? rec[1 + v] : nmax;
+    const int64_t e = (int64_t)rec[0];
+    const int64_t m = (int64_t)p.q * (int64_t)nmax - (int64_t)p.N;
+    emin = e < emin ? e : emin;
+    emax = e > emax ? e : emax;
+    mmin = m < mmin ? m : mmin;
+  }
+  ext[0][tid] = emin;
+  ext[1][tid] = emax;
+  ext[2][tid] = mmin;
+  __syncthreads();
+  for (uint32_t off = kStatsBlock / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      ext[0][tid] = ext[0][tid + off] < ext[0][tid] ? ext[0][tid + off] : ext[0][tid];
+      ext[1][tid] = ext[1][tid + off] > ext[1][tid] ? ext[1][tid + off] : ext[1][tid];
+      ext[2][tid] = ext[2][tid + off] < ext[2][tid] ? ext[2][tid + off] : ext[2][tid];
+    }
+    __syncthreads();
+  }
+  const int64_t eref = db > 0.0 ? ext[1][0] : ext[0][0];
+  const int64_t mref = ext[2][0];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};  // W, d, d^2, d^3, d^4, u, u^2 (weighted)
+  for (int64_t i = tid; i < p.n; i += kStatsBlock) {
+    const unsigned long long *rec = p.ring + ((p.slot0 + i) & (p.cap - 1)) * (int64_t)(p.q + 1);
+    uint64_t nmax = 0;
+    for (uint32_t v = 0; v < p.q; ++v) nmax = rec[1 + v] > nmax ? rec[1 + v] : nmax;
+    const double d = (double)((int64_t)rec[0] - eref);
+    const double u = (double)((int64_t)p.q * (int64_t)nmax - (int64_t)p.N - mref);
+    const double w = exp(db * d);
+    const double wd = w * d, wd2 = wd * d;
+    acc[0] += w;
+    acc[1] += wd;
+    acc[2] += wd2;
+    acc[3] += wd2 * d;
+    acc[4] += wd2 * d * d;
+    acc[5] += w * u;
+    acc[6] += w * u * u;
+  }
+  for (int k = 0; k < 7; ++k) sums[k][tid] = acc[k];
+  __syncthreads();
+  for (uint32_t off = kStatsBlock / 2; off > 0; off >>= 1) {
+    if (tid < off)
+      for (int k = 0; k < 7; ++k) sums[k][tid] += sums[k][tid + off];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const double W = sums[0][0];
+  const double D1 = sums[1][0] / W, D2 = sums[2][0] / W, D3 = sums[3][0] / W, D4 = sums[4][0] / W;
+  const double U1 = sums[5][0] / W, U2 = sums[6][0] / W;
+  const double N = (double)p.N, q1 = (double)(p.q - 1), r = (double)eref;
+  const double e1 = r + D1;
+  const double e2 = r * r + 2.0 * r * D1 + D2;
+  const double e4 = r * r * r * r + 4.0 * r * r * r * D1 + 6.0 * r * r * D2 + 4.0 * r * D3 + D4;
+  double *out = p.out + 5 * blockIdx.x;
+  out[0] = -e1 / N;
+  out[1] = beta * beta * (D2 - D1 * D1) / N;
+  out[2] = e2 == 0.0 ? 0.0 : 1.0 - e4 / (3.0 * e2 * e2);
+  out[3] = ((double)mref + U1) / (N * q1);
+  out[4] = beta * (U2 - U1 * U1) / (N * q1 * q1);
+}
+
 }  // namespace
+
+hipError_t launch_reweight(const ReweightParams &p, unsigned npoints, hipStream_t stream) {
+  if (npoints == 0) return hipSuccess;
+  hipLaunchKernelGGL(reweight_kernel, dim3(npoints), dim3(kStatsBlock), 0, stream, p);
+  return hipGetLastError();
+}
 
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream) {
   hipLaunchKernelGGL(stats_kernel, dim3(1), dim3(kStatsBlock), 0, stream, p, (const StatsParams *)nullptr);

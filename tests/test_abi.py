@@ -80,6 +80,7 @@ def test_bad_beta_and_null_state(lib):
 @pytest.mark.parametrize("bad", [dict(L=20), dict(L=8), dict(L=65552), dict(q=1), dict(q=257), dict(h=0),
                                  dict(h=3), dict(y0=1), dict(y0=-2), dict(y0=240, h=32), dict(colour=2),
                                  dict(t=-1), dict(slab=None), dict(thr=None), dict(ring=None),
+                                 dict(ring=None, colour=0),
                                  dict(slots=3), dict(slots=1)])
 def test_slab_half_sweep_rejects_bad_arguments(lib, bad):
     """Every check happens on the host, before anything reaches the device (the
@@ -91,6 +92,11 @@ def test_slab_half_sweep_rejects_bad_arguments(lib, bad):
                                    a["thr"], a["ring"], a["slots"], a["stream"])
     assert rc == -1
     assert lib.potts_last_error()
+
+
+def test_reweight_rejects_null_without_device(lib):
+    betas = (ctypes.c_double * 1)(1.0)
+    assert lib.potts_reweight(None, 0, 1, 1.0, betas, 1, None) == -1
 
 
 def test_strerror(lib):
