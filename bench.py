@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 ALGO_OPS_PER_SITE = 20.0
 # a sweep reads and writes every uint8 spin once: 2 bytes per site update
 ALGO_BYTES_PER_SITE = 2.0
-KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/strip.hip", "paper_1101_0876_amd/csrc/device.hpp"]
+KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/strip.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
+                  "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
 
 
 def kernel_hash() -> str:
@@ -404,13 +405,51 @@ def run_slabs(args):
             "launches_per_sweep": 2 * G, "halo_copies_per_sweep": 4 * G}
 
 
+def run_metastability(args):
+    """Binder's criterion (Sec. 6): both energy branches of q=9 at L=2048 (the
+    paper's size), 20 samples each, 8 temperatures with |T - T_c|/T_c from
+    10^-1.5 down to 10^-3.5, --meta-sweeps sweeps per point (the paper uses
+    5*10^4..2*10^5 of equilibration and 5*10^4 of measurement); samples run
+    concurrently through the serving loop.  Reports the rate and the fitted
+    exponents."""
+    import numpy as np
+    import torch
+
+    from paper_1101_0876_amd.metastability import analyse, branch, spinodal_std
+
+    torch.cuda.set_device(0)
+    q, L, samples = 9, 2048, 20
+    taus = np.logspace(-1.5, -3.5, 8)
+    per = args.meta_sweeps
+    branch(q, 256, 2, taus[:2], 10, "high")  # warm-up outside the timing
+    fits, total, wall = {}, 0, 0.0
+    for side in ("high", "low"):
+        t0 = time.perf_counter()
+        b = branch(q, L, samples, taus, per, side)
+        wall += time.perf_counter() - t0
+        total += samples * len(taus) * per * L * L
+        r = analyse(b)
+        fits[side] = {"tau": [float(t) for t in b["tau"]], "e": [float(x) for x in b["e_mean"]],
+                      "e_err": [float(x) for x in b["e_err"]],
+                      "fit_all": r["fit_all"], "fit_near": r.get("fit_near"), "fit_far": r.get("fit_far")}
+    return {"metric": "ns per spin flip", "value": wall * 1e9 / total, "unit": "ns", "n_gpus": 1,
+            "steps": per, "warmup": 1, "ms_per_step": wall * 1e3 / (2 * len(taus) * per),
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic",
+            "config": {"workload": "metastability branches", "q": q, "L": L, "samples": samples,
+                       "points": len(taus), "sweeps_per_point": per, "spinodal_tau_std": spinodal_std(q)},
+            "wall_s": wall, "site_updates": total, "branches": fits}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs"])
+    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
+                                                     "metastability"])
     ap.add_argument("--ramp-sweeps", type=int, default=100)
+    ap.add_argument("--meta-sweeps", type=int, default=1000)
     ap.add_argument("--batch-jobs", type=int, default=1024)
     ap.add_argument("--no-plain", action="store_true", help="batch: skip the one-lattice-at-a-time loop")
     ap.add_argument("--serve-jobs", type=int, default=1000)
@@ -433,6 +472,9 @@ def main():
         return
     if args.workload == "ramp":
         print(json.dumps(run_ramp(args)), flush=True)
+        return
+    if args.workload == "metastability":
+        print(json.dumps(run_metastability(args)), flush=True)
         return
     if args.workload == "slabs":
         print(json.dumps(run_slabs(args)), flush=True)

@@ -1,0 +1,64 @@
+"""Physics at the transition on the GPU path (through the C ABI), against the
+exact values the paper prints.
+
+Table 2 lists, for q = 6, 9, 15, 96, the exact energies per site of the
+ordered and disordered phases at T_c (Eq. 2, Eq. 3, Eq. 6).  At beta_c an
+ordered start stays in the ordered phase and a random start in the disordered
+one on these time scales (first-order transition, L much larger than the
+correlation length), so the mean energy of the second half of the run must
+approach e_o and e_d respectively.  Tolerances cover the relaxation left after
+the first half and the statistical error of L = 2048 lattices (measured
+deviations are several times smaller).  q = 6 relaxes too slowly for a test
+(correlation length ~ 160 sites at T_c): its curve is measured by the ramp
+workload instead.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from tests.inputs import beta_c
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+
+
+def table2():
+    out = {}
+    for line in open(GOLDEN):
+        parts = line.split()
+        if parts and parts[0] == "table2":
+            out[int(parts[1])] = (-float(parts[2]), -float(parts[3]))  # (e_o, e_d)
+    return out
+
+
+@pytest.fixture(scope="module")
+def potts():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_0876_amd as p
+
+    p.load()
+    return p
+
+
+@pytest.mark.parametrize("q,n,tol", [(9, 100000, 1.5e-3), (15, 20000, 1e-3), (96, 20000, 3e-4)])
+@pytest.mark.parametrize("start", [0, 1])
+def test_table2_phase_energies_at_beta_c(potts, q, n, tol, start):
+    L, seed = 2048, 7
+    e_o, e_d = table2()[q]
+    want = e_o if start == potts.ORDERED else e_d
+    print(f"table2 q={q} start={start} n={n}", flush=True)
+    with potts.Lattice(L, q, seed, start) as lat:
+        lat.reserve_records(n // 2 + 2)
+        lat.sweep(beta_c(q), n)
+        s = lat.stats(n - n // 2, n // 2, beta_c(q))
+        last = lat.records(n - 1, 1)
+    assert int(last[0, 1:].sum()) == L * L
+    assert abs(s["e"] - want) < tol, (s["e"], want)
+    # the other phase is far away: the run did not switch phase
+    other = e_d if start == potts.ORDERED else e_o
+    assert abs(s["e"] - other) > 0.1
