@@ -320,12 +320,23 @@ def run_plain(args):
             times.append(time.perf_counter() - t0)
     best = min(times)
     med = sorted(times)[len(times) // 2]
+    cpu = None
+    if not args.no_cpu:
+        # the whole workload fits the oracle's budget: one full run, 1 thread
+        import oracle
+
+        spins = oracle.init(L, q, seed, oracle.RANDOM)
+        t0 = time.perf_counter()
+        oracle.sweeps(spins, q, seed, 0, n, oracle.threshold_table(beta), record=True)
+        el = time.perf_counter() - t0
+        cpu = {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+               "sample": f"the whole workload (L={L} q={q}, {n} sweeps with records), 1 thread"}
     return {"metric": "ns per spin flip", "value": med * 1e9 / (n * L * L), "unit": "ns", "n_gpus": 1,
             "steps": reps, "warmup": 1, "ms_per_step": med * 1e3, "higher_is_better": False,
             "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "plain method", "q": q, "L": L, "beta": beta, "seed": seed,
                        "sweeps": n, "records": "every sweep"},
-            "best_ms": best * 1e3, "e_sat_last": obs["e_sat"]}
+            "best_ms": best * 1e3, "e_sat_last": obs["e_sat"], "cpu_baseline": cpu}
 
 
 def run_ramp(args):

@@ -115,7 +115,9 @@ int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
 
 /* Launch tuning; results never depend on it (the random numbers are keyed by
  * site and sweep, not by thread).  kernel: 0 = automatic, 1 = the 16-byte strip
- * kernel (needs L % 16 == 0 and L <= 65536), 2 = the 4-byte chunk kernel,
+ * kernel (needs L % 16 == 0 and L <= 65520, i.e. a lattice below 4 GiB, which its
+ * 32-bit buffer offsets address), 2 = the 4-byte chunk kernel (any L; the
+ * automatic choice for L = 65536),
  * 3 = the LDS-resident kernel (L % 16 == 0, L <= 256: one workgroup keeps the
  * lattice in LDS and runs all sweeps of a call in one launch);
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
@@ -148,7 +150,7 @@ int potts_threshold_table(double beta, uint32_t thr[4]);
  *     call of sweep t.
  *   hip_stream: hipStream_t (NULL = default stream); asynchronous.
  * Needs L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256, h and y0 even,
- * h >= 2, y0 + h <= L.  Errors: EINVAL, EDEVICE. */
+ * h >= 2, y0 + h <= L, and a slab below 4 GiB ((h+2) L < 2^32).  Errors: EINVAL, EDEVICE. */
 int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, int32_t q, uint64_t seed,
                           int64_t t, int32_t colour, const uint32_t thr[4], int64_t *dev_ring,
                           int64_t ring_slots, void *hip_stream);
@@ -228,7 +230,7 @@ int potts_load(const char *path, potts_state **out);
  * two overlapping branches) and replayed.
  */
 typedef struct {
-    int32_t L, q;        /* L % 16 == 0, 16 <= L <= 65536; 2 <= q <= 256       */
+    int32_t L, q;        /* L % 16 == 0, 16 <= L <= 65520; 2 <= q <= 256       */
     uint64_t seed;
     int32_t start;       /* potts_start                                        */
     int32_t _pad;
@@ -299,7 +301,7 @@ typedef struct {
  * at betas[k] with the configuration carried over.  Point k's summary covers
  * its last ceil(sweeps[k]/2) sweeps (the first half equilibrates). */
 typedef struct {
-    int32_t L, q;            /* L % 16 == 0, 16 <= L <= 65536; 2 <= q <= 256  */
+    int32_t L, q;            /* L % 16 == 0, 16 <= L <= 65520; 2 <= q <= 256  */
     uint64_t seed;
     int32_t start;           /* potts_start                                   */
     int32_t npoints;         /* 1 .. 4096                                     */

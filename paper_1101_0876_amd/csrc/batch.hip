@@ -346,8 +346,8 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
   if (!jobs || n < 1) return record_error(POTTS_EINVAL, "need at least one job");
   for (int32_t i = 0; i < n; ++i) {
     const potts_job &j = jobs[i];
-    if (j.L < 16 || j.L % 16 || j.L > 65536 || j.q < 2 || j.q > POTTS_QMAX)
-      return record_error(POTTS_EINVAL, "job " + std::to_string(i) + ": need L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256");
+    if (j.L < 16 || j.L % 16 || j.L > 65520 || j.q < 2 || j.q > POTTS_QMAX)
+      return record_error(POTTS_EINVAL, "job " + std::to_string(i) + ": need L % 16 == 0, 16 <= L <= 65520, 2 <= q <= 256");
     if (j.start != POTTS_ORDERED && j.start != POTTS_RANDOM)
       return record_error(POTTS_EINVAL, "job " + std::to_string(i) + ": bad start");
     if (j.nsweeps < 0 || j.nsweeps > (1ll << 31))

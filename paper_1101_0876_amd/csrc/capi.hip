@@ -182,7 +182,9 @@ int build_table(double beta, uint32_t thr[4]) {
   return POTTS_OK;
 }
 
-bool strip_ok(const potts_state *s) { return s->L % 16 == 0 && s->L <= 65536; }
+// the strip kernel addresses the lattice with 32-bit buffer offsets, whose
+// range check leaves the last bytes of a 4 GiB buffer out: L * L < 2^32
+bool strip_ok(const potts_state *s) { return s->L % 16 == 0 && s->L <= 65520; }
 
 bool resident_ok(const potts_state *s) { return potts::resident_fits((uint32_t)s->L, (uint32_t)s->q); }
 
@@ -419,6 +421,7 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
     return fail(POTTS_EINVAL, "need L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256");
   if (h < 2 || h % 2 || y0 < 0 || y0 % 2 || y0 + h > L)
     return fail(POTTS_EINVAL, "need h even >= 2, y0 even >= 0 and y0 + h <= L");
+  if ((uint64_t)(h + 2) * (uint64_t)L >= (1ull << 32)) return fail(POTTS_EINVAL, "the slab must stay below 4 GiB");
   if (colour != 0 && colour != 1) return fail(POTTS_EINVAL, "colour must be 0 or 1");
   if (t < 0) return fail(POTTS_EINVAL, "t must be >= 0");
   if (!dev_ring || ring_slots < 2 || (ring_slots & (ring_slots - 1)))
@@ -441,7 +444,7 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (kernel < 0 || kernel > 3) return fail(POTTS_EINVAL, "kernel must be 0, 1, 2 or 3");
-  if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65536");
+  if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65520");
   if (kernel == 3 && !resident_ok(s))
     return fail(POTTS_EINVAL, "LDS-resident kernel needs L % 16 == 0, L*L <= 65536 and LDS for q");
   if (strip_rows < 0 || strip_rows % 2 || (strip_rows && s->L % strip_rows))

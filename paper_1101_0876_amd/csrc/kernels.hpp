@@ -21,7 +21,7 @@ struct SweepParams {
   unsigned long long *rec_clear;  // record slot to zero for the next sweep, or null
 };
 
-// Main path (L % 16 == 0, L <= 65536): a work item is a 16-byte-wide strip of
+// Main path (L % 16 == 0, L <= 65520): a work item is a 16-byte-wide strip of
 // `rows` consecutive rows (rows even, nrows % rows == 0).  One StripParams per
 // lattice ("job"); it does not change between sweeps, so one table serves
 // every launch of a captured graph.  The updated rows are storage rows

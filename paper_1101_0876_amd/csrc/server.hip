@@ -512,8 +512,8 @@ int potts_server_start(const potts_server_cfg *cfg, potts_server **out) {
 
 int potts_server_submit(potts_server *s, const potts_request *req, int64_t *ticket) {
   if (!s || !req || !ticket) return record_error(POTTS_EINVAL, "NULL argument");
-  if (req->L < 16 || req->L % 16 || req->L > 65536 || req->q < 2 || req->q > POTTS_QMAX)
-    return record_error(POTTS_EINVAL, "need L % 16 == 0, 16 <= L <= 65536, 2 <= q <= 256");
+  if (req->L < 16 || req->L % 16 || req->L > 65520 || req->q < 2 || req->q > POTTS_QMAX)
+    return record_error(POTTS_EINVAL, "need L % 16 == 0, 16 <= L <= 65520, 2 <= q <= 256");
   if (req->start != POTTS_ORDERED && req->start != POTTS_RANDOM) return record_error(POTTS_EINVAL, "bad start");
   if (req->npoints < 1 || req->npoints > 4096 || !req->betas || !req->sweeps)
     return record_error(POTTS_EINVAL, "need 1 .. 4096 beta points with sweeps");

@@ -4,8 +4,8 @@
 // For records {e_sat_t, hist_t} of n sweeps on N sites with q states:
 //   S1 = sum e,  S2 = sum e^2,  S4 = sum e^4          (H = -e, Eq. 1)
 //   M1 = sum (q nmax - N),  M2 = sum (q nmax - N)^2   (m = (q nmax/N - 1)/(q-1), Eq. 7)
-// S1 and M1 fit in int64, S2 and M2 in 128 bits, S4 in 256 bits for any lattice
-// this library accepts and up to 2^32 records.  The moments are exact, so the
+// With e <= 2N <= 2^33 and windows of at most 2^24 records, S1 and M1 fit in
+// int64, S2 and M2 in 128 bits and S4 in 256 bits.  The moments are exact, so the
 // large cancellations in <H^2> - <H>^2 cost nothing.
 #include <hip/hip_runtime.h>
 
@@ -26,11 +26,25 @@ __device__ __forceinline__ void add256(U256 &a, const U256 &b) {
   a.lo = lo;
 }
 
+// Full 128 x 128 -> 256-bit product (schoolbook on 64-bit limbs).
+__device__ __forceinline__ U256 mul256(u128 a, u128 b) {
+  const uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64);
+  const uint64_t b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+  const u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0, p11 = (u128)a1 * b1;
+  const u128 mid = p01 + p10;
+  const u128 mid_carry = mid < p01 ? 1 : 0;  // worth 2^192
+  U256 r;
+  r.lo = p00 + (mid << 64);
+  const u128 lo_carry = r.lo < p00 ? 1 : 0;
+  r.hi = p11 + (mid >> 64) + lo_carry + (mid_carry << 64);
+  return r;
+}
+
 struct Partial {
   int64_t s1;
   u128 s2;
   U256 s4;
-  int64_t m1;
+  u128 m1;
   u128 m2;
 };
 
@@ -50,9 +64,12 @@ __device__ double u256_to_double(const U256 &v) {
   return u128_to_double(v.hi) * 340282366920938463463374607431768211456.0 + u128_to_double(v.lo);
 }
 
-// s128 = a - b for a >= 0 representation via two's complement, then to double
-__device__ double i128_to_double(__int128 v) {
-  return v < 0 ? -u128_to_double((u128)(-v)) : u128_to_double((u128)v);
+// a - b for a >= b
+__device__ __forceinline__ U256 sub256(const U256 &a, const U256 &b) {
+  U256 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1 : 0);
+  return r;
 }
 
 constexpr int kStatsBlock = 256;
@@ -67,14 +84,14 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams single, 
     const uint64_t e = rec[0];
     uint64_t nmax = 0;
     for (uint32_t v = 0; v < p.q; ++v) nmax = rec[1 + v] > nmax ? rec[1 + v] : nmax;
-    const uint64_t e2 = e * e;
-    const u128 e4 = (u128)e2 * e2;
+    // e <= 2N <= 2^33: e^2 needs 67 bits and e^4 up to 133
+    const u128 e2 = (u128)e * e;
     acc.s1 += (int64_t)e;
-    acc.s2 += (u128)e2;
-    add256(acc.s4, U256{e4, 0});
-    const int64_t dm = (int64_t)p.q * (int64_t)nmax - (int64_t)p.N;  // >= 0
+    acc.s2 += e2;
+    add256(acc.s4, mul256(e2, e2));
+    const uint64_t dm = (uint64_t)p.q * nmax - p.N;  // >= 0, below 2^40
     acc.m1 += dm;
-    acc.m2 += (u128)((__int128)dm * dm);
+    acc.m2 += (u128)dm * dm;
   }
   part[threadIdx.x] = acc;
   __syncthreads();
@@ -87,16 +104,17 @@ __global__ __launch_bounds__(kStatsBlock) void stats_kernel(StatsParams single, 
   const double n = (double)p.n, N = (double)p.N, q1 = (double)(p.q - 1);
   // e = <H>/N = -S1/(n N)
   const double e = -(double)s.s1 / (n * N);
-  // C = beta^2 (n S2 - S1^2) / (n^2 N): exact integer numerator
-  const __int128 varnum = (__int128)(p.n) * (__int128)s.s2 - (__int128)s.s1 * (__int128)s.s1;
-  const double heat = p.beta * p.beta * (i128_to_double(varnum) / (n * n * N));
+  // C = beta^2 (n S2 - S1^2) / (n^2 N): exact integer numerator (>= 0, below 2^116)
+  const u128 varnum = (u128)p.n * s.s2 - (u128)s.s1 * (u128)s.s1;
+  const double heat = p.beta * p.beta * (u128_to_double(varnum) / (n * n * N));
   // V_L = 1 - n S4 / (3 S2^2)
   const double s2d = u128_to_double(s.s2);
   const double vl = s.s2 == 0 ? 0.0 : 1.0 - n * u256_to_double(s.s4) / (3.0 * s2d * s2d);
   // <m> = M1 / (n N (q-1)); chi = N beta (<m^2> - <m>^2) = beta (n M2 - M1^2) / (n^2 N (q-1)^2)
-  const double m = (double)s.m1 / (n * N * q1);
-  const __int128 mvar = (__int128)(p.n) * (__int128)s.m2 - (__int128)s.m1 * (__int128)s.m1;
-  const double chi = p.beta * (i128_to_double(mvar) / (n * n * N * q1 * q1));
+  // (M1 can reach 2^64 and n M2 2^128, so this numerator is taken in 256 bits)
+  const double m = u128_to_double(s.m1) / (n * N * q1);
+  const U256 mvar = sub256(mul256((u128)p.n, s.m2), mul256(s.m1, s.m1));
+  const double chi = p.beta * (u256_to_double(mvar) / (n * n * N * q1 * q1));
   p.out[0] = e;
   p.out[1] = heat;
   p.out[2] = vl;

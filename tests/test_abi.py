@@ -80,7 +80,7 @@ def test_bad_beta_and_null_state(lib):
 @pytest.mark.parametrize("bad", [dict(L=20), dict(L=8), dict(L=65552), dict(q=1), dict(q=257), dict(h=0),
                                  dict(h=3), dict(y0=1), dict(y0=-2), dict(y0=240, h=32), dict(colour=2),
                                  dict(t=-1), dict(slab=None), dict(thr=None), dict(ring=None),
-                                 dict(ring=None, colour=0),
+                                 dict(ring=None, colour=0), dict(L=65536, h=65534, y0=0),
                                  dict(slots=3), dict(slots=1)])
 def test_slab_half_sweep_rejects_bad_arguments(lib, bad):
     """Every check happens on the host, before anything reaches the device (the

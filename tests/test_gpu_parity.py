@@ -193,6 +193,61 @@ def test_large_lattice_sampled_windows(potts, oracle_lib):
         assert np.array_equal(win[r:h - r, r:w - r], spins[np.ix_(ys, xs)]), (x0, y0)
 
 
+# the largest lattices: L = 65520 is the largest the strip kernel takes (just
+# below 4 GiB); L = 65536 (4 GiB, e_sat up to 2^33) runs on the chunk kernel
+MAX_LATTICES = [65520, 65536]
+
+
+@pytest.mark.parametrize("L", MAX_LATTICES)
+def test_maximum_lattice_frozen_ground_state(potts, L):
+    """q = 256 at beta = 9 from the ordered start: every proposal costs dE = 4,
+    whose threshold floor(exp(-36) 2^32) is 0, so the lattice never changes:
+    each record is e_sat = 2N, N_0 = N, and the window statistics are e = -2,
+    C = 0, V_L = 2/3, m = 1, chi = 0 (Eq. 7, Eq. 9) -- through the exact
+    integer moments at their largest values."""
+    q, n = 256, 3
+    _say(f"maximum lattice L={L} q={q} ordered beta=9")
+    N = L * L
+    with potts.Lattice.from_torch(L, q, 5, 0, records_capacity=4) as lat:
+        lat.sweep(9.0, n)
+        rec = lat.records(0, n)
+        s = lat.stats(0, n, 9.0)
+        r = lat.reweight(0, n, 9.0, [9.0, 9.5])
+    assert np.all(rec[:, 0] == 2 * N) and np.all(rec[:, 1] == N) and not rec[:, 2:].any()
+    assert s["e"] == -2.0 and s["C"] == 0.0 and s["m"] == 1.0 and s["chi"] == 0.0
+    assert s["V_L"] == pytest.approx(2.0 / 3.0, rel=1e-15)
+    for x in r:
+        assert x["e"] == -2.0 and x["C"] == 0.0 and x["m"] == 1.0 and x["chi"] == 0.0
+        assert x["V_L"] == pytest.approx(2.0 / 3.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("L", MAX_LATTICES)
+def test_maximum_lattice_sampled_windows(potts, oracle_lib, L):
+    """A random start and one sweep: windows at the corners (the lattice's
+    last bytes included), the last rows and the last columns against the
+    oracle's window restriction."""
+    import torch
+
+    q, seed, beta, n = 7, 21, beta_c(7), 1
+    _say(f"maximum lattice L={L} q={q} random windows")
+    thr = oracle_lib.threshold_table(beta)
+    with potts.Lattice.from_torch(L, q, seed, 1, records_capacity=4) as lat:
+        lat.sweep(beta, n)
+        rec = lat.records(0, n)
+        a, b, _ = lat._keep
+        cur = (a if lat.device_ptr() == a.data_ptr() else b)[:L * L].view(L, L)
+        torch.cuda.synchronize()
+        assert int(rec[0, 1:].sum()) == L * L
+        r, h, w = 2 * n, 24, 24
+        for (x0, y0) in [(0, 0), (L - 12, L - 12), (L - 20, L - 20), (40000, L - 20), (L - 20, 50000),
+                         (65000 % L, 1)]:
+            win = oracle_lib.window(L, q, seed, 1, n, thr, x0, y0, h, w)
+            ys = torch.tensor((y0 + np.arange(r, h - r)) % L, device=cur.device)
+            xs = torch.tensor((x0 + np.arange(r, w - r)) % L, device=cur.device)
+            got = cur.index_select(0, ys).index_select(1, xs).cpu().numpy()
+            assert np.array_equal(win[r:h - r, r:w - r], got), (x0, y0)
+
+
 def test_oracle_observables_of_large_lattice(potts, oracle_lib):
     L, q, seed, beta = 8192, 15, 3, beta_c(15)
     with potts.Lattice(L, q, seed, 0) as lat:
