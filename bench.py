@@ -18,6 +18,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -38,10 +39,15 @@ KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/strip.hip", "paper_1101_0876_amd/csr
 
 
 def kernel_hash() -> str:
+    """Hash of the strip kernel's sources without comments and blank space, so
+    edits of comments keep counter data taken on the same code valid."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
