@@ -276,10 +276,17 @@ int run_resident(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   return POTTS_OK;
 }
 
-// rows per strip item: at least 2048 x 256 items (eight workgroups of 256
-// lanes per CU) when the lattice allows it
+// rows per strip item: 32 when that still gives 2048 x 256 items (eight
+// workgroups of 256 lanes per CU; L >= 32768), else 16.  Shorter strips on
+// smaller lattices cost more than they gain: measured on MI355X (q = 6),
+// 16-row strips run L = 4096 / 8192 / 16384 at 2.45 / 1.22 / 0.88 ps per
+// site update, against 5.14 / 1.48 / 0.89 with the 2-, 8- and 32-row strips
+// that a fixed item count would pick.
 uint32_t strip_rows(const potts_state *s) {
-  return s->rows ? s->rows : potts::auto_strip_rows((uint32_t)s->L, (uint32_t)s->L, 2048ull * 256ull);
+  if (s->rows) return s->rows;
+  const uint32_t L = (uint32_t)s->L;
+  if (L % 32 == 0 && (uint64_t)(L / 32) * (L / 16) >= 2048ull * 256ull) return 32;
+  return 16;
 }
 
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
