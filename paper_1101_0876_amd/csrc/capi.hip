@@ -26,6 +26,7 @@ struct potts_state {
   unsigned long long *records = nullptr;  // ring of rec_cap slots of (1+q)
   int64_t rec_cap = 0;
   unsigned long long *scratch = nullptr;  // 1+q int64 for measurements
+  unsigned long long *stripes = nullptr;  // partial records of the strip kernel (2 sets)
   double *stats_out = nullptr;            // 5 doubles
   bool have_thr = false;
   double thr_beta = 0.0;
@@ -67,6 +68,9 @@ int hip_fail(hipError_t e, const char *what) {
 
 // The ring holds a power-of-two number of slots (>= the capacity asked for),
 // so kernels find a sweep's slot with a mask.
+// partial records per set of the strip kernel's single-lattice launches
+constexpr uint32_t kStripes = 32;
+
 int64_t ring_slots(int64_t capacity) {
   int64_t n = 2;
   while (n < capacity) n <<= 1;
@@ -86,6 +90,7 @@ void release(potts_state *s) {
   }
   if (s->records) (void)hipFree(s->records);
   if (s->scratch) (void)hipFree(s->scratch);
+  if (s->stripes) (void)hipFree(s->stripes);
   if (s->stats_out) (void)hipFree(s->stats_out);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -143,14 +148,20 @@ int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spi
   }
   s->rec_cap = rec_cap;
   const size_t rec_bytes = (size_t)rec_cap * (size_t)(q + 1) * sizeof(unsigned long long);
+  const uint64_t stripe_total = 2ull * kStripes * potts::stripe_words((uint32_t)q);
   if (hipMalloc(&s->records, rec_bytes) != hipSuccess ||
       hipMalloc(&s->scratch, (size_t)(q + 1) * sizeof(unsigned long long)) != hipSuccess ||
-      hipMalloc(&s->stats_out, 8 * sizeof(double)) != hipSuccess) {
+      hipMalloc(&s->stats_out, 8 * sizeof(double)) != hipSuccess ||
+      hipMalloc(&s->stripes, stripe_total * sizeof(unsigned long long)) != hipSuccess) {
     (void)hipGetLastError();
     release(s);
     return fail(POTTS_ENOMEM, "hipMalloc of the record ring failed");
   }
   int rc = write_initial(s, start);
+  if (rc == POTTS_OK) {
+    hipError_t e = potts::launch_fill_u64(s->stripes, stripe_total, 0ull, s->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "launch_fill_u64");
+  }
   if (rc == POTTS_OK) {
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) rc = hip_fail(e, "hipStreamSynchronize");
@@ -214,6 +225,8 @@ void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, u
   p.up_row = L - 1;
   p.down_row = 0;
   p.ctr0 = 0;
+  p.stripes = nullptr;
+  p.nstripes = 0;
   p.item_shift = -1;
   p.item_magic = 0;
   if ((p.ipr & (p.ipr - 1)) == 0) {
@@ -305,14 +318,24 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     p.nsweeps = (uint64_t)nsweeps;
     p.ring = s->records;
     p.cap = (uint64_t)s->rec_cap;
+    p.stripes = s->stripes;
+    p.nstripes = kStripes;
     const unsigned groups = s->max_groups ? s->max_groups : 8192u;
     const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
     const unsigned grid = (unsigned)(need < groups ? need : groups);
     const bool wide = wide_table(thr);
-    for (int64_t j = 0; j < nsweeps; ++j) {
-      l.sweep = (uint32_t)j;
-      HIP_TRY(potts::launch_strip(l, 0, grid, p.q, wide, s->stream));
-      HIP_TRY(potts::launch_strip(l, 1, grid, p.q, wide, s->stream));
+    // segments of at most 2^30 sweeps keep the launch's sweep index in 32 bits
+    const int64_t seg = 1ll << 30;
+    for (int64_t base = 0; base < nsweeps; base += seg) {
+      const int64_t count = std::min<int64_t>(seg, nsweeps - base);
+      p.t0 = (uint64_t)(s->t + base);
+      for (int64_t j = 0; j < count; ++j) {
+        l.sweep = (uint32_t)j;
+        HIP_TRY(potts::launch_strip(l, 0, grid, p.q, wide, s->stream));
+        HIP_TRY(potts::launch_strip(l, 1, grid, p.q, wide, s->stream));
+      }
+      // the segment's last sweep: no later colour-0 launch folds its records
+      HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
     }
   } else {
     potts::SweepParams p{};

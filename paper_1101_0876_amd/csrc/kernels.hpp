@@ -46,7 +46,18 @@ struct StripParams {
   uint64_t nsweeps;     // launches with sweep >= nsweeps leave this job alone
   unsigned long long *ring;  // records of sweep t in slot t % cap
   uint64_t cap;              // a power of two
+  // Optional (single lattices): instead of adding its totals to the ring slot,
+  // a workgroup adds them to one of nstripes partial records (stripe =
+  // workgroup % nstripes, set t & 1, stripe_words() apart), which spreads the
+  // atomics of many short launches over many cache lines.  The lead
+  // workgroup of colour 0 of the next launched sweep folds set t & 1 into slot
+  // t and clears it; launch_fold_stripes does so after a run's last sweep.
+  unsigned long long *stripes;
+  uint32_t nstripes;  // a power of two
 };
+
+// distance between two partial records (1+q words rounded up to 128 bytes)
+__host__ __device__ inline uint32_t stripe_words(uint32_t q) { return (q + 1 + 15) & ~15u; }
 
 // Workgroup -> (job, item range) for launches that sweep many lattices.
 struct StripTile {
@@ -137,6 +148,8 @@ hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t strea
 // comparison mode and table form covering every job of the launch
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
                         hipStream_t stream);
+// folds stripe set t & 1 of p into ring slot t and clears it
+hipError_t launch_fold_stripes(const StripParams &p, uint64_t t, hipStream_t stream);
 size_t resident_lds_bytes(uint32_t L, uint32_t q);
 bool resident_fits(uint32_t L, uint32_t q);
 // n jobs (n workgroups); LDS sized for the largest L and q among them

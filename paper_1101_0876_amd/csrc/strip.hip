@@ -76,6 +76,27 @@ __device__ __forceinline__ void do_row(const StripParams &p, const PhiloxHead &h
 // lattices); otherwise the single descriptor in the kernel arguments with a
 // grid-stride loop.  Two instantiations keep the descriptor in scalar
 // registers in both cases.
+// Stripe set t & 1 of p summed into ring slot t, then cleared, by one whole
+// workgroup (every (stripe, word) pair loaded at once; acc: 1+q words of
+// LDS).  Contains barriers: call it from workgroup-uniform control flow.
+__device__ __forceinline__ void fold_stripes(const StripParams &p, uint64_t t, unsigned long long *acc) {
+  const uint32_t n = p.q + 1, sw = stripe_words(p.q), total = p.nstripes * n;
+  unsigned long long *set = p.stripes + (t & 1) * (uint64_t)p.nstripes * sw;
+  unsigned long long *slot = p.ring + (t & (p.cap - 1)) * (uint64_t)n;
+  for (uint32_t i = threadIdx.x; i < n; i += kBlock) acc[i] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+    const uint32_t s = k / n, i = k - s * n;
+    const unsigned long long v = set[s * sw + i];
+    if (v) {
+      atomicAdd(&acc[i], v);
+      set[s * sw + i] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += kBlock) slot[i] = acc[i];
+}
+
 template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
 __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   // acceptance table in static LDS, so its address folds into the ds_read offset
@@ -109,11 +130,14 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   const uint32_t nh = PRIV ? 64 * q : q;
   for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
   if (threadIdx.x == 0) partial[q] = 0;
-  if (COLOUR == 1) {
+  if (p.stripes) {
+    // the previous launched sweep's partial records, complete now
+    __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
+    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes(p, t - 1, fold_acc);
+  } else if (COLOUR == 1 && lead) {
     // the slot of sweep t+1, zeroed before the next colour-0 launch starts
     unsigned long long *rec_next = p.ring + ((t + 1) & (p.cap - 1)) * (uint64_t)(q + 1);
-    if (lead)
-      for (uint32_t i = threadIdx.x; i < q + 1; i += kBlock) rec_next[i] = 0;
+    for (uint32_t i = threadIdx.x; i < q + 1; i += kBlock) rec_next[i] = 0;
   }
   __syncthreads();
 
@@ -173,11 +197,18 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
     }
     __syncthreads();
   }
+  unsigned long long *dst =
+      p.stripes ? p.stripes + ((t & 1) * p.nstripes + (bid & (p.nstripes - 1))) * (uint64_t)stripe_words(q) : rec;
   for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
     const uint32_t s = PRIV ? partial[v] : hist[v];
-    if (s) atomicAdd(&rec[1 + v], (unsigned long long)s);
+    if (s) atomicAdd(&dst[1 + v], (unsigned long long)s);
   }
-  if (COLOUR == 1 && threadIdx.x == 0 && *esum) atomicAdd(&rec[0], (unsigned long long)*esum);
+  if (COLOUR == 1 && threadIdx.x == 0 && *esum) atomicAdd(&dst[0], (unsigned long long)*esum);
+}
+
+__global__ __launch_bounds__(kBlock) void fold_kernel(StripParams p, uint64_t t) {
+  __shared__ unsigned long long acc[257];
+  fold_stripes(p, t, acc);
 }
 
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
@@ -204,6 +235,11 @@ hipError_t launch_c(const StripLaunch &l, unsigned grid, uint32_t q, bool wide, 
 }
 
 }  // namespace
+
+hipError_t launch_fold_stripes(const StripParams &p, uint64_t t, hipStream_t stream) {
+  hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(kBlock), 0, stream, p, t);
+  return hipGetLastError();
+}
 
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
                         hipStream_t stream) {
