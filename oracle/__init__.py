@@ -55,6 +55,14 @@ def _load():
                                   ctypes.c_int64, u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, u8p]
     lib.oracle_window.restype = ctypes.c_int
+    lib.oracle_heatbath_site.argtypes = [ctypes.c_int, u8p, ctypes.c_uint32, u32p]
+    lib.oracle_heatbath_site.restype = ctypes.c_int
+    lib.oracle_heatbath_half_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                               ctypes.c_int, u32p, u8p]
+    lib.oracle_heatbath_half_sweep.restype = ctypes.c_int
+    lib.oracle_heatbath_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_int64, u32p, u8p, i64p]
+    lib.oracle_heatbath_sweeps.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -129,6 +137,34 @@ def sweeps(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, record: b
     rptr = _ptr(rec, ctypes.c_int64) if record else None
     _check(_load().oracle_sweeps(L, q, seed, t0, n, _ptr(t_arr, ctypes.c_uint32),
                                  _ptr(spins, ctypes.c_uint8), rptr), "sweeps")
+    return rec
+
+
+def heatbath_site(q: int, nb, w: int, thr) -> int:
+    """Heat-bath draw for one site: nb = (up, down, left, right), w its word."""
+    nbs = np.ascontiguousarray(nb, dtype=np.uint8)
+    t = np.ascontiguousarray(thr, dtype=np.uint32)
+    return int(_load().oracle_heatbath_site(q, _ptr(nbs, ctypes.c_uint8), w, _ptr(t, ctypes.c_uint32)))
+
+
+def heatbath_half_sweep(spins: np.ndarray, q: int, seed: int, t: int, colour: int, thr) -> None:
+    """In-place heat-bath update of every site of one colour."""
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    L = spins.shape[0]
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint32)
+    _check(_load().oracle_heatbath_half_sweep(L, q, seed, t, colour, _ptr(t_arr, ctypes.c_uint32),
+                                              _ptr(spins, ctypes.c_uint8)), "heatbath_half_sweep")
+
+
+def heatbath_sweeps(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, record: bool = True):
+    """n heat-bath sweeps in place from sweep index t0; records shaped (n, 1+q) or None."""
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    L = spins.shape[0]
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint32)
+    rec = np.zeros((n, 1 + q), dtype=np.int64) if record else None
+    rptr = _ptr(rec, ctypes.c_int64) if record else None
+    _check(_load().oracle_heatbath_sweeps(L, q, seed, t0, n, _ptr(t_arr, ctypes.c_uint32),
+                                          _ptr(spins, ctypes.c_uint8), rptr), "heatbath_sweeps")
     return rec
 
 

@@ -231,6 +231,97 @@ int oracle_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, con
 }
 
 /* ------------------------------------------------------------------------ */
+/* Heat-bath update (Sec. 7 names other single-spin-flip algorithms as the
+ * natural extension of the Metropolis update).  The new value k of a site is
+ * drawn with probability proportional to exp(beta n(k)), n(v) = number of the
+ * four neighbours equal to v (Eq. 1), whatever the current value.  The
+ * contract (readings of this implementation):
+ *   - weights are taken relative to the best neighbour count n_max: value v
+ *     weighs D[n_max - n(v)], D[0] = 2^32, D[d] = thr[d-1] for d = 1..4 (the
+ *     Metropolis table); the common factor exp(beta n_max) cancels and the
+ *     total weight Z is at least 2^32;
+ *   - values are ranked: the distinct neighbour values in order of first
+ *     appearance among (up, down, left, right), then every other value in
+ *     increasing order; r = floor(w Z / 2^32) for the site's 32-bit word w,
+ *     and k is the first value in the ranking whose cumulative weight exceeds
+ *     r;
+ *   - w is the word the Metropolis update uses as its proposal, from a block
+ *     whose counter word 3 is colour + 4 (a stream of its own). */
+int oracle_heatbath_site(int q, const uint8_t nb[4], uint32_t w, const uint32_t thr[4])
+{
+    int count[256] = {0};
+    int seen[256] = {0};
+    int rank[256];
+    int m = 0, n_max = 0;
+    for (int j = 0; j < 4; ++j) ++count[nb[j]];
+    for (int v = 0; v < q; ++v)
+        if (count[v] > n_max) n_max = count[v];
+    for (int j = 0; j < 4; ++j) {
+        if (!seen[nb[j]]) {
+            seen[nb[j]] = 1;
+            rank[m++] = nb[j];
+        }
+    }
+    for (int v = 0; v < q; ++v)
+        if (!seen[v]) rank[m++] = v;
+    const uint64_t D[5] = {(uint64_t)1 << 32, thr[0], thr[1], thr[2], thr[3]};
+    uint64_t Z = 0;
+    for (int i = 0; i < q; ++i) Z += D[n_max - count[rank[i]]];
+    const uint64_t r = (uint64_t)(((unsigned __int128)w * Z) >> 32);
+    uint64_t cum = 0;
+    for (int i = 0; i < q; ++i) {
+        cum += D[n_max - count[rank[i]]];
+        if (r < cum) return rank[i];
+    }
+    return rank[q - 1]; /* not reached: r < Z */
+}
+
+/* One colour of a heat-bath sweep; sites of one colour only have neighbours
+ * of the other colour (Sec. 3), so they are visited in row-major order. */
+int oracle_heatbath_half_sweep(int L, int q, uint64_t seed, uint64_t t, int colour, const uint32_t thr[4],
+                               uint8_t *spins)
+{
+    if (!valid_shape(L, q) || spins == NULL || thr == NULL || (colour != 0 && colour != 1))
+        return ORACLE_EINVAL;
+    for (int y = 0; y < L; ++y) {
+        for (int x = 0; x < L; ++x) {
+            if (((x + y) & 1) != colour) continue;
+            const uint8_t nb[4] = {
+                spins[(size_t)((y + L - 1) % L) * L + (size_t)x],      /* up    */
+                spins[(size_t)((y + 1) % L) * L + (size_t)x],          /* down  */
+                spins[(size_t)y * L + (size_t)((x + L - 1) % L)],      /* left  */
+                spins[(size_t)y * L + (size_t)((x + 1) % L)],          /* right */
+            };
+            uint32_t w[4];
+            chunk_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)colour + 4u, w);
+            const int b = (x / 2) & 1;
+            spins[(size_t)y * L + (size_t)x] = (uint8_t)oracle_heatbath_site(q, nb, w[2 * b], thr);
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* n heat-bath sweeps from sweep index t0, records as oracle_sweeps. */
+int oracle_heatbath_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, const uint32_t thr[4],
+                           uint8_t *spins, int64_t *records)
+{
+    if (!valid_shape(L, q) || spins == NULL || thr == NULL || nsweeps < 0) return ORACLE_EINVAL;
+    for (int64_t j = 0; j < nsweeps; ++j) {
+        const uint64_t t = t0 + (uint64_t)j;
+        int rc = oracle_heatbath_half_sweep(L, q, seed, t, 0, thr, spins);
+        if (rc) return rc;
+        rc = oracle_heatbath_half_sweep(L, q, seed, t, 1, thr, spins);
+        if (rc) return rc;
+        if (records) {
+            int64_t *rec = records + (size_t)j * (size_t)(1 + q);
+            rc = oracle_observables(L, q, spins, &rec[0], &rec[1]);
+            if (rc) return rc;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The same chain restricted to an h-by-w window of an L-by-L lattice whose
  * top-left corner is (x0, y0) (coordinates wrap periodically).  The window
  * starts from the initial condition and runs nsweeps sweeps from t = 0 with
