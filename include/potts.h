@@ -113,6 +113,25 @@ int potts_sweep(potts_state *s, double beta, int64_t nsweeps);
 /* As potts_sweep with a caller-supplied threshold table thr[0..3] (d = 1..4). */
 int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
 
+/* Heat-bath sweeps (Sec. 7 names other single-spin-flip algorithms as the
+ * extension of the Metropolis update): each site of colour 0, then of colour
+ * 1, takes a new value k drawn with probability proportional to
+ * exp(beta n(k)), n(k) = number of its 4 neighbours equal to k, whatever its
+ * current value.  Contract: value v weighs D[n_max - n(v)] with n_max the
+ * largest neighbour count, D[0] = 2^32 and D[d] = thr[d-1] (the table of
+ * potts_threshold_table); values are ranked as the distinct neighbour values
+ * in order of first appearance among (up, down, left, right), then the other
+ * values ascending; with Z the total weight and w the site's word (the word
+ * the Metropolis update uses as its proposal, from a block with counter word
+ * 3 = colour + 4), k is the first value in the ranking whose cumulative
+ * weight exceeds floor(w Z / 2^32).  Records, the sweep counter t and the
+ * state are shared with potts_sweep, so both kinds of sweep can be mixed.
+ * Asynchronous on the state's stream; any L % 4 == 0.
+ * Errors: as potts_sweep. */
+int potts_sweep_heatbath(potts_state *s, double beta, int64_t nsweeps);
+/* The same with a caller-supplied table. */
+int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps);
+
 /* Launch tuning; results never depend on it (the random numbers are keyed by
  * site and sweep, not by thread).  kernel: 0 = automatic, 1 = the 16-byte strip
  * kernel (needs L % 16 == 0 and L <= 65520, i.e. a lattice below 4 GiB, which its

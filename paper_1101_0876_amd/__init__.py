@@ -77,6 +77,15 @@ class Lattice:
     def sweep(self, beta: float, nsweeps: int = 1) -> None:
         check(self._lib.potts_sweep(self._h, float(beta), int(nsweeps)))
 
+    def sweep_heatbath(self, beta: float, nsweeps: int = 1) -> None:
+        """Heat-bath sweeps (potts_sweep_heatbath); shares t and records with sweep()."""
+        check(self._lib.potts_sweep_heatbath(self._h, float(beta), int(nsweeps)))
+
+    def sweep_heatbath_thr(self, thr, nsweeps: int = 1) -> None:
+        t = np.ascontiguousarray(thr, dtype=np.uint32)
+        check(self._lib.potts_sweep_heatbath_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                                 int(nsweeps)))
+
     def sweep_thr(self, thr, nsweeps: int = 1) -> None:
         t = np.ascontiguousarray(thr, dtype=np.uint32)
         check(self._lib.potts_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(nsweeps)))

@@ -122,6 +122,8 @@ SIGNATURES = [
                                      ctypes.c_size_t, _VP, ctypes.c_int64, ctypes.POINTER(_VP)]),
     ("potts_sweep", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64]),
     ("potts_sweep_thr", ctypes.c_int, [_VP, _U32P, ctypes.c_int64]),
+    ("potts_sweep_heatbath", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64]),
+    ("potts_sweep_heatbath_thr", ctypes.c_int, [_VP, _U32P, ctypes.c_int64]),
     ("potts_threshold_table", ctypes.c_int, [ctypes.c_double, _U32P]),
     ("potts_tune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("potts_slab_half_sweep", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,

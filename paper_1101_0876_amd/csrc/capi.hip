@@ -361,6 +361,37 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   return POTTS_OK;
 }
 
+// Heat-bath sweeps (kernels.hip): one thread per 4-byte chunk, records as the
+// chunk path; the sweep counter is shared with the Metropolis sweeps.
+int run_heatbath(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
+  if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
+  if (nsweeps == 0) return POTTS_OK;
+  const int64_t rl = s->q + 1;
+  HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
+  potts::SweepParams p{};
+  p.spins = s->spins;
+  p.L = (uint32_t)s->L;
+  p.q = (uint32_t)s->q;
+  p.nchunks = n_sites(s) / 4;
+  p.k0 = (uint32_t)s->seed;
+  p.k1 = (uint32_t)(s->seed >> 32);
+  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+  for (int64_t j = 0; j < nsweeps; ++j) {
+    const int64_t t = s->t + j;
+    p.t_lo = (uint32_t)(uint64_t)t;
+    p.t_hi = (uint32_t)((uint64_t)t >> 32);
+    p.rec = s->records + (t % s->rec_cap) * rl;
+    p.rec_clear = nullptr;
+    HIP_TRY(potts::launch_heatbath(p, 0, s->stream));
+    p.rec_clear = s->records + ((t + 1) % s->rec_cap) * rl;
+    HIP_TRY(potts::launch_heatbath(p, 1, s->stream));
+  }
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
 // Validates [t0, t0+n) against the ring; returns the first slot.
 int ring_window(const potts_state *s, int64_t t0, int64_t n, int64_t *slot0) {
   if (n < 0 || t0 < 0) return fail(POTTS_EINVAL, "negative record index or count");
@@ -436,6 +467,19 @@ int potts_sweep(potts_state *s, double beta, int64_t nsweeps) {
     s->have_thr = true;
   }
   return run_sweeps(s, s->thr, nsweeps);
+}
+
+int potts_sweep_heatbath(potts_state *s, double beta, int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  uint32_t thr[4];
+  int rc = build_table(beta, thr);
+  if (rc) return rc;
+  return run_heatbath(s, thr, nsweeps);
+}
+
+int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
+  return run_heatbath(s, thr, nsweeps);
 }
 
 int potts_sweep_thr(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {

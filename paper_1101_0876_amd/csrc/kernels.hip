@@ -94,6 +94,107 @@ __global__ __launch_bounds__(kBlock) void sweep4_kernel(SweepParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Heat-bath update (Sec. 7 names other single-spin-flip algorithms as the
+// extension of the Metropolis update): the new value k is drawn with weight
+// exp(beta n(k)), n(k) = neighbours equal to k, whatever the current value.
+// Weights relative to the best neighbour count n_max: value v weighs
+// D[n_max - n(v)] with D[0] = 2^32 and D[d] = thr[d-1].  Ranking: the distinct
+// neighbour values in order of first appearance among (up, down, left,
+// right), then the other values ascending; r = floor(w Z / 2^32) picks the
+// first value whose cumulative weight exceeds r.  Non-neighbour values all
+// weigh D[n_max], so that run is indexed with one division and the j-th
+// value outside the (at most four) neighbour values is found by fixed-point
+// iteration of k = j + #{excluded values <= k}.
+__device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                                  uint32_t w, const Thresholds &thr) {
+  const uint32_t na = 1 + (a == b) + (a == c) + (a == d);
+  const uint32_t nb = 1 + (b == a) + (b == c) + (b == d);
+  const uint32_t nc = 1 + (c == a) + (c == b) + (c == d);
+  const uint32_t nd = 1 + (d == a) + (d == b) + (d == c);
+  const uint32_t nmax = max(max(na, nb), max(nc, nd));
+  // first appearances
+  const bool fb = b != a, fc = c != a && c != b, fd = d != a && d != b && d != c;
+  const uint32_t m = 1 + fb + fc + fd;
+  auto weight = [&](uint32_t gap) -> uint64_t {
+    return gap == 0 ? (1ull << 32) : (uint64_t)thr.v[gap - 1];
+  };
+  const uint64_t wa = weight(nmax - na);
+  const uint64_t wb = fb ? weight(nmax - nb) : 0;
+  const uint64_t wc = fc ? weight(nmax - nc) : 0;
+  const uint64_t wd = fd ? weight(nmax - nd) : 0;
+  const uint64_t w0 = weight(nmax);  // each value no neighbour holds
+  const uint64_t S = wa + wb + wc + wd;
+  const uint64_t Z = S + (uint64_t)(q - m) * w0;  // < 2^41
+  // r = floor(w Z / 2^32), exactly, from the two halves of Z
+  const uint64_t r = (uint64_t)w * (Z >> 32) + (((uint64_t)w * (Z & 0xFFFFFFFFull)) >> 32);
+  if (r < wa) return a;
+  if (r < wa + wb) return b;
+  if (r < wa + wb + wc) return c;
+  if (r < S) return d;
+  const uint64_t j = (r - S) / w0;  // w0 > 0 here: r < Z
+  uint32_t k = (uint32_t)j;
+#pragma unroll
+  for (int it = 0; it < 5; ++it)
+    k = (uint32_t)j + (a <= k) + (fb && b <= k) + (fc && c <= k) + (fd && d <= k);
+  return k;
+}
+
+template <int COLOUR>
+__global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t esum;
+  for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
+  if (threadIdx.x == 0) esum = 0;
+  if (COLOUR == 1 && blockIdx.x == 0 && p.rec_clear) {
+    for (uint32_t i = threadIdx.x; i < p.q + 1; i += kBlock) p.rec_clear[i] = 0;
+  }
+  __syncthreads();
+
+  const uint32_t cpr = p.L >> 2;
+  uint32_t e = 0;
+  for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < p.nchunks;
+       g += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t y = (uint32_t)(g / cpr);
+    const uint32_t j = (uint32_t)(g - (uint64_t)y * cpr);
+    const uint32_t yu = y == 0 ? p.L - 1 : y - 1;
+    const uint32_t yd = y + 1 == p.L ? 0 : y + 1;
+    uint32_t *row = reinterpret_cast<uint32_t *>(p.spins + (size_t)y * p.L);
+    const uint32_t up = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yu * p.L)[j];
+    const uint32_t dn = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * p.L)[j];
+    const uint32_t cur = row[j];
+    const uint32_t lf = row[j == 0 ? cpr - 1 : j - 1];
+    const uint32_t rt = row[j + 1 == cpr ? 0 : j + 1];
+    const uint32_t left = (cur << 8) | (lf >> 24);   // byte i: spin at x-1
+    const uint32_t right = (cur >> 8) | (rt << 24);  // byte i: spin at x+1
+
+    const Words w = philox4x32_10(p.t_lo, (uint32_t)g, p.t_hi, (uint32_t)COLOUR + 4u, p.k0, p.k1);
+    const uint32_t o = (COLOUR + y) & 1u;  // byte of the first active site; the second is o + 2
+    uint32_t out = cur;
+#pragma unroll
+    for (uint32_t s = 0; s < 2; ++s) {
+      const uint32_t i = o + 2 * s;
+      const uint32_t a = byte_of(up, i), b = byte_of(dn, i), c = byte_of(left, i), d = byte_of(right, i);
+      const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, p.thr);
+      out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
+      if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
+    }
+    row[j] = out;
+    if (COLOUR == 1)
+      for (uint32_t bb = 0; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
+  }
+  if (COLOUR == 1) {
+    e = wave_sum(e);
+    if ((threadIdx.x & 63) == 0 && e) atomicAdd(&esum, e);
+    __syncthreads();
+    for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) {
+      const uint32_t cnt = hist[v];
+      if (cnt) atomicAdd(&p.rec[1 + v], (unsigned long long)cnt);
+    }
+    if (threadIdx.x == 0 && esum) atomicAdd(&p.rec[0], (unsigned long long)esum);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void init_kernel(InitParams p) {
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= p.nchunks) return;
@@ -173,6 +274,15 @@ hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t strea
     hipLaunchKernelGGL(sweep4_kernel<0>, dim3(grid), dim3(kBlock), 0, stream, p);
   else
     hipLaunchKernelGGL(sweep4_kernel<1>, dim3(grid), dim3(kBlock), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_heatbath(const SweepParams &p, int colour, hipStream_t stream) {
+  const unsigned grid = persistent_grid(p.nchunks, 4096);
+  if (colour == 0)
+    hipLaunchKernelGGL(heatbath4_kernel<0>, dim3(grid), dim3(kBlock), 0, stream, p);
+  else
+    hipLaunchKernelGGL(heatbath4_kernel<1>, dim3(grid), dim3(kBlock), 0, stream, p);
   return hipGetLastError();
 }
 

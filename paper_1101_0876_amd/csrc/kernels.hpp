@@ -144,6 +144,8 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
                            hipStream_t stream);
 hipError_t launch_init(const InitParams &p, hipStream_t stream);
 hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t stream);
+// heat-bath half sweep (kernels.hip), same parameters and records
+hipError_t launch_heatbath(const SweepParams &p, int colour, hipStream_t stream);
 // grid: number of workgroups (tiles when l.jobs is set); max_q/wide: the
 // comparison mode and table form covering every job of the launch
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,

@@ -1,0 +1,96 @@
+"""Heat-bath sweeps through the C ABI (potts_sweep_heatbath) against the
+oracle's heat-bath chain: spins and every per-sweep record bit-exact, alone
+and interleaved with Metropolis sweeps on the same state."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.inputs import beta_c
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def potts():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_0876_amd as p
+
+    p.load()
+    return p
+
+
+CASES = [
+    # L, q, seed, start, beta, sweeps
+    (4, 2, 1, 1, 0.7, 9),
+    (12, 3, 2, 1, beta_c(3), 7),
+    (20, 5, 3, 0, 1.1, 6),           # L % 16 != 0
+    (64, 9, 1, 1, 1.02 * math.log(4.0), 10),
+    (68, 100, 4, 1, 1.0, 5),
+    (32, 256, 5, 1, 2.0, 4),
+    (48, 200, 6, 0, 9.0, 4),         # zero thresholds: only the best neighbour counts
+    (128, 6, 7, 1, 0.0, 3),          # beta = 0: uniform draws
+    (256, 15, 8, 1, beta_c(15), 5),
+]
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n", CASES)
+def test_heatbath_matches_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
+    print(f"heatbath L={L} q={q} beta={beta:.4f} n={n}", flush=True)
+    s = oracle_lib.init(L, q, seed, start)
+    rec = oracle_lib.heatbath_sweeps(s, q, seed, 0, n, oracle_lib.threshold_table(beta))
+    with potts.Lattice(L, q, seed, start) as lat:
+        lat.sweep_heatbath(beta, n)
+        assert lat.t == n
+        assert np.array_equal(lat.spins(), s)
+        assert np.array_equal(lat.records(0, n), rec)
+
+
+@pytest.mark.parametrize("L", [64, 512, 100])  # resident, strip, chunk Metropolis paths
+def test_heatbath_interleaved_with_metropolis(potts, oracle_lib, L):
+    q, seed, beta = 7, 13, beta_c(7)
+    thr = oracle_lib.threshold_table(beta)
+    s = oracle_lib.init(L, q, seed, 1)
+    r1 = oracle_lib.sweeps(s, q, seed, 0, 3, thr)
+    r2 = oracle_lib.heatbath_sweeps(s, q, seed, 3, 4, thr)
+    r3 = oracle_lib.sweeps(s, q, seed, 7, 2, thr)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, 3)
+        lat.sweep_heatbath(beta, 4)
+        lat.sweep(beta, 2)
+        assert np.array_equal(lat.spins(), s)
+        assert np.array_equal(lat.records(0, 9), np.concatenate([r1, r2, r3]))
+
+
+def test_heatbath_large_lattice(potts, oracle_lib):
+    L, q, seed, beta, n = 4096, 9, 11, beta_c(9), 2
+    print(f"heatbath large L={L}", flush=True)
+    s = oracle_lib.init(L, q, seed, 1)
+    rec = oracle_lib.heatbath_sweeps(s, q, seed, 0, n, oracle_lib.threshold_table(beta))
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep_heatbath(beta, n)
+        assert np.array_equal(lat.records(0, n), rec)
+        assert np.array_equal(lat.spins(), s)
+
+
+def test_heatbath_phase_energies_at_beta_c(potts):
+    """At beta_c the ordered and random starts of q = 15 settle near Table 2's
+    e_o = -1.765905 and e_d = -0.750492 (same protocol as the Metropolis test)."""
+    L, q, n = 1024, 15, 20000
+    for start, want in ((0, -1.765905), (1, -0.750492)):
+        with potts.Lattice(L, q, 3, start) as lat:
+            lat.reserve_records(n // 2 + 2)
+            lat.sweep_heatbath(beta_c(q), n)
+            e = lat.stats(n - n // 2, n // 2, beta_c(q))["e"]
+        assert abs(e - want) < 2e-3, (start, e, want)
+
+
+def test_heatbath_rejects_bad_arguments(potts):
+    with potts.Lattice(16, 3, 1, 1) as lat:
+        with pytest.raises(potts.PottsError):
+            lat.sweep_heatbath(-1.0, 1)
+        with pytest.raises(potts.PottsError):
+            lat.sweep_heatbath(1.0, -1)
