@@ -458,13 +458,64 @@ def run_metastability(args):
             "wall_s": wall, "site_updates": total, "branches": fits}
 
 
+def run_heatbath(args):
+    """Heat-bath sweeps (Sec. 7): q=9, L=8192, random start, seed 1, beta =
+    1.02 ln 4 (the plain-method temperature), --steps sweeps (default 200),
+    with records every sweep; the oracle's heat-bath chain on an L=1024
+    sample as the CPU baseline."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    torch.cuda.set_device(0)
+    L, q, seed = 8192, 9, 1
+    beta = 1.02 * math.log(4.0)
+    steps = args.steps if args.steps != 2000 else 200
+    st = torch.cuda.Stream()
+    with potts.Lattice.from_torch(L, q, seed, potts.RANDOM, stream=st) as lat:
+        lat.sweep_heatbath(beta, max(1, args.warmup))
+        st.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        lat.sweep_heatbath(beta, steps)
+        ev1.record(st)
+        st.synchronize()
+        wall = time.perf_counter() - t0
+        rec = lat.records(lat.t - 1, 1)
+        assert int(rec[0, 1:].sum()) == L * L, "population sum != N"
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        Ls = 1024
+        spins = oracle.init(Ls, q, seed, oracle.RANDOM)
+        thr = oracle.threshold_table(beta)
+        n, t1 = 0, time.perf_counter()
+        while True:
+            oracle.heatbath_sweeps(spins, q, seed, n, 1, thr, record=True)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= args.cpu_seconds or n >= 64:
+                break
+        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+               "sample": f"L={Ls} q={q} heat-bath, random start, {n} sweeps with records, 1 thread"}
+    return {"metric": "ns per spin flip", "value": wall * 1e9 / (steps * L * L), "unit": "ns", "n_gpus": 1,
+            "steps": steps, "warmup": max(1, args.warmup), "ms_per_step": wall * 1e3 / steps,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "heat-bath sweeps", "q": q, "L": L, "beta": beta, "seed": seed,
+                       "start": "random", "records": "every sweep"},
+            "event_ms": ev0.elapsed_time(ev1), "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
-                                                     "metastability"])
+                                                     "metastability", "heatbath"])
     ap.add_argument("--ramp-sweeps", type=int, default=100)
     ap.add_argument("--meta-sweeps", type=int, default=1000)
     ap.add_argument("--batch-jobs", type=int, default=1024)
@@ -489,6 +540,9 @@ def main():
         return
     if args.workload == "ramp":
         print(json.dumps(run_ramp(args)), flush=True)
+        return
+    if args.workload == "heatbath":
+        print(json.dumps(run_heatbath(args)), flush=True)
         return
     if args.workload == "metastability":
         print(json.dumps(run_metastability(args)), flush=True)
