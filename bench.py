@@ -34,12 +34,12 @@ HBM_PEAK_GBS = 8000.0
 ALGO_OPS_PER_SITE = 20.0
 # a sweep reads and writes every uint8 spin once: 2 bytes per site update
 ALGO_BYTES_PER_SITE = 2.0
-KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/strip.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
+KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/packed.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
                   "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
 
 
 def kernel_hash() -> str:
-    """Hash of the strip kernel's sources without comments and blank space, so
+    """Hash of the dominant kernel's sources without comments and blank space, so
     edits of comments keep counter data taken on the same code valid."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -98,8 +98,11 @@ def run_large(args):
     stream = torch.cuda.Stream(device=dev)
 
     def make():
-        return [potts.Lattice.from_torch(L, q, seed, start, device=dev, stream=stream)
+        lats = [potts.Lattice.from_torch(L, q, seed, start, device=dev, stream=stream)
                 for start in (potts.ORDERED, potts.RANDOM)]
+        for lat in lats:
+            lat.tune(kernel=args.kernel)
+        return lats
 
     if args.warmup > 0:
         warm = make()
@@ -137,7 +140,7 @@ def run_large(args):
     per_launch_s = ev_ms * 1e-3 / launches
     per_launch_sites = N / 2
     achieved_ops = ALGO_OPS_PER_SITE * per_launch_sites / per_launch_s
-    traffic = counter_traffic("large")
+    traffic = counter_traffic("large") if args.kernel in (0, 4) else None
     out = {
         "metric": "ns per spin flip",
         "value": wall * 1e9 / site_updates,
@@ -161,7 +164,8 @@ def run_large(args):
             "unit": "Tops/s",
             "frac": achieved_ops / VALU_PEAK_OPS,
             "traffic": traffic,
-            "kernel": "half_sweep",
+            "kernel": {0: "packed_kernel (colour-split half sweep)", 4: "packed_kernel (colour-split half sweep)",
+                       1: "strip_kernel (row-major half sweep)", 2: "sweep4_kernel (chunk half sweep)"}[args.kernel],
             "avg_launch_us": per_launch_s * 1e6,
             "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
         },
@@ -516,6 +520,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
                                                      "metastability", "heatbath"])
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split")
     ap.add_argument("--ramp-sweeps", type=int, default=100)
     ap.add_argument("--meta-sweeps", type=int, default=1000)
     ap.add_argument("--batch-jobs", type=int, default=1024)

@@ -138,7 +138,10 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * 32-bit buffer offsets address), 2 = the 4-byte chunk kernel (any L; the
  * automatic choice for L = 65536),
  * 3 = the LDS-resident kernel (L % 16 == 0, L <= 256: one workgroup keeps the
- * lattice in LDS and runs all sweeps of a call in one launch);
+ * lattice in LDS and runs all sweeps of a call in one launch), 4 = the
+ * colour-split kernel (L % 32 == 0, L <= 65520: a call copies the lattice into
+ * two colour planes in the second buffer, sweeps there and copies it back;
+ * the automatic choice for such L above 256);
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
  * L); max_groups: persistent grid size in workgroups (0 = automatic).
  * Errors: EINVAL. */

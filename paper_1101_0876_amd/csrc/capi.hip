@@ -203,6 +203,11 @@ bool use_resident(const potts_state *s) {
   return resident_ok(s) && (s->kernel == 3 || s->kernel == 0);
 }
 
+// the colour-split copy needs 16-byte groups of packed bytes: L % 32 == 0
+bool packed_ok(const potts_state *s) { return strip_ok(s) && s->L % 32 == 0; }
+
+bool use_packed(const potts_state *s) { return packed_ok(s) && (s->kernel == 4 || s->kernel == 0); }
+
 bool use_strip(const potts_state *s) { return strip_ok(s) && (s->kernel == 1 || s->kernel == 0); }
 
 bool wide_table(const uint32_t thr[4]) { return !thr[0] || !thr[1] || !thr[2] || !thr[3]; }
@@ -211,15 +216,30 @@ bool wide_table(const uint32_t thr[4]) { return !thr[0] || !thr[1] || !thr[2] ||
 
 namespace potts {
 
+// Items of `rows` rows and ipr items per row band over nrows rows, with the
+// division item -> row band as a shift or a multiply.
+void set_items(StripParams &p, uint32_t ipr, uint32_t nrows, uint32_t rows) {
+  p.ipr = ipr;
+  p.rows = rows;
+  p.nitems = (nrows / rows) * ipr;
+  p.item_shift = -1;
+  p.item_magic = 0;
+  if ((ipr & (ipr - 1)) == 0) {
+    p.item_shift = 0;
+    while ((1u << p.item_shift) < ipr) ++p.item_shift;
+  } else {
+    // ceil(2^64 / ipr); ipr >= 3 here
+    p.item_magic = (uint64_t)(((unsigned __int128)1 << 64) / ipr) + 1;
+  }
+}
+
 // Fills the per-lattice descriptor of the strip kernel (not t0/nsweeps/ring).
 void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, uint64_t seed,
                        const uint32_t thr[4], uint32_t rows) {
   p.spins = spins;
   p.L = L;
   p.q = q;
-  p.ipr = L / 16;
-  p.rows = rows;
-  p.nitems = (L / rows) * p.ipr;
+  set_items(p, L / 16, L, rows);
   p.nrows = L;
   p.first_row = 0;
   p.up_row = L - 1;
@@ -227,15 +247,6 @@ void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, u
   p.ctr0 = 0;
   p.stripes = nullptr;
   p.nstripes = 0;
-  p.item_shift = -1;
-  p.item_magic = 0;
-  if ((p.ipr & (p.ipr - 1)) == 0) {
-    p.item_shift = 0;
-    while ((1u << p.item_shift) < p.ipr) ++p.item_shift;
-  } else {
-    // ceil(2^64 / ipr); ipr >= 3 here
-    p.item_magic = (uint64_t)(((unsigned __int128)1 << 64) / p.ipr) + 1;
-  }
   p.row_words = L / 4;
   p.k0 = (uint32_t)seed;
   p.k1 = (uint32_t)(seed >> 32);
@@ -245,7 +256,7 @@ void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, u
 void fill_slab_params(StripParams &p, uint8_t *slab, uint32_t L, uint32_t h, uint32_t y0, uint32_t q,
                       uint64_t seed, const uint32_t thr[4], uint32_t rows) {
   fill_strip_params(p, slab, L, q, seed, thr, rows);
-  p.nitems = (h / rows) * p.ipr;
+  set_items(p, L / 16, h, rows);
   p.nrows = h;
   p.first_row = 1;
   p.up_row = 0;
@@ -302,6 +313,53 @@ uint32_t strip_rows(const potts_state *s) {
   return 16;
 }
 
+// rows per item of the colour-split kernel (32 sites per item row): the
+// tallest of 32, 16, 8 that still gives 2^20 items (4096 workgroups), else 4.
+// Measured on MI355X (q = 6): L = 4096 / 8192 / 16384 / 32768 run at
+// 1.69 / 0.95 / 0.82 / 0.85 ps per site update with 4 / 4 / 8 / 32 rows.
+uint32_t packed_rows(const potts_state *s) {
+  if (s->rows) return s->rows;
+  const uint32_t L = (uint32_t)s->L;
+  for (uint32_t r = 32; r >= 8; r /= 2)
+    if (L % r == 0 && (uint64_t)(L / r) * (L / 32) >= (1ull << 20)) return r;
+  return 4;
+}
+
+// Sweeps on the colour-split copy in the second buffer (packed.hip): pack,
+// sweep, unpack; records as the strip path (striped partial records).
+int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  const uint32_t L = (uint32_t)s->L;
+  HIP_TRY(potts::launch_pack(s->spins, s->spins2, L, s->stream));
+  potts::StripLaunch l{};
+  potts::StripParams &p = l.single;
+  const uint32_t rows = packed_rows(s);
+  fill_strip_params(p, s->spins2, L, (uint32_t)s->q, s->seed, thr, rows);
+  potts::set_items(p, L / 32, L, rows);
+  p.ring = s->records;
+  p.cap = (uint64_t)s->rec_cap;
+  p.stripes = s->stripes;
+  p.nstripes = kStripes;
+  const unsigned groups = s->max_groups ? s->max_groups : 8192u;
+  const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
+  const unsigned grid = (unsigned)(need < groups ? need : groups);
+  const bool wide = wide_table(thr);
+  const int64_t seg = 1ll << 30;
+  for (int64_t base = 0; base < nsweeps; base += seg) {
+    const int64_t count = std::min<int64_t>(seg, nsweeps - base);
+    p.t0 = (uint64_t)(s->t + base);
+    p.nsweeps = (uint64_t)count;
+    for (int64_t j = 0; j < count; ++j) {
+      l.sweep = (uint32_t)j;
+      HIP_TRY(potts::launch_packed(l, 0, grid, wide, s->stream));
+      HIP_TRY(potts::launch_packed(l, 1, grid, wide, s->stream));
+    }
+    HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
+  }
+  HIP_TRY(potts::launch_unpack(s->spins2, s->spins, L, s->stream));
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
@@ -310,6 +368,7 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (use_resident(s)) return run_resident(s, thr, nsweeps);
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
+  if (use_packed(s)) return run_packed(s, thr, nsweeps);
   if (use_strip(s)) {
     potts::StripLaunch l{};
     potts::StripParams &p = l.single;
@@ -517,7 +576,9 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
 
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
-  if (kernel < 0 || kernel > 3) return fail(POTTS_EINVAL, "kernel must be 0, 1, 2 or 3");
+  if (kernel < 0 || kernel > 4) return fail(POTTS_EINVAL, "kernel must be 0 .. 4");
+  if (kernel == 4 && !packed_ok(s))
+    return fail(POTTS_EINVAL, "colour-split kernel needs L % 32 == 0 and L <= 65520");
   if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65520");
   if (kernel == 3 && !resident_ok(s))
     return fail(POTTS_EINVAL, "LDS-resident kernel needs L % 16 == 0, L*L <= 65536 and LDS for q");

@@ -133,6 +133,8 @@ struct StatsParams {
 
 void fill_strip_params(StripParams &p, uint8_t *spins, uint32_t L, uint32_t q, uint64_t seed,
                        const uint32_t thr[4], uint32_t rows);
+// items of `rows` rows, ipr per row band, over nrows rows
+void set_items(StripParams &p, uint32_t ipr, uint32_t nrows, uint32_t rows);
 // the same for a slab of h rows (global rows y0 ..) stored between its halos
 void fill_slab_params(StripParams &p, uint8_t *slab, uint32_t L, uint32_t h, uint32_t y0, uint32_t q,
                       uint64_t seed, const uint32_t thr[4], uint32_t rows);
@@ -150,6 +152,11 @@ hipError_t launch_heatbath(const SweepParams &p, int colour, hipStream_t stream)
 // comparison mode and table form covering every job of the launch
 hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_t max_q, bool wide,
                         hipStream_t stream);
+// colour-split single-lattice kernel (packed.hip): l.single describes the
+// split copy (spins = its two planes, ipr = L/32); pack/unpack convert
+hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, bool wide, hipStream_t stream);
+hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream);
+hipError_t launch_unpack(const uint8_t *packed, uint8_t *row_major, uint32_t L, hipStream_t stream);
 // folds stripe set t & 1 of p into ring slot t and clears it
 hipError_t launch_fold_stripes(const StripParams &p, uint64_t t, hipStream_t stream);
 size_t resident_lds_bytes(uint32_t L, uint32_t q);

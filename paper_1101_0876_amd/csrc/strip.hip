@@ -76,27 +76,6 @@ __device__ __forceinline__ void do_row(const StripParams &p, const PhiloxHead &h
 // lattices); otherwise the single descriptor in the kernel arguments with a
 // grid-stride loop.  Two instantiations keep the descriptor in scalar
 // registers in both cases.
-// Stripe set t & 1 of p summed into ring slot t, then cleared, by one whole
-// workgroup (every (stripe, word) pair loaded at once; acc: 1+q words of
-// LDS).  Contains barriers: call it from workgroup-uniform control flow.
-__device__ __forceinline__ void fold_stripes(const StripParams &p, uint64_t t, unsigned long long *acc) {
-  const uint32_t n = p.q + 1, sw = stripe_words(p.q), total = p.nstripes * n;
-  unsigned long long *set = p.stripes + (t & 1) * (uint64_t)p.nstripes * sw;
-  unsigned long long *slot = p.ring + (t & (p.cap - 1)) * (uint64_t)n;
-  for (uint32_t i = threadIdx.x; i < n; i += kBlock) acc[i] = 0;
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
-    const uint32_t s = k / n, i = k - s * n;
-    const unsigned long long v = set[s * sw + i];
-    if (v) {
-      atomicAdd(&acc[i], v);
-      set[s * sw + i] = 0;
-    }
-  }
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < n; i += kBlock) slot[i] = acc[i];
-}
-
 template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
 __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   // acceptance table in static LDS, so its address folds into the ds_read offset
@@ -133,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   if (p.stripes) {
     // the previous launched sweep's partial records, complete now
     __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
-    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes(p, t - 1, fold_acc);
+    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<kBlock>(p, t - 1, fold_acc);
   } else if (COLOUR == 1 && lead) {
     // the slot of sweep t+1, zeroed before the next colour-0 launch starts
     unsigned long long *rec_next = p.ring + ((t + 1) & (p.cap - 1)) * (uint64_t)(q + 1);
@@ -208,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
 
 __global__ __launch_bounds__(kBlock) void fold_kernel(StripParams p, uint64_t t) {
   __shared__ unsigned long long acc[257];
-  fold_stripes(p, t, acc);
+  fold_stripes<kBlock>(p, t, acc);
 }
 
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>

@@ -307,5 +307,27 @@ __device__ __forceinline__ void count_row_shared(uint32_t *bins, const u32x4 &ou
   }
 }
 
+// Stripe set t & 1 of p summed into ring slot t, then cleared, by one whole
+// workgroup (every (stripe, word) pair loaded at once; acc: 1+q words of
+// LDS).  Contains barriers: call it from workgroup-uniform control flow.
+template <int BLOCK>
+__device__ __forceinline__ void fold_stripes(const StripParams &p, uint64_t t, unsigned long long *acc) {
+  const uint32_t n = p.q + 1, sw = stripe_words(p.q), total = p.nstripes * n;
+  unsigned long long *set = p.stripes + (t & 1) * (uint64_t)p.nstripes * sw;
+  unsigned long long *slot = p.ring + (t & (p.cap - 1)) * (uint64_t)n;
+  for (uint32_t i = threadIdx.x; i < n; i += BLOCK) acc[i] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < total; k += BLOCK) {
+    const uint32_t s = k / n, i = k - s * n;
+    const unsigned long long v = set[s * sw + i];
+    if (v) {
+      atomicAdd(&acc[i], v);
+      set[s * sw + i] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += BLOCK) slot[i] = acc[i];
+}
+
 }  // namespace row
 }  // namespace potts

@@ -122,9 +122,11 @@ def test_record_ring_wraps(potts, oracle_lib, asked, slots):
     for); the last slots - 1 records survive any chunking of the sweeps."""
     import torch
 
-    L, q, seed, beta, n = 16, 5, 2, 0.9, 23
-    _, want = oracle_lib.run(L, q, seed, 1, beta, n)
-    for kernel in (2, 3):  # records cleared per sweep (chunk kernel) / written whole (resident)
+    q, seed, beta, n = 5, 2, 0.9, 23
+    # records cleared per sweep (chunk kernel), written whole (resident), folded
+    # from partial records (strip, colour-split)
+    for kernel, L in ((2, 16), (3, 16), (1, 32), (4, 32)):
+        _, want = oracle_lib.run(L, q, seed, 1, beta, n)
         lat = potts.Lattice.from_torch(L, q, seed, 1, records_capacity=asked)
         with lat:
             lat.tune(kernel=kernel)
@@ -261,11 +263,14 @@ def test_oracle_observables_of_large_lattice(potts, oracle_lib):
 # q at the edges of the kernels' comparison modes (<=16, <=128, <=256) and of
 # the lane-private histogram (<=32); L with power-of-two and other row widths
 @pytest.mark.parametrize("L,q", [(48, 16), (48, 17), (80, 32), (80, 33), (96, 64), (96, 65), (96, 128),
-                                 (112, 129), (208, 256), (1040, 9), (64, 2), (128, 3), (16, 7)])
-@pytest.mark.parametrize("kernel", [1, 3])
+                                 (112, 129), (208, 256), (1040, 9), (64, 2), (128, 3), (16, 7),
+                                 (224, 256), (1056, 9), (320, 33)])
+@pytest.mark.parametrize("kernel", [1, 3, 4])
 def test_kernel_q_edges(potts, oracle_lib, L, q, kernel):
     if kernel == 3 and L > 256:
         pytest.skip("LDS-resident kernel holds L <= 256")
+    if kernel == 4 and L % 32:
+        pytest.skip("colour-split kernel needs L % 32 == 0")
     seed, beta, n = 6, 0.9, 7
     _say(f"q-edge L={L} q={q} kernel={kernel}")
     want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
@@ -306,7 +311,7 @@ def test_launch_shape_does_not_change_results(potts, oracle_lib, L):
     q, seed, beta, n = 9, 11, 1.4, 6
     want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
     shapes = [(2, 0, 0), (1, 0, 0), (1, 2, 1), (1, 2, 7), (1, 4, 0), (1, 8, 3), (1, 16, 64), (1, 32, 0),
-              (3, 0, 0)]
+              (3, 0, 0), (4, 0, 0), (4, 2, 1), (4, 8, 3), (4, 16, 0), (4, 32, 5)]
     for kernel, rows, groups in shapes:
         if rows and L % rows:
             continue
@@ -329,7 +334,12 @@ def test_tune_rejects_bad_shapes(potts):
         with pytest.raises(potts.PottsError):
             lat.tune(kernel=4)
         with pytest.raises(potts.PottsError):
+            lat.tune(kernel=5)
+        with pytest.raises(potts.PottsError):
             lat.tune(kernel=0, strip_rows=3)
+    with potts.Lattice(48, 3, 1, 1) as lat:
+        with pytest.raises(potts.PottsError):
+            lat.tune(kernel=4)  # 48 % 32 != 0
 
 
 @pytest.mark.parametrize("L,start", [(64, 0), (64, 1), (512, 1), (100, 0)])
