@@ -9,10 +9,11 @@
 // A launch may hold many jobs (one per workgroup), which is how batches of
 // small lattices run.
 //
-// Work item: 16 bytes of one row (8 active sites), updated by the shared row
-// routine (sweep_row.hpp).  Items are ordered so that all rows of one parity
-// come first: a wave then usually sees a single byte parity and the parity
-// branch is uniform.
+// Work item: 8 bytes of one row (4 active sites), updated by the shared
+// 4-site row routine (sweep_row.hpp); 512 lanes, so a 64 x 64 lattice gives
+// every lane one item per half sweep and each SIMD two waves to overlap.
+// Items are ordered so that all rows of one parity come first: a wave then
+// usually sees a single byte parity and the parity branch is uniform.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -24,8 +25,11 @@ namespace {
 
 using namespace row;
 
-constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
+// A single lattice runs 8-byte items on 512 lanes (latency first: a 64 x 64
+// lattice gives each lane one item per half sweep and each SIMD two waves);
+// a batch runs 16-byte items on 256 lanes per lattice (fewer instructions per
+// site, many workgroups per CU).
+constexpr int kMaxWaves = 8;
 
 __device__ __forceinline__ u32x4 lds16(const uint8_t *lat, uint32_t off) {
   return *reinterpret_cast<const u32x4 *>(lat + off);
@@ -34,9 +38,68 @@ __device__ __forceinline__ uint32_t lds4(const uint8_t *lat, uint32_t off) {
   return *reinterpret_cast<const uint32_t *>(lat + off);
 }
 
-// One 16-byte row item of the LDS lattice (row y, byte column col).
+__device__ __forceinline__ uint2 lds8(const uint8_t *lat, uint32_t off) {
+  return *reinterpret_cast<const uint2 *>(lat + off);
+}
+
+// One 8-byte row item of the LDS lattice (row y, byte column col): 4 active
+// sites.  Returns the differing-neighbour count of its new spins (colour 1).
 template <int COLOUR, int O, int CMP, bool PRIV, bool WIDE>
 __device__ __forceinline__ uint32_t item_update(uint8_t *lat, const ResidentJob &j, uint32_t y,
+                                                uint32_t col, const PhiloxHead &h,
+                                                const uint8_t *table, uint8_t *hist,
+                                                uint32_t lane_off) {
+  const uint32_t L = j.L;
+  const uint32_t ro = y * L;
+  const uint32_t ru = (y == 0 ? L - 1 : y - 1) * L;
+  const uint32_t rd = (y + 1 == L ? 0 : y + 1) * L;
+  const uint2 cur = lds8(lat, ro + col);
+  const uint2 up = lds8(lat, ru + col);
+  const uint2 dn = lds8(lat, rd + col);
+  const uint32_t side = O == 0 ? lds4(lat, ro + (col == 0 ? L - 4 : col - 4))
+                               : lds4(lat, ro + (col + 8 == L ? 0u : col + 8));
+  const Row4 r = update4<COLOUR, O, CMP, WIDE>(
+      perm(cur.y, cur.x, kSel<O>), perm(cur.y, cur.x, kSel<O ^ 1>), perm(up.y, up.x, kSel<O>),
+      perm(dn.y, dn.x, kSel<O>), side, y * (L >> 2) + (col >> 2), h, j.q, table);
+  *reinterpret_cast<uint2 *>(lat + ro + col) = make_uint2(r.out_x, r.out_y);
+  if (COLOUR == 1) {
+    // every site is final after colour 1: count all 8 bytes
+    if (PRIV)
+      count_active_private(hist, lane_off, r.out_x, r.out_y);
+    else
+      count_active_shared(reinterpret_cast<uint32_t *>(hist), r.out_x, r.out_y);
+    return __popc(r.nz & 0xF0F0F0F0u);
+  }
+  return 0;
+}
+
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, int BLOCK>
+__device__ __forceinline__ uint32_t half_sweep8(uint8_t *lat, const ResidentJob &j, uint64_t t,
+                                               const uint8_t *table, uint8_t *hist, uint32_t lane_off) {
+  const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, j.k0, j.k1);
+  const uint32_t L = j.L;
+  const uint32_t cpr = L >> 3;                  // 8-byte items per row
+  const uint32_t per_parity = (L >> 1) * cpr;   // items in the rows of one parity
+  uint32_t nz = 0;
+  for (uint32_t i = threadIdx.x; i < 2 * per_parity; i += BLOCK) {
+    const uint32_t par = i >= per_parity;
+    const uint32_t k = i - par * per_parity;
+    const uint32_t rr = k / cpr;
+    const uint32_t y = 2 * rr + par;
+    const uint32_t col = (k - rr * cpr) * 8u;
+    if (((COLOUR + y) & 1u) == 0)
+      nz += item_update<COLOUR, 0, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
+    else
+      nz += item_update<COLOUR, 1, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
+  }
+  return nz;
+}
+
+
+// One 16-byte row item of the LDS lattice (row y, byte column col): 8 active
+// sites (batches: many lattices per launch, throughput first).
+template <int COLOUR, int O, int CMP, bool PRIV, bool WIDE>
+__device__ __forceinline__ uint32_t item_update16(uint8_t *lat, const ResidentJob &j, uint32_t y,
                                                 uint32_t col, const PhiloxHead &h,
                                                 const uint8_t *table, uint8_t *hist,
                                                 uint32_t lane_off) {
@@ -66,37 +129,43 @@ __device__ __forceinline__ uint32_t item_update(uint8_t *lat, const ResidentJob 
   return 0;
 }
 
-template <int COLOUR, int CMP, bool PRIV, bool WIDE>
-__device__ __forceinline__ uint32_t half_sweep(uint8_t *lat, const ResidentJob &j, uint64_t t,
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, int BLOCK>
+__device__ __forceinline__ uint32_t half_sweep16(uint8_t *lat, const ResidentJob &j, uint64_t t,
                                                const uint8_t *table, uint8_t *hist, uint32_t lane_off) {
   const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, j.k0, j.k1);
   const uint32_t L = j.L;
   const uint32_t cpr = L >> 4;                  // 16-byte items per row
   const uint32_t per_parity = (L >> 1) * cpr;   // items in the rows of one parity
   uint32_t nz = 0;
-  for (uint32_t i = threadIdx.x; i < 2 * per_parity; i += kBlock) {
+  for (uint32_t i = threadIdx.x; i < 2 * per_parity; i += BLOCK) {
     const uint32_t par = i >= per_parity;
     const uint32_t k = i - par * per_parity;
     const uint32_t rr = k / cpr;
     const uint32_t y = 2 * rr + par;
     const uint32_t col = (k - rr * cpr) * 16u;
     if (((COLOUR + y) & 1u) == 0)
-      nz += item_update<COLOUR, 0, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
+      nz += item_update16<COLOUR, 0, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
     else
-      nz += item_update<COLOUR, 1, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
+      nz += item_update16<COLOUR, 1, CMP, PRIV, WIDE>(lat, j, y, col, h, table, hist, lane_off);
   }
   return nz;
 }
 
-template <int CMP, bool PRIV, bool WIDE>
-__global__ __launch_bounds__(kBlock) void resident_kernel(ResidentLaunch p) {
+
+template <int CMP, bool PRIV, bool WIDE, bool NARROW>
+__global__ __launch_bounds__(NARROW ? 512 : 256) void resident_kernel(ResidentLaunch p) {
+  constexpr int kBlock = NARROW ? 512 : 256;
+  constexpr int kWaves = kBlock / 64;
+  // table, counters and totals in static LDS (addresses fold into the LDS
+  // instructions' offsets); the lattice in dynamic LDS
   __shared__ __align__(16) uint32_t table_words[512];
+  constexpr uint32_t kHistWords = PRIV ? 64u * (CMP == 0 ? 16u : kPrivateHistMaxQ) : 256u;
+  __shared__ __align__(16) uint32_t hist[kHistWords];  // PRIV: q x 64 lane columns; else q bins
+  __shared__ uint32_t partial[256 + kMaxWaves];        // q totals, then kWaves bond sums
   extern __shared__ __align__(16) uint32_t lds[];
   const ResidentJob j = p.jobs ? p.jobs[blockIdx.x] : p.single;
   const uint32_t L = j.L, q = j.q, nbytes = L * L;
   uint8_t *lat = reinterpret_cast<uint8_t *>(lds);
-  uint32_t *hist = lds + nbytes / 4;  // PRIV: q x 64 lane columns; else q bins
-  uint32_t *partial = hist + (PRIV ? 64 * q : q);  // q totals, then kWaves bond sums
   uint8_t *table = reinterpret_cast<uint8_t *>(table_words);
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint32_t lane_off = lane * 4u;
@@ -110,10 +179,14 @@ __global__ __launch_bounds__(kBlock) void resident_kernel(ResidentLaunch p) {
   for (uint32_t s = 0; s < j.nsweeps; ++s) {
     const uint64_t t = j.t0 + s;
     for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-    half_sweep<0, CMP, PRIV, WIDE>(lat, j, t, table, reinterpret_cast<uint8_t *>(hist), lane_off);
+    uint8_t *hb = reinterpret_cast<uint8_t *>(hist);
+    if (NARROW)
+      half_sweep8<0, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off);
+    else
+      half_sweep16<0, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off);
     __syncthreads();
-    const uint32_t nz = half_sweep<1, CMP, PRIV, WIDE>(lat, j, t, table,
-                                                      reinterpret_cast<uint8_t *>(hist), lane_off);
+    const uint32_t nz = NARROW ? half_sweep8<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off)
+                               : half_sweep16<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off);
     const uint32_t nz_w = wave_sum(nz);
     __syncthreads();
     if (PRIV) {
@@ -143,7 +216,10 @@ __global__ __launch_bounds__(kBlock) void resident_kernel(ResidentLaunch p) {
 
 template <int CMP, bool PRIV, bool WIDE>
 hipError_t launch_t(const ResidentLaunch &p, unsigned n, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((resident_kernel<CMP, PRIV, WIDE>), dim3(n), dim3(kBlock), lds, stream, p);
+  if (p.jobs)
+    hipLaunchKernelGGL((resident_kernel<CMP, PRIV, WIDE, false>), dim3(n), dim3(256), lds, stream, p);
+  else
+    hipLaunchKernelGGL((resident_kernel<CMP, PRIV, WIDE, true>), dim3(n), dim3(512), lds, stream, p);
   return hipGetLastError();
 }
 
@@ -157,13 +233,14 @@ hipError_t launch_w(const ResidentLaunch &p, unsigned n, uint32_t q, size_t lds,
 
 }  // namespace
 
+// dynamic LDS: the lattice (the rest is static, at most 19 KB)
 size_t resident_lds_bytes(uint32_t L, uint32_t q) {
-  const size_t hist_words = q <= kPrivateHistMaxQ ? (size_t)64 * q : q;
-  return (size_t)L * L + hist_words * 4 + ((size_t)q + kWaves) * 4;
+  (void)q;
+  return (size_t)L * L;
 }
 
 bool resident_fits(uint32_t L, uint32_t q) {
-  return L % 16 == 0 && (uint64_t)L * L <= 65536 && resident_lds_bytes(L, q) <= 96 * 1024;
+  return L % 16 == 0 && (uint64_t)L * L <= 65536 && q >= 2 && q <= 256;
 }
 
 hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max_L, uint32_t max_q,

@@ -259,6 +259,66 @@ __device__ __forceinline__ Row8 update8(uint32_t s_lo, uint32_t s_hi, uint32_t p
   return r;
 }
 
+// The same update for the 4 active sites of 8 row bytes (two Philox blocks):
+// s/p/u/d are the packed active, passive, up and down bytes, side the dword
+// left (O == 0) or right (O == 1) of the 8 bytes, ctr the chunk of the first
+// dword (even).  Used where more, smaller work items pay (the LDS-resident
+// kernel, one workgroup per small lattice).
+struct Row4 {
+  uint32_t out_x, out_y;  // the 8 bytes after the update
+  uint32_t ns;            // the 4 updated bytes, packed
+  uint32_t nz;            // colour 1: differing-neighbour flags of the new spins
+};
+
+template <int COLOUR, int O, int CMP, bool WIDE>
+__device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint32_t d, uint32_t side,
+                                        uint32_t ctr, const PhiloxHead &h, uint32_t q, const uint8_t *table) {
+  const uint32_t x = O == 0 ? alignbyte(p, side, 3) : alignbyte(side, p, 1);
+  // ctr + 1 == ctr ^ 1 for even ctr
+  const uint32_t x0 = h.a0 ^ ctr;
+  const Words b0 = philox_tail(x0, h);
+  const Words b1 = philox_tail(x0 ^ 1u, h);
+  const uint32_t k = pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
+  const uint32_t ps = diff_pattern<CMP>(s, u, d, p, x);
+  const uint32_t pk = diff_pattern<CMP>(k, u, d, p, x);
+  const uint32_t idx = bfi(0xF0F0F0F0u, pk, ps >> 4);
+  uint32_t ns = s, nz = 0;
+  if (!WIDE) {
+#define POTTS_T(J) *reinterpret_cast<const uint32_t *>(table + table_offset<J, 2>(idx))
+    const uint32_t t0 = POTTS_T(0), t1 = POTTS_T(1), t2 = POTTS_T(2), t3 = POTTS_T(3);
+#undef POTTS_T
+    if (COLOUR == 0) {
+      accept_byte<0>(ns, b0.w1, t0, s, k);
+      accept_byte<1>(ns, b0.w3, t1, s, k);
+      accept_byte<2>(ns, b1.w1, t2, s, k);
+      accept_byte<3>(ns, b1.w3, t3, s, k);
+    } else {
+      nz = ps;
+      accept_byte2<0>(ns, nz, b0.w1, t0, s, k, ps, pk);
+      accept_byte2<1>(ns, nz, b0.w3, t1, s, k, ps, pk);
+      accept_byte2<2>(ns, nz, b1.w1, t2, s, k, ps, pk);
+      accept_byte2<3>(ns, nz, b1.w3, t3, s, k, ps, pk);
+    }
+  } else {
+    const uint64_t *t64 = reinterpret_cast<const uint64_t *>(table);
+    const uint32_t acc_w[4] = {b0.w1, b0.w3, b1.w1, b1.w3};
+    uint32_t sel = 0x03020100u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if ((uint64_t)acc_w[j] < t64[(idx >> (8 * j)) & 0xFFu]) sel |= 4u << (8 * j);
+    ns = perm(k, s, sel);
+    if (COLOUR == 1) nz = perm(pk, ps, sel);
+  }
+  constexpr uint32_t sel_w0 = O ? 0x05010400u : 0x01050004u;
+  constexpr uint32_t sel_w1 = O ? 0x07030602u : 0x03070206u;
+  Row4 r;
+  r.out_x = perm(ns, p, sel_w0);
+  r.out_y = perm(ns, p, sel_w1);
+  r.ns = ns;
+  r.nz = nz;
+  return r;
+}
+
 // Counts the 16 final values of a row into lane-private LDS columns:
 // counter (value, lane) at byte (value << 8) | lane*4 of `hist`, one v_perm
 // per value.  Colours share the columns; LDS atomics keep them exact.
