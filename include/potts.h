@@ -98,7 +98,10 @@ int potts_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_sta
 /* As potts_init, but on caller-owned device buffers and stream: dev_spins and
  * dev_spins2 each hold at least L*L bytes (bytes gives the size of each) and
  * must outlive the state; hip_stream is a hipStream_t (NULL = the default
- * stream).  The records ring is still owned by the library. */
+ * stream).  dev_spins holds the row-major lattice between calls; dev_spins2
+ * is the library's scratch (the colour-split copy a sweep call works on), so
+ * neither may be touched while a call's work is in flight on the stream.  The
+ * records ring is still owned by the library. */
 int potts_init_ex(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spins,
                   void *dev_spins2, size_t bytes, void *hip_stream, int64_t records_capacity,
                   potts_state **out);
