@@ -63,6 +63,20 @@ def _load():
     lib.oracle_heatbath_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.c_int64, u32p, u8p, i64p]
     lib.oracle_heatbath_sweeps.restype = ctypes.c_int
+    lib.oracle_threshold_table6.argtypes = [ctypes.c_double, u32p]
+    lib.oracle_threshold_table6.restype = ctypes.c_int
+    lib.oracle3d_init.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, u8p]
+    lib.oracle3d_init.restype = ctypes.c_int
+    lib.oracle3d_site_update.argtypes = [ctypes.c_int, ctypes.c_int, u8p, ctypes.c_uint32, ctypes.c_uint32, u32p]
+    lib.oracle3d_site_update.restype = ctypes.c_int
+    lib.oracle3d_half_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                        u32p, u8p]
+    lib.oracle3d_half_sweep.restype = ctypes.c_int
+    lib.oracle3d_observables.argtypes = [ctypes.c_int, ctypes.c_int, u8p, i64p, i64p]
+    lib.oracle3d_observables.restype = ctypes.c_int
+    lib.oracle3d_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                    u32p, u8p, i64p]
+    lib.oracle3d_sweeps.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -165,6 +179,52 @@ def heatbath_sweeps(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, 
     rptr = _ptr(rec, ctypes.c_int64) if record else None
     _check(_load().oracle_heatbath_sweeps(L, q, seed, t0, n, _ptr(t_arr, ctypes.c_uint32),
                                           _ptr(spins, ctypes.c_uint8), rptr), "heatbath_sweeps")
+    return rec
+
+
+# -- simple-cubic lattice ---------------------------------------------------------
+def threshold_table6(beta: float) -> np.ndarray:
+    """thr[d-1] = min(floor(exp(-beta*d) * 2^32), 2^32-1), d = 1..6 (cubic lattice)."""
+    thr = np.zeros(6, dtype=np.uint32)
+    _check(_load().oracle_threshold_table6(float(beta), _ptr(thr, ctypes.c_uint32)), "threshold_table6")
+    return thr
+
+
+def init3d(L: int, q: int, seed: int, start: int) -> np.ndarray:
+    spins = np.zeros((L, L, L), dtype=np.uint8)  # [z, y, x]
+    _check(_load().oracle3d_init(L, q, seed, start, _ptr(spins, ctypes.c_uint8)), "init3d")
+    return spins
+
+
+def site_update3d(q: int, s: int, nb, w_prop: int, w_acc: int, thr) -> int:
+    nbs = np.ascontiguousarray(nb, dtype=np.uint8)
+    t = np.ascontiguousarray(thr, dtype=np.uint32)
+    return int(_load().oracle3d_site_update(q, s, _ptr(nbs, ctypes.c_uint8), w_prop, w_acc,
+                                            _ptr(t, ctypes.c_uint32)))
+
+
+def half_sweep3d(spins: np.ndarray, q: int, seed: int, t: int, colour: int, thr) -> None:
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint32)
+    _check(_load().oracle3d_half_sweep(spins.shape[0], q, seed, t, colour, _ptr(t_arr, ctypes.c_uint32),
+                                       _ptr(spins, ctypes.c_uint8)), "half_sweep3d")
+
+
+def observables3d(spins: np.ndarray, q: int):
+    e = np.zeros(1, dtype=np.int64)
+    hist = np.zeros(q, dtype=np.int64)
+    _check(_load().oracle3d_observables(spins.shape[0], q, _ptr(spins, ctypes.c_uint8), _ptr(e, ctypes.c_int64),
+                                        _ptr(hist, ctypes.c_int64)), "observables3d")
+    return int(e[0]), hist
+
+
+def sweeps3d(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, record: bool = True):
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint32)
+    rec = np.zeros((n, 1 + q), dtype=np.int64) if record else None
+    rptr = _ptr(rec, ctypes.c_int64) if record else None
+    _check(_load().oracle3d_sweeps(spins.shape[0], q, seed, t0, n, _ptr(t_arr, ctypes.c_uint32),
+                                   _ptr(spins, ctypes.c_uint8), rptr), "sweeps3d")
     return rec
 
 

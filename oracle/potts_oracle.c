@@ -379,3 +379,140 @@ int oracle_window(int L, int q, uint64_t seed, int start, int64_t nsweeps, const
     free(cur);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Simple-cubic lattice (Sec. 7: the checkerboard update carries over to three
+ * dimensions with its two independent sub-lattices).  Contract of this
+ * implementation, the 2D one lifted to L x L x L:
+ *   - site (x, y, z) at byte (z L + y) L + x, periodic, L >= 4, L % 4 == 0;
+ *   - colour (x + y + z) & 1, colour 0 first;
+ *   - six neighbours, dE = n(s) - n(k) in -6..6, thresholds for d = 1..6;
+ *   - Philox block per (4-byte row chunk, sweep, colour): counter
+ *     (t_lo, ((z L + y) L + x) / 4, t_hi, colour + 8); site x takes
+ *     (w[2b], w[2b+1]), b = (x/2) & 1; random start: counter
+ *     (0, chunk, 0, 10) and value floor(w[x&3] q / 2^32). */
+int oracle_threshold_table6(double beta, uint32_t thr[6])
+{
+    if (!(beta >= 0.0) || isinf(beta)) return ORACLE_EINVAL;
+    for (int d = 1; d <= 6; ++d) {
+        double scaled = floor(exp(-beta * (double)d) * 4294967296.0);
+        if (scaled > 4294967295.0) scaled = 4294967295.0;
+        thr[d - 1] = (uint32_t)scaled;
+    }
+    return ORACLE_OK;
+}
+
+static int valid_cube(int L, int q)
+{
+    return L >= 4 && L % 4 == 0 && (uint64_t)L * L * L / 4 < ((uint64_t)1 << 32) && q >= 2 && q <= 256;
+}
+
+static void cube_words(int L, int x, int y, int z, uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3,
+                       uint32_t w[4])
+{
+    const uint64_t site = ((uint64_t)z * L + (uint64_t)y) * L + (uint64_t)x;
+    const uint32_t ctr[4] = {c0, (uint32_t)(site / 4), c2, c3};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, w);
+}
+
+static size_t cube_at(int L, int x, int y, int z)
+{
+    return ((size_t)z * (size_t)L + (size_t)y) * (size_t)L + (size_t)x;
+}
+
+int oracle3d_init(int L, int q, uint64_t seed, int start, uint8_t *spins)
+{
+    if (!valid_cube(L, q) || spins == NULL || (start != 0 && start != 1)) return ORACLE_EINVAL;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                uint8_t value = 0;
+                if (start == 1) {
+                    uint32_t w[4];
+                    cube_words(L, x, y, z, seed, 0u, 0u, 10u, w);
+                    value = (uint8_t)word_to_value(w[x & 3], q);
+                }
+                spins[cube_at(L, x, y, z)] = value;
+            }
+    return ORACLE_OK;
+}
+
+/* One Metropolis trial with six neighbours (Eq. 1 on the cubic lattice). */
+int oracle3d_site_update(int q, int s, const uint8_t nb[6], uint32_t w_prop, uint32_t w_acc,
+                         const uint32_t thr[6])
+{
+    const int k = (int)word_to_value(w_prop, q);
+    int equal_now = 0, equal_new = 0;
+    for (int j = 0; j < 6; ++j) {
+        if (nb[j] == s) ++equal_now;
+        if (nb[j] == k) ++equal_new;
+    }
+    const int dE = equal_now - equal_new;
+    const int accept = dE <= 0 ? 1 : (w_acc < thr[dE - 1]);
+    return accept ? k : s;
+}
+
+int oracle3d_half_sweep(int L, int q, uint64_t seed, uint64_t t, int colour, const uint32_t thr[6],
+                        uint8_t *spins)
+{
+    if (!valid_cube(L, q) || spins == NULL || thr == NULL || (colour != 0 && colour != 1))
+        return ORACLE_EINVAL;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                if (((x + y + z) & 1) != colour) continue;
+                const uint8_t nb[6] = {
+                    spins[cube_at(L, (x + 1) % L, y, z)], spins[cube_at(L, (x + L - 1) % L, y, z)],
+                    spins[cube_at(L, x, (y + 1) % L, z)], spins[cube_at(L, x, (y + L - 1) % L, z)],
+                    spins[cube_at(L, x, y, (z + 1) % L)], spins[cube_at(L, x, y, (z + L - 1) % L)],
+                };
+                uint32_t w[4];
+                cube_words(L, x, y, z, seed, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)colour + 8u, w);
+                const int b = (x / 2) & 1;
+                const size_t i = cube_at(L, x, y, z);
+                spins[i] = (uint8_t)oracle3d_site_update(q, spins[i], nb, w[2 * b], w[2 * b + 1], thr);
+            }
+    return ORACLE_OK;
+}
+
+/* e_sat over the 3N bonds (each counted once through +x, +y, +z) and N_v. */
+int oracle3d_observables(int L, int q, const uint8_t *spins, int64_t *e_sat, int64_t *hist)
+{
+    if (!valid_cube(L, q) || spins == NULL) return ORACLE_EINVAL;
+    int64_t bonds = 0;
+    if (hist) memset(hist, 0, sizeof(int64_t) * (size_t)q);
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const uint8_t s = spins[cube_at(L, x, y, z)];
+                bonds += s == spins[cube_at(L, (x + 1) % L, y, z)];
+                bonds += s == spins[cube_at(L, x, (y + 1) % L, z)];
+                bonds += s == spins[cube_at(L, x, y, (z + 1) % L)];
+                if (hist) {
+                    if (s >= q) return ORACLE_EINVAL;
+                    ++hist[s];
+                }
+            }
+    if (e_sat) *e_sat = bonds;
+    return ORACLE_OK;
+}
+
+int oracle3d_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, const uint32_t thr[6],
+                    uint8_t *spins, int64_t *records)
+{
+    if (!valid_cube(L, q) || spins == NULL || thr == NULL || nsweeps < 0) return ORACLE_EINVAL;
+    for (int64_t j = 0; j < nsweeps; ++j) {
+        const uint64_t t = t0 + (uint64_t)j;
+        int rc = oracle3d_half_sweep(L, q, seed, t, 0, thr, spins);
+        if (rc) return rc;
+        rc = oracle3d_half_sweep(L, q, seed, t, 1, thr, spins);
+        if (rc) return rc;
+        if (records) {
+            int64_t *rec = records + (size_t)j * (size_t)(1 + q);
+            rc = oracle3d_observables(L, q, spins, &rec[0], &rec[1]);
+            if (rc) return rc;
+        }
+    }
+    return ORACLE_OK;
+}
