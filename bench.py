@@ -513,13 +513,58 @@ def run_heatbath(args):
             "event_ms": ev0.elapsed_time(ev1), "cpu_baseline": cpu}
 
 
+def run_cubic(args):
+    """Simple-cubic lattice (Sec. 7's three-dimensional variant): q = 3,
+    L = 1024 (2^30 uint8 spins, the default workload's site count), beta =
+    0.5505, random start, seed 1, --steps sweeps (default 200) with records
+    every sweep; the oracle's cubic chain on an L = 128 sample as the CPU
+    baseline."""
+    import paper_1101_0876_amd as potts
+
+    L, q, seed, beta = 1024, 3, 1, 0.5505
+    N = L ** 3
+    steps = args.steps if args.steps != 2000 else 200
+    warm = max(1, args.warmup)
+    with potts.Cube(L, q, seed, potts.RANDOM) as c:
+        c.sweep(beta, warm)
+        c.records(c.t - 1, 1)  # synchronizes
+        t0 = time.perf_counter()
+        c.sweep(beta, steps)
+        rec = c.records(c.t - 1, 1)
+        wall = time.perf_counter() - t0
+        assert int(rec[0, 1:].sum()) == N, "population sum != N"
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        Ls = 128
+        spins = oracle.init3d(Ls, q, seed, oracle.RANDOM)
+        thr = oracle.threshold_table6(beta)
+        n, t1 = 0, time.perf_counter()
+        while True:
+            oracle.sweeps3d(spins, q, seed, n, 1, thr, record=True)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= args.cpu_seconds or n >= 64:
+                break
+        cpu = {"value": el * 1e9 / (n * Ls ** 3), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+               "sample": f"L={Ls}^3 q={q} cubic, random start, {n} sweeps with records, 1 thread"}
+    ns = wall * 1e9 / (steps * N)
+    return {"metric": "ns per spin flip", "value": ns, "unit": "ns", "n_gpus": 1, "steps": steps, "warmup": warm,
+            "ms_per_step": wall * 1e3 / steps, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "simple-cubic sweeps", "q": q, "L": L, "beta": beta, "seed": seed,
+                       "start": "random", "records": "every sweep"},
+            "spin_bytes_GBs": ALGO_BYTES_PER_SITE / ns, "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
-                                                     "metastability", "heatbath"])
+                                                     "metastability", "heatbath", "cubic"])
     ap.add_argument("--kernel", type=int, default=0,
                     help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split")
     ap.add_argument("--ramp-sweeps", type=int, default=100)
@@ -549,6 +594,9 @@ def main():
         return
     if args.workload == "heatbath":
         print(json.dumps(run_heatbath(args)), flush=True)
+        return
+    if args.workload == "cubic":
+        print(json.dumps(run_cubic(args)), flush=True)
         return
     if args.workload == "metastability":
         print(json.dumps(run_metastability(args)), flush=True)

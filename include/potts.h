@@ -379,6 +379,63 @@ int potts_server_stop(potts_server *srv);
 /* Releases the state (synchronizes its stream first).  NULL is a no-op. */
 void potts_free(potts_state *s);
 
+/* ---- Simple-cubic lattice (Sec. 7: the checkerboard update in three
+ * dimensions, where the lattice still splits into two independent
+ * sub-lattices).  The 2D contract lifted to L x L x L sites:
+ *   - site (x, y, z) at byte (z L + y) L + x, periodic in all three axes;
+ *   - colour (x + y + z) & 1, colour 0 first; six neighbours, so the energy
+ *     change of a proposal is dE = n(s) - n(k) in -6..6 and the table holds
+ *     thr[d-1] = min(floor(exp(-beta d) 2^32), 2^32 - 1) for d = 1..6 (Eq. 1
+ *     with the Metropolis rule of Sec. 3);
+ *   - one Philox4x32-10 block per 4-byte row chunk, sweep t and colour c, with
+ *     counter (t_lo, ((z L + y) L + x) / 4, t_hi, c + 8) and key (seed_lo,
+ *     seed_hi); site x of the chunk takes (w[2b], w[2b+1]), b = (x/2) & 1, as
+ *     proposal and acceptance words;
+ *   - random start: counter (0, chunk, 0, 10), value floor(w[x & 3] q / 2^32);
+ *   - records {e_sat, hist[0..q)} per sweep, e_sat over the 3 L^3 bonds.
+ * The state owns its lattice (L^3 bytes), a 4096-slot record ring and a stream.
+ * Every call returns 0 or a negative POTTS_E* code (potts_last_error()). */
+typedef struct potts3d_state potts3d_state;
+
+/* Creates an L^3 lattice on the current device.  Errors: EINVAL (L < 4,
+ * L % 4 != 0, q outside 2..256, bad start, out NULL), ERANGE (L^3/4 >= 2^32),
+ * ENOMEM, EDEVICE.  On error *out is NULL. */
+int potts3d_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts3d_state **out);
+
+/* The six-entry Metropolis table above.  Errors: EINVAL (beta < 0, not finite,
+ * thr NULL). */
+int potts3d_threshold_table(double beta, uint32_t thr[6]);
+
+/* nsweeps full sweeps (colour 0 then colour 1) at beta, each writing its
+ * record; asynchronous on the state's stream.  Errors: EINVAL, ERANGE (sweep
+ * counter overflow), EDEVICE. */
+int potts3d_sweep(potts3d_state *s, double beta, int64_t nsweeps);
+
+/* As potts3d_sweep with a caller-supplied table (host memory, 6 entries). */
+int potts3d_sweep_thr(potts3d_state *s, const uint32_t thr[6], int64_t nsweeps);
+
+/* Records of sweeps t0 .. t0+n-1 into out[n*(1+q)] (synchronizes).  Errors:
+ * ERANGE if one of them is not (or no longer) in the ring. */
+int potts3d_records(potts3d_state *s, int64_t t0, int64_t n, int64_t *out);
+
+/* Measures the current lattice with a kernel of its own (independent of the
+ * records; synchronizes). */
+int potts3d_observables(potts3d_state *s, potts_obs *out);
+
+/* e, C, V_L, m, chi of the window t0 .. t0+n-1 with N = L^3 (the same
+ * definitions and exact moments as potts_stats).  Errors: EINVAL (n outside
+ * 1..2^24, bad beta), ERANGE. */
+int potts3d_stats(potts3d_state *s, int64_t t0, int64_t n, double beta, potts_summary *out);
+
+/* Copies the lattice (L^3 bytes, layout above) to host memory (synchronizes). */
+int potts3d_get_spins(potts3d_state *s, uint8_t *host_out);
+
+/* Sweeps done so far, or -1 for NULL. */
+int64_t potts3d_time(const potts3d_state *s);
+
+/* Releases the state (synchronizes first).  NULL is a no-op. */
+void potts3d_free(potts3d_state *s);
+
 const char *potts_strerror(int code);
 const char *potts_last_error(void);
 

@@ -77,6 +77,9 @@ def _load():
     lib.oracle3d_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                     u32p, u8p, i64p]
     lib.oracle3d_sweeps.restype = ctypes.c_int
+    lib.oracle3d_window.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64,
+                                    u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p]
+    lib.oracle3d_window.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -226,6 +229,16 @@ def sweeps3d(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, record:
     _check(_load().oracle3d_sweeps(spins.shape[0], q, seed, t0, n, _ptr(t_arr, ctypes.c_uint32),
                                    _ptr(spins, ctypes.c_uint8), rptr), "sweeps3d")
     return rec
+
+
+def window3d(L: int, q: int, seed: int, start: int, nsweeps: int, thr, x0: int, y0: int, z0: int, d: int):
+    """d^3 window ([z, y, x], corner (x0, y0, z0), periodic) of the cubic chain after
+    nsweeps sweeps; only sites at distance >= 2*nsweeps from every face are exact."""
+    out = np.zeros(d * d * d, dtype=np.uint8)
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint32)
+    _check(_load().oracle3d_window(L, q, seed, start, nsweeps, _ptr(t_arr, ctypes.c_uint32), x0, y0, z0, d,
+                                   _ptr(out, ctypes.c_uint8)), "window3d")
+    return out.reshape(d, d, d)
 
 
 def run(L: int, q: int, seed: int, start: int, beta: float, n: int):

@@ -516,3 +516,55 @@ int oracle3d_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, c
     }
     return ORACLE_OK;
 }
+
+/* The cubic chain restricted to a d x d x d window with corner (x0, y0, z0)
+ * (coordinates wrap), from the initial condition at t = 0, with the random
+ * words of the full lattice (the 2D window above, one dimension up): after
+ * nsweeps sweeps only sites at least 2*nsweeps from every face of the window
+ * equal the full-lattice chain. */
+int oracle3d_window(int L, int q, uint64_t seed, int start, int64_t nsweeps, const uint32_t thr[6], int x0,
+                    int y0, int z0, int d, uint8_t *out)
+{
+    if (!valid_cube(L, q) || out == NULL || thr == NULL || d < 1 || d > L || x0 < 0 || y0 < 0 || z0 < 0 ||
+        x0 >= L || y0 >= L || z0 >= L || nsweeps < 0 || (start != 0 && start != 1))
+        return ORACLE_EINVAL;
+    for (int k = 0; k < d; ++k)
+        for (int j = 0; j < d; ++j)
+            for (int i = 0; i < d; ++i) {
+                const int x = (x0 + i) % L, y = (y0 + j) % L, z = (z0 + k) % L;
+                uint8_t value = 0;
+                if (start == 1) {
+                    uint32_t w[4];
+                    cube_words(L, x, y, z, seed, 0u, 0u, 10u, w);
+                    value = (uint8_t)word_to_value(w[x & 3], q);
+                }
+                out[cube_at(d, i, j, k)] = value;
+            }
+    for (int64_t n = 0; n < nsweeps; ++n) {
+        const uint64_t t = (uint64_t)n;
+        for (int colour = 0; colour < 2; ++colour)
+            for (int k = 0; k < d; ++k)
+                for (int j = 0; j < d; ++j)
+                    for (int i = 0; i < d; ++i) {
+                        const int x = (x0 + i) % L, y = (y0 + j) % L, z = (z0 + k) % L;
+                        if (((x + y + z) & 1) != colour) continue;
+                        /* neighbours outside the window read as the site itself
+                         * (those faces are discarded) */
+                        const uint8_t self = out[cube_at(d, i, j, k)];
+                        const uint8_t nb[6] = {
+                            i + 1 < d ? out[cube_at(d, i + 1, j, k)] : self,
+                            i > 0 ? out[cube_at(d, i - 1, j, k)] : self,
+                            j + 1 < d ? out[cube_at(d, i, j + 1, k)] : self,
+                            j > 0 ? out[cube_at(d, i, j - 1, k)] : self,
+                            k + 1 < d ? out[cube_at(d, i, j, k + 1)] : self,
+                            k > 0 ? out[cube_at(d, i, j, k - 1)] : self,
+                        };
+                        uint32_t w[4];
+                        cube_words(L, x, y, z, seed, (uint32_t)t, (uint32_t)(t >> 32), (uint32_t)colour + 8u, w);
+                        const int b = (x / 2) & 1;
+                        out[cube_at(d, i, j, k)] =
+                            (uint8_t)oracle3d_site_update(q, self, nb, w[2 * b], w[2 * b + 1], thr);
+                    }
+    }
+    return ORACLE_OK;
+}

@@ -19,8 +19,8 @@ from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, Pott
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
-           "ORDERED", "RANDOM", "load"]
+__all__ = ["Lattice", "Cube", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
+           "threshold_table6", "ORDERED", "RANDOM", "load"]
 
 
 def threshold_table(beta: float) -> np.ndarray:
@@ -163,6 +163,82 @@ class Lattice:
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
             self._lib.potts_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def threshold_table6(beta: float) -> np.ndarray:
+    """thr[d-1] = min(floor(exp(-beta d) 2^32), 2^32-1), d = 1..6: the table of
+    the simple-cubic lattice (host FP64)."""
+    thr = np.zeros(6, dtype=np.uint32)
+    check(load().potts3d_threshold_table(float(beta), thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+    return thr
+
+
+class Cube:
+    """One L x L x L simple-cubic Potts lattice on the GPU (a potts3d_state):
+    the checkerboard Metropolis sweep with colour (x + y + z) & 1 and six
+    neighbours, records and statistics as for Lattice with N = L^3."""
+
+    def __init__(self, L: int, q: int, seed: int = 1, start: int = RANDOM):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        check(self._lib.potts3d_init(int(L), int(q), int(seed), int(start), ctypes.byref(self._h)))
+        self.L = int(L)
+        self.q = int(q)
+        self.seed = int(seed)
+
+    def sweep(self, beta: float, nsweeps: int = 1) -> None:
+        check(self._lib.potts3d_sweep(self._h, float(beta), int(nsweeps)))
+
+    def sweep_thr(self, thr, nsweeps: int = 1) -> None:
+        t = np.ascontiguousarray(thr, dtype=np.uint32)
+        if t.size != 6:
+            raise ValueError("the cubic table has six entries")
+        check(self._lib.potts3d_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                          int(nsweeps)))
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.potts3d_time(self._h))
+
+    def observables(self) -> dict:
+        o = PottsObs()
+        check(self._lib.potts3d_observables(self._h, ctypes.byref(o)))
+        return {"t": o.t, "e_sat": o.e_sat, "nmax": o.nmax,
+                "hist": np.array(o.hist[: self.q], dtype=np.int64)}
+
+    def records(self, t0: int, n: int) -> np.ndarray:
+        out = np.zeros((n, 1 + self.q), dtype=np.int64)
+        check(self._lib.potts3d_records(self._h, int(t0), int(n),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return out
+
+    def stats(self, t0: int, n: int, beta: float) -> dict:
+        s = PottsSummary()
+        check(self._lib.potts3d_stats(self._h, int(t0), int(n), float(beta), ctypes.byref(s)))
+        return {"n": s.n, "e": s.e, "C": s.C, "V_L": s.V_L, "m": s.m, "chi": s.chi}
+
+    def spins(self) -> np.ndarray:
+        """The lattice as an array indexed [z, y, x]."""
+        out = np.zeros(self.L ** 3, dtype=np.uint8)
+        check(self._lib.potts3d_get_spins(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.reshape(self.L, self.L, self.L)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.potts3d_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

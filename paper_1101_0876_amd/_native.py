@@ -165,6 +165,18 @@ SIGNATURES = [
     ("potts_server_iterations", ctypes.c_int64, [_VP]),
     ("potts_server_stop", ctypes.c_int, [_VP]),
     ("potts_free", None, [_VP]),
+    ("potts3d_init", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int,
+                                    ctypes.POINTER(_VP)]),
+    ("potts3d_threshold_table", ctypes.c_int, [ctypes.c_double, _U32P]),
+    ("potts3d_sweep", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_int64]),
+    ("potts3d_sweep_thr", ctypes.c_int, [_VP, _U32P, ctypes.c_int64]),
+    ("potts3d_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    ("potts3d_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
+    ("potts3d_stats", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                                     ctypes.POINTER(PottsSummary)]),
+    ("potts3d_get_spins", ctypes.c_int, [_VP, _U8P]),
+    ("potts3d_time", ctypes.c_int64, [_VP]),
+    ("potts3d_free", None, [_VP]),
     ("potts_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("potts_last_error", ctypes.c_char_p, []),
 ]

@@ -20,7 +20,7 @@ def declared_functions():
     for path in HEADERS:
         text = open(path).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(potts_[a-z_0-9]+)\s*\(", text, flags=re.M)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(potts(?:3d)?_[a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -33,7 +33,8 @@ def lib():
 
 def test_header_declares_the_core_calls():
     names = declared_functions()
-    for core in ("potts_init", "potts_sweep", "potts_observables", "potts_free", "potts_strerror"):
+    for core in ("potts_init", "potts_sweep", "potts_observables", "potts_free", "potts_strerror",
+                 "potts3d_init", "potts3d_sweep", "potts3d_free"):
         assert core in names
 
 
@@ -97,6 +98,35 @@ def test_slab_half_sweep_rejects_bad_arguments(lib, bad):
 def test_reweight_rejects_null_without_device(lib):
     betas = (ctypes.c_double * 1)(1.0)
     assert lib.potts_reweight(None, 0, 1, 1.0, betas, 1, None) == -1
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.2, 0.4433, 0.5505, 1.0, 3.0, 40.0])
+def test_cubic_threshold_table_matches_oracle(oracle_lib, beta):
+    import paper_1101_0876_amd as p
+
+    assert np.array_equal(p.threshold_table6(beta), oracle_lib.threshold_table6(beta))
+
+
+@pytest.mark.parametrize("L,q,start", [(0, 3, 1), (2, 3, 1), (6, 3, 1), (8, 1, 1), (8, 257, 1), (8, 3, 5),
+                                       (2584, 3, 1)])
+def test_cubic_init_rejects_bad_shapes_without_device(lib, L, q, start):
+    h = ctypes.c_void_p()
+    rc = lib.potts3d_init(L, q, 1, start, ctypes.byref(h))
+    assert rc in (-1, -4) and not h.value
+    assert lib.potts_last_error()
+
+
+def test_cubic_null_state(lib):
+    thr = (ctypes.c_uint32 * 6)()
+    assert lib.potts3d_threshold_table(-1.0, thr) == -1
+    assert lib.potts3d_threshold_table(float("inf"), thr) == -1
+    assert lib.potts3d_threshold_table(0.5, None) == -1
+    assert lib.potts3d_sweep(None, 1.0, 1) == -1
+    assert lib.potts3d_sweep_thr(None, thr, 1) == -1
+    assert lib.potts3d_observables(None, None) == -1
+    assert lib.potts3d_records(None, 0, 1, None) == -1
+    assert lib.potts3d_time(None) == -1
+    lib.potts3d_free(None)
 
 
 def test_strerror(lib):

@@ -1,0 +1,174 @@
+"""The simple-cubic lattice through the C ABI (potts3d_*) against the oracle's
+cubic chain: initial conditions, spins and every per-sweep record bit-exact,
+the derived statistics to the oracle's exact-rational values, windows of the
+largest lattice the library takes, and the argument checks."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+# transition of the 3D three-state model, used as a representative coupling
+BETA3 = 0.5505
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def potts():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_0876_amd as p
+
+    p.load()
+    return p
+
+
+@pytest.mark.parametrize("L,q,seed", [(4, 2, 1), (12, 5, 2), (20, 256, 3), (64, 9, 4)])
+def test_initial_conditions(potts, oracle_lib, L, q, seed):
+    for start in (0, 1):
+        with potts.Cube(L, q, seed, start) as c:
+            assert c.t == 0
+            assert np.array_equal(c.spins(), oracle_lib.init3d(L, q, seed, start))
+
+
+CASES = [
+    # L, q, seed, start, beta, sweeps
+    (4, 2, 1, 1, 0.7, 9),            # one row chunk per row, 16 chunks
+    (8, 3, 2, 1, BETA3, 7),
+    (12, 5, 3, 0, 0.9, 6),           # 432 chunks: a ragged last workgroup
+    (20, 9, 4, 1, 1.2, 5),
+    (32, 256, 5, 1, 2.0, 4),
+    (48, 200, 6, 0, 9.0, 4),         # zero thresholds: only dE <= 0 moves
+    (64, 6, 7, 1, 0.0, 3),           # beta = 0: every proposal accepted
+    (100, 3, 8, 1, BETA3, 4),
+    (128, 2, 9, 0, 0.4433, 3),       # near the 3D Ising point (beta_Potts = 2 beta_Ising)
+    (256, 6, 10, 1, 0.8, 2),         # 16.7 M sites, grid-stride loop
+]
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n", CASES)
+def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
+    _say(f"cubic L={L} q={q} beta={beta} n={n}")
+    s = oracle_lib.init3d(L, q, seed, start)
+    rec = oracle_lib.sweeps3d(s, q, seed, 0, n, oracle_lib.threshold_table6(beta))
+    with potts.Cube(L, q, seed, start) as c:
+        c.sweep(beta, n)
+        assert c.t == n
+        assert np.array_equal(c.records(0, n), rec)
+        assert np.array_equal(c.spins(), s)
+        obs = c.observables()
+        e, hist = oracle_lib.observables3d(s, q)
+        assert obs["e_sat"] == e and np.array_equal(obs["hist"], hist) and obs["t"] == n
+
+
+def test_split_calls_and_tables(potts, oracle_lib):
+    """Sweeps split over calls, a table change between them and a caller table
+    continue the same chain (t carries the counter)."""
+    L, q, seed = 24, 4, 31
+    t1, t2 = oracle_lib.threshold_table6(0.5), oracle_lib.threshold_table6(0.75)
+    s = oracle_lib.init3d(L, q, seed, 1)
+    r1 = oracle_lib.sweeps3d(s, q, seed, 0, 3, t1)
+    r2 = oracle_lib.sweeps3d(s, q, seed, 3, 2, t2)
+    r3 = oracle_lib.sweeps3d(s, q, seed, 5, 4, t1)
+    with potts.Cube(L, q, seed, 1) as c:
+        assert np.array_equal(potts.threshold_table6(0.5), t1)
+        c.sweep(0.5, 1)
+        c.sweep(0.5, 2)
+        c.sweep(0.75, 2)
+        c.sweep_thr(t1, 4)
+        assert c.t == 9
+        assert np.array_equal(c.records(0, 9), np.concatenate([r1, r2, r3]))
+        assert np.array_equal(c.spins(), s)
+
+
+def test_stats_match_oracle(potts, oracle_lib):
+    from oracle import stats as ostats
+
+    L, q, seed, beta, n = 32, 3, 5, BETA3, 60
+    s = oracle_lib.init3d(L, q, seed, 1)
+    rec = oracle_lib.sweeps3d(s, q, seed, 0, n, oracle_lib.threshold_table6(beta))
+    want = ostats.derived(rec[20:, 0], rec[20:, 1:].max(axis=1), L**3, q, beta)
+    with potts.Cube(L, q, seed, 1) as c:
+        c.sweep(beta, n)
+        got = c.stats(20, n - 20, beta)
+    assert got["n"] == n - 20
+    for k in ("e", "C", "V_L", "m", "chi"):
+        assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-15), k
+
+
+def test_record_ring_window(potts):
+    """4096 slots, one of them the next sweep's (cleared ahead): the last 4095
+    records stay readable, older and future ones are refused."""
+    with potts.Cube(8, 3, 1, 1) as c:
+        c.sweep(1.0, 4100)
+        with pytest.raises(potts.PottsError):
+            c.records(4, 1)          # overwritten
+        with pytest.raises(potts.PottsError):
+            c.records(4099, 2)       # not yet run
+        r = c.records(4100 - 4095, 4095)
+        assert np.all(r[:, 1:].sum(axis=1) == 512)
+        assert np.array_equal(r[-1], np.concatenate([[c.observables()["e_sat"]], c.observables()["hist"]]))
+
+
+# the largest lattice: L^3 / 4 chunks just below 2^32 (17.2 GB of spins)
+L_MAX = 2580
+
+
+def test_maximum_cube_frozen_ground_state(potts):
+    """q = 256 at beta = 9 from the ordered start: every proposal costs dE = 6,
+    whose threshold floor(exp(-54) 2^32) is 0, so nothing moves: each record is
+    e_sat = 3N, N_0 = N, and the window statistics are e = -3, C = 0,
+    V_L = 2/3, m = 1, chi = 0, through the exact moments at their largest."""
+    L, q, n = L_MAX, 256, 2
+    _say(f"maximum cube L={L} q={q} ordered beta=9")
+    N = L**3
+    with potts.Cube(L, q, 5, 0) as c:
+        c.sweep(9.0, n)
+        rec = c.records(0, n)
+        s = c.stats(0, n, 9.0)
+    assert np.all(rec[:, 0] == 3 * N) and np.all(rec[:, 1] == N) and not rec[:, 2:].any()
+    assert s["e"] == -3.0 and s["C"] == 0.0 and s["m"] == 1.0 and s["chi"] == 0.0
+    assert s["V_L"] == pytest.approx(2.0 / 3.0, rel=1e-15)
+
+
+def test_maximum_cube_sampled_windows(potts, oracle_lib):
+    """A random start and one sweep on the largest cube: windows at the origin,
+    across every periodic face and at the last bytes against the oracle's
+    window restriction; the record against the observables kernel."""
+    L, q, seed, beta, n = L_MAX, 7, 21, BETA3, 1
+    _say(f"maximum cube L={L} q={q} random windows")
+    thr = oracle_lib.threshold_table6(beta)
+    with potts.Cube(L, q, seed, 1) as c:
+        c.sweep(beta, n)
+        rec = c.records(0, n)
+        obs = c.observables()
+        spins = c.spins()
+    assert int(rec[0, 1:].sum()) == L**3
+    assert rec[0, 0] == obs["e_sat"] and np.array_equal(rec[0, 1:], obs["hist"])
+    d, r = 12, 2 * n
+    for (x0, y0, z0) in [(0, 0, 0), (L - 6, L - 6, L - 6), (L - d, L - d, L - d), (1000, L - 5, 3),
+                         (L - 7, 1500, L - 9), (2047, 2048, 2049)]:
+        win = oracle_lib.window3d(L, q, seed, 1, n, thr, x0, y0, z0, d)
+        idx = [(c0 + np.arange(r, d - r)) % L for c0 in (z0, y0, x0)]
+        assert np.array_equal(win[r:d - r, r:d - r, r:d - r], spins[np.ix_(*idx)]), (x0, y0, z0)
+
+
+def test_rejects_bad_arguments(potts):
+    for L, q in [(6, 3), (2, 3), (0, 3), (8, 1), (8, 257), (2584, 3)]:
+        with pytest.raises(potts.PottsError):
+            potts.Cube(L, q, 1, 1)
+    with potts.Cube(8, 3, 1, 1) as c:
+        with pytest.raises(potts.PottsError):
+            c.sweep(-1.0, 1)
+        with pytest.raises(potts.PottsError):
+            c.sweep(float("nan"), 1)
+        with pytest.raises(potts.PottsError):
+            c.sweep(1.0, -1)
+        with pytest.raises(potts.PottsError):
+            c.stats(0, 0, 1.0)
+        c.sweep(1.0, 0)
+        assert c.t == 0

@@ -154,3 +154,18 @@ def test_quench_never_loses_bonds(oracle_lib):
     rec = oracle_lib.sweeps3d(s, q, 4, 0, 30, oracle_lib.threshold_table6(40.0))
     assert np.all(np.diff(rec[:, 0]) >= 0)
     assert np.all(rec[:, 1:].sum(axis=1) == L**3)
+
+
+@pytest.mark.parametrize("start", [0, 1])
+def test_window_matches_full_cube(oracle_lib, start):
+    """The window restriction reproduces the full chain on its exact interior,
+    including windows that wrap around every axis."""
+    L, q, seed, n, beta = 16, 5, 17, 2, 0.6
+    thr = oracle_lib.threshold_table6(beta)
+    full = oracle_lib.init3d(L, q, seed, start)
+    oracle_lib.sweeps3d(full, q, seed, 0, n, thr, record=False)
+    r = 2 * n
+    for (x0, y0, z0, d) in [(0, 0, 0, 12), (11, 13, 9, 12), (3, 0, 14, 16)]:
+        win = oracle_lib.window3d(L, q, seed, start, n, thr, x0, y0, z0, d)
+        idx = [(c0 + np.arange(r, d - r)) % L for c0 in (z0, y0, x0)]
+        assert np.array_equal(win[r:d - r, r:d - r, r:d - r], full[np.ix_(*idx)])
