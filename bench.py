@@ -526,6 +526,7 @@ def run_cubic(args):
     steps = args.steps if args.steps != 2000 else 200
     warm = max(1, args.warmup)
     with potts.Cube(L, q, seed, potts.RANDOM) as c:
+        c.tune(args.kernel if args.kernel in (0, 1, 2) else 0)
         c.sweep(beta, warm)
         c.records(c.t - 1, 1)  # synchronizes
         t0 = time.perf_counter()
@@ -554,7 +555,8 @@ def run_cubic(args):
             "ms_per_step": wall * 1e3 / steps, "higher_is_better": False, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "simple-cubic sweeps", "q": q, "L": L, "beta": beta, "seed": seed,
-                       "start": "random", "records": "every sweep"},
+                       "start": "random", "records": "every sweep",
+                       "kernel": {0: "automatic", 1: "colour-split", 2: "chunk"}.get(args.kernel, "automatic")},
             "spin_bytes_GBs": ALGO_BYTES_PER_SITE / ns, "cpu_baseline": cpu}
 
 
@@ -566,7 +568,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
                                                      "metastability", "heatbath", "cubic"])
     ap.add_argument("--kernel", type=int, default=0,
-                    help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split")
+                    help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split; "
+                         "cubic: 0 automatic (colour-split), 1 colour-split, 2 chunk")
     ap.add_argument("--ramp-sweeps", type=int, default=100)
     ap.add_argument("--meta-sweeps", type=int, default=1000)
     ap.add_argument("--batch-jobs", type=int, default=1024)

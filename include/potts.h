@@ -393,7 +393,8 @@ void potts_free(potts_state *s);
  *     proposal and acceptance words;
  *   - random start: counter (0, chunk, 0, 10), value floor(w[x & 3] q / 2^32);
  *   - records {e_sat, hist[0..q)} per sweep, e_sat over the 3 L^3 bonds.
- * The state owns its lattice (L^3 bytes), a 4096-slot record ring and a stream.
+ * The state owns its lattice (L^3 bytes, plus a colour-split copy of the same
+ * size when that kernel runs), a 4096-slot record ring and a stream.
  * Every call returns 0 or a negative POTTS_E* code (potts_last_error()). */
 typedef struct potts3d_state potts3d_state;
 
@@ -429,6 +430,15 @@ int potts3d_stats(potts3d_state *s, int64_t t0, int64_t n, double beta, potts_su
 
 /* Copies the lattice (L^3 bytes, layout above) to host memory (synchronizes). */
 int potts3d_get_spins(potts3d_state *s, uint8_t *host_out);
+
+/* Kernel choice for later sweeps; every choice gives identical spins and
+ * records.  kernel 0: automatic (colour-split when L % 32 == 0, else chunk);
+ * 1: colour-split (the state keeps a second L^3-byte copy of the cube split
+ * into its two colour planes, allocated on first use, and rebuilds the
+ * row-major cube only when it is read); 2: chunk (row-major, any L).  rows:
+ * rows of y walked by one colour-split work item, 0 automatic, else an even
+ * divisor of L.  Errors: EINVAL (kernel 1 with L % 32 != 0, bad values). */
+int potts3d_tune(potts3d_state *s, int32_t kernel, int32_t rows);
 
 /* Sweeps done so far, or -1 for NULL. */
 int64_t potts3d_time(const potts3d_state *s);

@@ -209,6 +209,10 @@ class Cube:
         check(self._lib.potts3d_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                           int(nsweeps)))
 
+    def tune(self, kernel: int = 0, rows: int = 0) -> None:
+        """0 automatic, 1 colour-split (L % 32 == 0), 2 chunk; results are identical."""
+        check(self._lib.potts3d_tune(self._h, int(kernel), int(rows)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts3d_time(self._h))

@@ -6,10 +6,15 @@
 // t_hi, colour + 8), random start on counter word 3 = 10.  Records, rings and
 // statistics are those of the 2D library with N = L^3 and 3N bonds.
 //
-// Kernel: one thread per 4-byte row chunk (two active sites, one Philox
-// block); the six neighbour dwords are the row's own (shifted by one byte for
-// x-1 and x+1), the same dword of rows y-1 and y+1, and of planes z-1 and
-// z+1.  The colour-1 pass reduces the sweep's energy and populations.
+// Two half-sweep kernels give identical results:
+//   - colour-split (cubic_packed.hip, L % 32 == 0): the state keeps a copy of
+//     the cube split into its two colour planes and sweeps there; the
+//     row-major copy is rebuilt only when it is read;
+//   - chunk (here, any L): one thread per 4-byte row chunk (two active sites,
+//     one Philox block) on the row-major cube; the six neighbour dwords are
+//     the row's own (shifted by one byte for x-1 and x+1), the same dword of
+//     rows y-1 and y+1, and of planes z-1 and z+1.
+// The colour-1 pass reduces the sweep's energy; populations come from both.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -20,6 +25,7 @@
 #include <vector>
 
 #include "../../include/potts.h"
+#include "cubic.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -27,7 +33,12 @@ struct potts3d_state {
   int32_t L = 0, q = 0;
   uint64_t seed = 0;
   int64_t t = 0;
-  uint8_t *spins = nullptr;
+  uint8_t *spins = nullptr;   // row-major cube
+  uint8_t *planes = nullptr;  // colour-split copy (L % 32 == 0)
+  bool spins_valid = true;    // spins holds the current configuration
+  bool planes_valid = false;  // planes holds it
+  int32_t kernel = 0;         // 0 automatic, 1 colour-split, 2 chunk
+  int32_t rows = 0;           // colour-split walk length (0 automatic)
   hipStream_t stream = nullptr;
   unsigned long long *records = nullptr;  // ring of rec_cap slots of 1+q
   int64_t rec_cap = 0;
@@ -222,11 +233,46 @@ void release(potts3d_state *s) {
   if (!s) return;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->spins) (void)hipFree(s->spins);
+  if (s->planes) (void)hipFree(s->planes);
   if (s->records) (void)hipFree(s->records);
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->stats_out) (void)hipFree(s->stats_out);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
+}
+
+bool packed_ok(const potts3d_state *s) { return s->L % 32 == 0; }
+
+bool use_packed(const potts3d_state *s) { return s->kernel == 1 || (s->kernel == 0 && packed_ok(s)); }
+
+// longest walk that still leaves >= 2048 workgroups to spread over the chip
+uint32_t packed_rows(const potts3d_state *s) {
+  if (s->rows) return (uint32_t)s->rows;
+  const uint64_t L = (uint64_t)s->L, ipr = L / 32;
+  for (uint32_t R : {32u, 16u, 8u, 4u})
+    if (ipr * L * (L / R) >= 2048ull * kBlock) return R;
+  return 2;
+}
+
+// make the row-major cube current
+int sync_spins(potts3d_state *s) {
+  if (s->spins_valid) return POTTS_OK;
+  HIP_TRY3(potts::cube::launch_unpack(s->planes, s->spins, (uint32_t)s->L, s->stream));
+  s->spins_valid = true;
+  return POTTS_OK;
+}
+
+// make the colour-split copy current (allocated on first use)
+int sync_planes(potts3d_state *s) {
+  if (s->planes_valid) return POTTS_OK;
+  if (!s->planes && hipMalloc(&s->planes, (size_t)s->L * s->L * s->L) != hipSuccess) {
+    (void)hipGetLastError();
+    s->planes = nullptr;
+    return fail(POTTS_ENOMEM, "device allocation of the colour planes failed");
+  }
+  HIP_TRY3(potts::cube::launch_pack(s->spins, s->planes, (uint32_t)s->L, s->stream));
+  s->planes_valid = true;
+  return POTTS_OK;
 }
 
 int run(potts3d_state *s, const uint32_t thr[6], int64_t nsweeps) {
@@ -235,28 +281,53 @@ int run(potts3d_state *s, const uint32_t thr[6], int64_t nsweeps) {
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
   const int64_t rl = s->q + 1;
-  CubeSweep p{};
-  p.c = cube_of(s);
-  for (int i = 0; i < 6; ++i) p.thr[i] = thr[i];
-  const unsigned grid = grid_of(p.c.nchunks, 4096);
-  hipError_t e = hipSuccess;
+  const bool packed = use_packed(s);
+  const int rc = packed ? sync_planes(s) : sync_spins(s);
+  if (rc) return rc;
   // the first sweep's slot; each colour-1 launch clears the next one
-  {
-    const int64_t slot = s->t & (s->rec_cap - 1);
-    e = hipMemsetAsync(s->records + slot * rl, 0, (size_t)rl * 8, s->stream);
-    if (e != hipSuccess) return fail(POTTS_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
-  }
-  for (int64_t k = 0; k < nsweeps; ++k) {
-    const int64_t t = s->t + k;
-    p.t_lo = (uint32_t)(uint64_t)t;
-    p.t_hi = (uint32_t)((uint64_t)t >> 32);
-    p.rec = s->records + (t & (s->rec_cap - 1)) * rl;
-    p.rec_clear = nullptr;
-    hipLaunchKernelGGL(cube_sweep_kernel<0>, dim3(grid), dim3(kBlock), 0, s->stream, p);
-    p.rec_clear = s->records + ((t + 1) & (s->rec_cap - 1)) * rl;
-    hipLaunchKernelGGL(cube_sweep_kernel<1>, dim3(grid), dim3(kBlock), 0, s->stream, p);
-    e = hipGetLastError();
-    if (e != hipSuccess) return fail(POTTS_EDEVICE, std::string("cube_sweep_kernel: ") + hipGetErrorString(e));
+  const int64_t slot = s->t & (s->rec_cap - 1);
+  HIP_TRY3(hipMemsetAsync(s->records + slot * rl, 0, (size_t)rl * 8, s->stream));
+  if (packed) {
+    potts::cube::CubeLaunch l{};
+    l.planes = s->planes;
+    l.plane_bytes = (uint64_t)s->L * s->L * s->L / 2;
+    l.L = (uint32_t)s->L;
+    l.q = (uint32_t)s->q;
+    l.ipr = l.L / 32;
+    l.rows = packed_rows(s);
+    l.nitems = l.ipr * l.L * (l.L / l.rows);
+    l.k0 = (uint32_t)s->seed;
+    l.k1 = (uint32_t)(s->seed >> 32);
+    for (int i = 0; i < 6; ++i) l.thr.v[i] = thr[i];
+    const unsigned grid = potts::cube::packed_grid(l);
+    for (int64_t k = 0; k < nsweeps; ++k) {
+      const int64_t t = s->t + k;
+      l.t_lo = (uint32_t)(uint64_t)t;
+      l.t_hi = (uint32_t)((uint64_t)t >> 32);
+      l.rec = s->records + (t & (s->rec_cap - 1)) * rl;
+      l.rec_clear = nullptr;
+      HIP_TRY3(potts::cube::launch_packed(l, 0, grid, s->stream));
+      l.rec_clear = s->records + ((t + 1) & (s->rec_cap - 1)) * rl;
+      HIP_TRY3(potts::cube::launch_packed(l, 1, grid, s->stream));
+    }
+    s->spins_valid = false;
+  } else {
+    CubeSweep p{};
+    p.c = cube_of(s);
+    for (int i = 0; i < 6; ++i) p.thr[i] = thr[i];
+    const unsigned grid = grid_of(p.c.nchunks, 4096);
+    for (int64_t k = 0; k < nsweeps; ++k) {
+      const int64_t t = s->t + k;
+      p.t_lo = (uint32_t)(uint64_t)t;
+      p.t_hi = (uint32_t)((uint64_t)t >> 32);
+      p.rec = s->records + (t & (s->rec_cap - 1)) * rl;
+      p.rec_clear = nullptr;
+      hipLaunchKernelGGL(cube_sweep_kernel<0>, dim3(grid), dim3(kBlock), 0, s->stream, p);
+      p.rec_clear = s->records + ((t + 1) & (s->rec_cap - 1)) * rl;
+      hipLaunchKernelGGL(cube_sweep_kernel<1>, dim3(grid), dim3(kBlock), 0, s->stream, p);
+      HIP_TRY3(hipGetLastError());
+    }
+    s->planes_valid = false;
   }
   s->t += nsweeps;
   return POTTS_OK;
@@ -358,6 +429,8 @@ int potts3d_records(potts3d_state *s, int64_t t0, int64_t n, int64_t *out) {
 int potts3d_observables(potts3d_state *s, potts_obs *out) {
   if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
   const int64_t rl = s->q + 1;
+  const int rc = sync_spins(s);
+  if (rc) return rc;
   HIP_TRY3(hipMemsetAsync(s->scratch, 0, (size_t)rl * 8, s->stream));
   const Cube c = cube_of(s);
   hipLaunchKernelGGL(cube_measure_kernel, dim3(grid_of(c.nchunks, 4096)), dim3(kBlock), 0, s->stream, c, s->scratch);
@@ -406,8 +479,21 @@ int potts3d_stats(potts3d_state *s, int64_t t0, int64_t n, double beta, potts_su
 
 int potts3d_get_spins(potts3d_state *s, uint8_t *host_out) {
   if (!s || !host_out) return fail(POTTS_EINVAL, "NULL argument");
+  const int rc = sync_spins(s);
+  if (rc) return rc;
   HIP_TRY3(hipMemcpyAsync(host_out, s->spins, (size_t)s->L * s->L * s->L, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY3(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+int potts3d_tune(potts3d_state *s, int32_t kernel, int32_t rows) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (kernel < 0 || kernel > 2) return fail(POTTS_EINVAL, "kernel must be 0 (automatic), 1 or 2");
+  if (kernel == 1 && !packed_ok(s)) return fail(POTTS_EINVAL, "the colour-split kernel needs L % 32 == 0");
+  if (rows < 0 || rows % 2 || (rows && (rows > s->L || s->L % rows)))
+    return fail(POTTS_EINVAL, "rows must be 0 or an even divisor of L");
+  s->kernel = kernel;
+  s->rows = rows;
   return POTTS_OK;
 }
 

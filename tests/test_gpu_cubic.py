@@ -52,6 +52,7 @@ CASES = [
 
 @pytest.mark.parametrize("L,q,seed,start,beta,n", CASES)
 def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
+    """Automatic kernel choice: colour-split where L % 32 == 0, chunk elsewhere."""
     _say(f"cubic L={L} q={q} beta={beta} n={n}")
     s = oracle_lib.init3d(L, q, seed, start)
     rec = oracle_lib.sweeps3d(s, q, seed, 0, n, oracle_lib.threshold_table6(beta))
@@ -63,6 +64,88 @@ def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
         obs = c.observables()
         e, hist = oracle_lib.observables3d(s, q)
         assert obs["e_sat"] == e and np.array_equal(obs["hist"], hist) and obs["t"] == n
+
+
+# colour-split kernel: every q class of its templates (<= 16, <= 64, <= 128,
+# <= 256), narrow and wide tables, each walk length, one and many workgroups
+PACKED_CASES = [
+    # L, q, seed, start, beta, sweeps, rows
+    (32, 2, 1, 1, 0.4433, 6, 0),
+    (32, 16, 2, 1, 0.9, 5, 2),
+    (64, 17, 3, 1, 1.1, 4, 4),
+    (64, 64, 4, 0, 1.3, 4, 8),
+    (96, 65, 5, 1, 1.5, 3, 32),      # L / 32 = 3 items per row
+    (64, 128, 6, 1, 2.0, 3, 16),
+    (32, 129, 7, 1, 2.5, 3, 0),
+    (64, 256, 8, 1, 3.0, 3, 0),
+    (32, 5, 9, 0, 9.0, 4, 0),        # wide table (thresholds 0), q <= 16
+    (64, 100, 10, 1, 9.0, 3, 0),     # wide, shared bins
+    (64, 200, 11, 0, 9.0, 3, 2),     # wide, q > 128
+    (64, 7, 12, 1, 0.0, 3, 0),       # beta = 0: every proposal accepted
+    (160, 3, 13, 1, BETA3, 3, 0),
+    (256, 4, 14, 1, 0.7, 2, 0),      # 16.7 M sites, many workgroups
+]
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n,rows", PACKED_CASES)
+def test_colour_split_kernel_matches_oracle(potts, oracle_lib, L, q, seed, start, beta, n, rows):
+    _say(f"cubic colour-split L={L} q={q} beta={beta} n={n} rows={rows}")
+    s = oracle_lib.init3d(L, q, seed, start)
+    rec = oracle_lib.sweeps3d(s, q, seed, 0, n, oracle_lib.threshold_table6(beta))
+    with potts.Cube(L, q, seed, start) as c:
+        c.tune(1, rows)
+        c.sweep(beta, n)
+        assert np.array_equal(c.records(0, n), rec)
+        assert np.array_equal(c.spins(), s)
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n", [(32, 3, 1, 1, 0.6, 4), (64, 9, 2, 0, 1.0, 3),
+                                                   (64, 150, 3, 1, 2.0, 3)])
+def test_chunk_kernel_on_colour_split_sizes(potts, oracle_lib, L, q, seed, start, beta, n):
+    s = oracle_lib.init3d(L, q, seed, start)
+    rec = oracle_lib.sweeps3d(s, q, seed, 0, n, oracle_lib.threshold_table6(beta))
+    with potts.Cube(L, q, seed, start) as c:
+        c.tune(2)
+        c.sweep(beta, n)
+        assert np.array_equal(c.records(0, n), rec)
+        assert np.array_equal(c.spins(), s)
+
+
+@pytest.mark.parametrize("q", [4, 40, 100, 250])
+def test_non_monotone_tables(potts, oracle_lib, q):
+    """Caller tables need not decrease with d: zeros between non-zero entries
+    (the wide form) and non-zero entries after large ones (the narrow form)."""
+    L, seed, n = 32, 41, 3
+    for thr in ([0, 2**31, 0, 5, 2**32 - 1, 0], [2**32 - 1, 7, 2**31, 1, 3 * 2**30, 2]):
+        for kernel in (1, 2):
+            s = oracle_lib.init3d(L, q, seed, 1)
+            rec = oracle_lib.sweeps3d(s, q, seed, 0, n, thr)
+            with potts.Cube(L, q, seed, 1) as c:
+                c.tune(kernel)
+                c.sweep_thr(thr, n)
+                assert np.array_equal(c.records(0, n), rec), (thr, kernel)
+                assert np.array_equal(c.spins(), s), (thr, kernel)
+
+
+def test_kernel_switches_and_reads_mid_chain(potts, oracle_lib):
+    """Reading the cube between colour-split sweeps and switching kernels keeps
+    the chain (the row-major and colour-split copies stay in step)."""
+    L, q, seed, beta = 64, 6, 23, 0.8
+    thr = oracle_lib.threshold_table6(beta)
+    s = oracle_lib.init3d(L, q, seed, 1)
+    with potts.Cube(L, q, seed, 1) as c:
+        t = 0
+        for kernel, n in [(1, 2), (1, 1), (2, 2), (1, 3), (0, 1), (2, 1), (2, 1), (1, 2)]:
+            rec = oracle_lib.sweeps3d(s, q, seed, t, n, thr)
+            c.tune(kernel)
+            c.sweep(beta, n)
+            t += n
+            assert np.array_equal(c.records(t - n, n), rec), kernel
+            assert np.array_equal(c.spins(), s), kernel
+            e, hist = oracle_lib.observables3d(s, q)
+            obs = c.observables()
+            assert obs["e_sat"] == e and np.array_equal(obs["hist"], hist)
+        assert np.array_equal(c.spins(), s)
 
 
 def test_split_calls_and_tables(potts, oracle_lib):
@@ -114,16 +197,18 @@ def test_record_ring_window(potts):
         assert np.array_equal(r[-1], np.concatenate([[c.observables()["e_sat"]], c.observables()["hist"]]))
 
 
-# the largest lattice: L^3 / 4 chunks just below 2^32 (17.2 GB of spins)
-L_MAX = 2580
+# the largest cubes: L^3 / 4 chunks just below 2^32 (L = 2580, 17.2 GB, chunk
+# kernel) and the largest L % 32 == 0 (L = 2560, colour-split kernel)
+MAX_CUBES = [2580, 2560]
 
 
-def test_maximum_cube_frozen_ground_state(potts):
+@pytest.mark.parametrize("L", MAX_CUBES)
+def test_maximum_cube_frozen_ground_state(potts, L):
     """q = 256 at beta = 9 from the ordered start: every proposal costs dE = 6,
     whose threshold floor(exp(-54) 2^32) is 0, so nothing moves: each record is
     e_sat = 3N, N_0 = N, and the window statistics are e = -3, C = 0,
     V_L = 2/3, m = 1, chi = 0, through the exact moments at their largest."""
-    L, q, n = L_MAX, 256, 2
+    q, n = 256, 2
     _say(f"maximum cube L={L} q={q} ordered beta=9")
     N = L**3
     with potts.Cube(L, q, 5, 0) as c:
@@ -135,11 +220,12 @@ def test_maximum_cube_frozen_ground_state(potts):
     assert s["V_L"] == pytest.approx(2.0 / 3.0, rel=1e-15)
 
 
-def test_maximum_cube_sampled_windows(potts, oracle_lib):
+@pytest.mark.parametrize("L", MAX_CUBES)
+def test_maximum_cube_sampled_windows(potts, oracle_lib, L):
     """A random start and one sweep on the largest cube: windows at the origin,
     across every periodic face and at the last bytes against the oracle's
     window restriction; the record against the observables kernel."""
-    L, q, seed, beta, n = L_MAX, 7, 21, BETA3, 1
+    q, seed, beta, n = 7, 21, BETA3, 1
     _say(f"maximum cube L={L} q={q} random windows")
     thr = oracle_lib.threshold_table6(beta)
     with potts.Cube(L, q, seed, 1) as c:
@@ -161,6 +247,10 @@ def test_rejects_bad_arguments(potts):
     for L, q in [(6, 3), (2, 3), (0, 3), (8, 1), (8, 257), (2584, 3)]:
         with pytest.raises(potts.PottsError):
             potts.Cube(L, q, 1, 1)
+    with potts.Cube(48, 3, 1, 1) as c:
+        for kernel, rows in [(1, 0), (3, 0), (-1, 0), (0, 3), (0, 96), (0, 36), (2, -2)]:
+            with pytest.raises(potts.PottsError):
+                c.tune(kernel, rows)  # 48 % 32 != 0; bad kernel; odd, too long, non-dividing rows
     with potts.Cube(8, 3, 1, 1) as c:
         with pytest.raises(potts.PottsError):
             c.sweep(-1.0, 1)
