@@ -36,13 +36,18 @@ ALGO_OPS_PER_SITE = 20.0
 ALGO_BYTES_PER_SITE = 2.0
 KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/packed.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
                   "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
+# the simple-cubic workload's dominant kernel
+CUBE_SOURCES = ["paper_1101_0876_amd/csrc/cubic_packed.hip", "paper_1101_0876_amd/csrc/cubic.hpp",
+                "paper_1101_0876_amd/csrc/sweep_row.hpp", "paper_1101_0876_amd/csrc/device.hpp",
+                "paper_1101_0876_amd/csrc/kernels.hpp"]
+SOURCES_OF = {"large": KERNEL_SOURCES, "cubic": CUBE_SOURCES}
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=None) -> str:
     """Hash of the dominant kernel's sources without comments and blank space, so
     edits of comments keep counter data taken on the same code valid."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel)) as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -59,7 +64,7 @@ def counter_traffic(workload: str):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(SOURCES_OF.get(workload)):
         return None
     return rec.get("bytes_per_launch")
 
@@ -518,21 +523,33 @@ def run_cubic(args):
     L = 1024 (2^30 uint8 spins, the default workload's site count), beta =
     0.5505, random start, seed 1, --steps sweeps (default 200) with records
     every sweep; the oracle's cubic chain on an L = 128 sample as the CPU
-    baseline."""
+    baseline.  Roofline of the half-sweep kernel from HIP events on the
+    state's own stream."""
+    import torch
+
     import paper_1101_0876_amd as potts
 
+    torch.cuda.set_device(0)
     L, q, seed, beta = 1024, 3, 1, 0.5505
     N = L ** 3
     steps = args.steps if args.steps != 2000 else 200
     warm = max(1, args.warmup)
+    kernel = args.kernel if args.kernel in (0, 1, 2) else 0
     with potts.Cube(L, q, seed, potts.RANDOM) as c:
-        c.tune(args.kernel if args.kernel in (0, 1, 2) else 0)
+        c.tune(kernel)
+        st = torch.cuda.ExternalStream(c.stream_handle())
         c.sweep(beta, warm)
         c.records(c.t - 1, 1)  # synchronizes
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        ev0.record(st)
         c.sweep(beta, steps)
+        ev1.record(st)
         rec = c.records(c.t - 1, 1)
         wall = time.perf_counter() - t0
+        ev1.synchronize()
+        ev_ms = ev0.elapsed_time(ev1)
         assert int(rec[0, 1:].sum()) == N, "population sum != N"
     cpu = None
     if not args.no_cpu:
@@ -551,13 +568,34 @@ def run_cubic(args):
         cpu = {"value": el * 1e9 / (n * Ls ** 3), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
                "sample": f"L={Ls}^3 q={q} cubic, random start, {n} sweeps with records, 1 thread"}
     ns = wall * 1e9 / (steps * N)
+    packed = kernel in (0, 1)
+    per_launch_s = ev_ms * 1e-3 / (2 * steps)
+    achieved_ops = ALGO_OPS_PER_SITE * (N / 2) / per_launch_s
     return {"metric": "ns per spin flip", "value": ns, "unit": "ns", "n_gpus": 1, "steps": steps, "warmup": warm,
             "ms_per_step": wall * 1e3 / steps, "higher_is_better": False, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "simple-cubic sweeps", "q": q, "L": L, "beta": beta, "seed": seed,
                        "start": "random", "records": "every sweep",
-                       "kernel": {0: "automatic", 1: "colour-split", 2: "chunk"}.get(args.kernel, "automatic")},
-            "spin_bytes_GBs": ALGO_BYTES_PER_SITE / ns, "cpu_baseline": cpu}
+                       "kernel": "colour-split" if packed else "chunk"},
+            "roofline": {
+                "bound": "alu",
+                "achieved": achieved_ops / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s",
+                "frac": achieved_ops / VALU_PEAK_OPS,
+                "traffic": counter_traffic("cubic") if packed else None,
+                "kernel": "cube_packed_kernel (colour-split half sweep)" if packed
+                          else "cube_sweep_kernel (chunk half sweep)",
+                "avg_launch_us": per_launch_s * 1e6,
+                "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
+            },
+            "hbm": {
+                "achieved_gbs": ALGO_BYTES_PER_SITE * N / (2 * per_launch_s) / 1e9,
+                "peak_gbs": HBM_PEAK_GBS,
+                "frac": ALGO_BYTES_PER_SITE * N / (2 * per_launch_s) / 1e9 / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_site_update": ALGO_BYTES_PER_SITE,
+            },
+            "event_ms": ev_ms, "cpu_baseline": cpu}
 
 
 def main():

@@ -443,6 +443,10 @@ int potts3d_tune(potts3d_state *s, int32_t kernel, int32_t rows);
 /* Sweeps done so far, or -1 for NULL. */
 int64_t potts3d_time(const potts3d_state *s);
 
+/* The state's stream (a hipStream_t; NULL for NULL), for callers that order
+ * their own work or events after its sweeps. */
+void *potts3d_stream(const potts3d_state *s);
+
 /* Releases the state (synchronizes first).  NULL is a no-op. */
 void potts3d_free(potts3d_state *s);
 

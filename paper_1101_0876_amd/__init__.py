@@ -217,6 +217,10 @@ class Cube:
     def t(self) -> int:
         return int(self._lib.potts3d_time(self._h))
 
+    def stream_handle(self) -> int:
+        """The state's hipStream_t as an integer (for torch.cuda.ExternalStream)."""
+        return int(self._lib.potts3d_stream(self._h) or 0)
+
     def observables(self) -> dict:
         o = PottsObs()
         check(self._lib.potts3d_observables(self._h, ctypes.byref(o)))

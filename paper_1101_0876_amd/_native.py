@@ -177,6 +177,7 @@ SIGNATURES = [
     ("potts3d_get_spins", ctypes.c_int, [_VP, _U8P]),
     ("potts3d_tune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     ("potts3d_time", ctypes.c_int64, [_VP]),
+    ("potts3d_stream", _VP, [_VP]),
     ("potts3d_free", None, [_VP]),
     ("potts_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("potts_last_error", ctypes.c_char_p, []),

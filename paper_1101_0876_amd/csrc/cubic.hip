@@ -499,6 +499,8 @@ int potts3d_tune(potts3d_state *s, int32_t kernel, int32_t rows) {
 
 int64_t potts3d_time(const potts3d_state *s) { return s ? s->t : -1; }
 
+void *potts3d_stream(const potts3d_state *s) { return s ? (void *)s->stream : nullptr; }
+
 void potts3d_free(potts3d_state *s) { release(s); }
 
 }  // extern "C"
