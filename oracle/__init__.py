@@ -80,6 +80,20 @@ def _load():
     lib.oracle3d_window.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64,
                                     u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p]
     lib.oracle3d_window.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_nnn_table.argtypes = [ctypes.c_double, ctypes.c_double, u64p]
+    lib.oracle_nnn_table.restype = ctypes.c_int
+    lib.oracle_nnn_site_update.argtypes = [ctypes.c_int, ctypes.c_int, u8p, u8p, ctypes.c_uint32, ctypes.c_uint32,
+                                           u64p]
+    lib.oracle_nnn_site_update.restype = ctypes.c_int
+    lib.oracle_nnn_colour_pass.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_int, u64p, u8p]
+    lib.oracle_nnn_colour_pass.restype = ctypes.c_int
+    lib.oracle_nnn_observables.argtypes = [ctypes.c_int, ctypes.c_int, u8p, i64p, i64p, i64p]
+    lib.oracle_nnn_observables.restype = ctypes.c_int
+    lib.oracle_nnn_sweeps.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_int64, u64p, u8p, i64p]
+    lib.oracle_nnn_sweeps.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -239,6 +253,50 @@ def window3d(L: int, q: int, seed: int, start: int, nsweeps: int, thr, x0: int, 
     _check(_load().oracle3d_window(L, q, seed, start, nsweeps, _ptr(t_arr, ctypes.c_uint32), x0, y0, z0, d,
                                    _ptr(out, ctypes.c_uint8)), "window3d")
     return out.reshape(d, d, d)
+
+
+# -- first and second neighbours ----------------------------------------------------
+def nnn_table(beta: float, j2: float) -> np.ndarray:
+    """81 acceptance entries, index (d1 + 4) * 9 + (d2 + 4): 2^32 when
+    d1 + j2 d2 <= 0, else min(floor(exp(-beta (d1 + j2 d2)) 2^32), 2^32 - 1)."""
+    thr = np.zeros(81, dtype=np.uint64)
+    _check(_load().oracle_nnn_table(float(beta), float(j2), _ptr(thr, ctypes.c_uint64)), "nnn_table")
+    return thr
+
+
+def nnn_site_update(q: int, s: int, nb1, nb2, w_prop: int, w_acc: int, thr) -> int:
+    a = np.ascontiguousarray(nb1, dtype=np.uint8)
+    b = np.ascontiguousarray(nb2, dtype=np.uint8)
+    t = np.ascontiguousarray(thr, dtype=np.uint64)
+    return int(_load().oracle_nnn_site_update(q, s, _ptr(a, ctypes.c_uint8), _ptr(b, ctypes.c_uint8), w_prop,
+                                              w_acc, _ptr(t, ctypes.c_uint64)))
+
+
+def nnn_colour_pass(spins: np.ndarray, q: int, seed: int, t: int, colour: int, thr) -> None:
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint64)
+    _check(_load().oracle_nnn_colour_pass(spins.shape[0], q, seed, t, colour, _ptr(t_arr, ctypes.c_uint64),
+                                          _ptr(spins, ctypes.c_uint8)), "nnn_colour_pass")
+
+
+def nnn_observables(spins: np.ndarray, q: int):
+    e1 = np.zeros(1, dtype=np.int64)
+    e2 = np.zeros(1, dtype=np.int64)
+    hist = np.zeros(q, dtype=np.int64)
+    _check(_load().oracle_nnn_observables(spins.shape[0], q, _ptr(spins, ctypes.c_uint8), _ptr(e1, ctypes.c_int64),
+                                          _ptr(e2, ctypes.c_int64), _ptr(hist, ctypes.c_int64)), "nnn_observables")
+    return int(e1[0]), int(e2[0]), hist
+
+
+def nnn_sweeps(spins: np.ndarray, q: int, seed: int, t0: int, n: int, thr, record: bool = True):
+    """n sweeps (nine colour passes each); records {e1, e2, hist[q]} per sweep."""
+    assert spins.dtype == np.uint8 and spins.flags.c_contiguous
+    t_arr = np.ascontiguousarray(thr, dtype=np.uint64)
+    rec = np.zeros((n, 2 + q), dtype=np.int64) if record else None
+    rptr = _ptr(rec, ctypes.c_int64) if record else None
+    _check(_load().oracle_nnn_sweeps(spins.shape[0], q, seed, t0, n, _ptr(t_arr, ctypes.c_uint64),
+                                     _ptr(spins, ctypes.c_uint8), rptr), "nnn_sweeps")
+    return rec
 
 
 def run(L: int, q: int, seed: int, start: int, beta: float, n: int):

@@ -568,3 +568,132 @@ int oracle3d_window(int L, int q, uint64_t seed, int start, int64_t nsweeps, con
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* First and second neighbours on the square lattice (Sec. 7: with
+ * second-neighbour couplings the lattice splits into nine independent
+ * sub-lattices instead of two).  Contract of this implementation:
+ *   - H = -sum_<ij> delta(s_i, s_j) - j2 sum_<<ij>> delta(s_i, s_j): the four
+ *     nearest neighbours with coupling 1 and the four diagonal neighbours
+ *     with coupling j2 (Eq. 1 extended to second neighbours);
+ *   - L x L periodic, L % 12 == 0 (three colours per axis, 4-byte chunks);
+ *   - colour c = 3 (y mod 3) + (x mod 3); one sweep updates colours 0..8 in
+ *     turn (two sites of one colour are at least three apart along an axis,
+ *     so neither is a first or second neighbour of the other);
+ *   - dE = (n1(s) - n1(k)) + j2 (n2(s) - n2(k)) with n1/n2 the numbers of
+ *     nearest/diagonal neighbours equal to a value; the table holds, for
+ *     d1 = n1(s) - n1(k) and d2 = n2(s) - n2(k) in -4..4, entry
+ *     (d1 + 4) * 9 + (d2 + 4) = 2^32 when dE <= 0 (always accept), else
+ *     min(floor(exp(-beta dE) 2^32), 2^32 - 1); a move is accepted iff
+ *     w_acc < entry;
+ *   - Philox block per (4-byte row chunk, sweep, colour): counter
+ *     (t_lo, y L/4 + x/4, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
+ *     b = (x & 3) >> 1 (the only two sites of one colour in a chunk sit at
+ *     x & 3 = 0 and 3);
+ *   - the initial conditions are those of the nearest-neighbour lattice;
+ *   - records {e1, e2, hist[q]}: satisfied nearest-neighbour bonds (2N),
+ *     satisfied diagonal bonds (2N) and the populations. */
+static int valid_nnn(int L, int q)
+{
+    return L >= 12 && L % 12 == 0 && (uint64_t)L * (uint64_t)L / 4 < ((uint64_t)1 << 32) && q >= 2 && q <= 256;
+}
+
+int oracle_nnn_table(double beta, double j2, uint64_t thr[81])
+{
+    if (!(beta >= 0.0) || isinf(beta) || !isfinite(j2) || thr == NULL) return ORACLE_EINVAL;
+    for (int d1 = -4; d1 <= 4; ++d1)
+        for (int d2 = -4; d2 <= 4; ++d2) {
+            const double de = (double)d1 + j2 * (double)d2;
+            uint64_t entry;
+            if (de <= 0.0) {
+                entry = (uint64_t)1 << 32;
+            } else {
+                double scaled = floor(exp(-beta * de) * 4294967296.0);
+                if (scaled > 4294967295.0) scaled = 4294967295.0;
+                entry = (uint64_t)scaled;
+            }
+            thr[(d1 + 4) * 9 + (d2 + 4)] = entry;
+        }
+    return ORACLE_OK;
+}
+
+/* One Metropolis trial: nb1 the four nearest, nb2 the four diagonal neighbours. */
+int oracle_nnn_site_update(int q, int s, const uint8_t nb1[4], const uint8_t nb2[4], uint32_t w_prop,
+                           uint32_t w_acc, const uint64_t thr[81])
+{
+    const int k = (int)word_to_value(w_prop, q);
+    int n1s = 0, n1k = 0, n2s = 0, n2k = 0;
+    for (int j = 0; j < 4; ++j) {
+        n1s += nb1[j] == s;
+        n1k += nb1[j] == k;
+        n2s += nb2[j] == s;
+        n2k += nb2[j] == k;
+    }
+    const int d1 = n1s - n1k, d2 = n2s - n2k;
+    return (uint64_t)w_acc < thr[(d1 + 4) * 9 + (d2 + 4)] ? k : s;
+}
+
+int oracle_nnn_colour_pass(int L, int q, uint64_t seed, uint64_t t, int colour, const uint64_t thr[81],
+                           uint8_t *spins)
+{
+    if (!valid_nnn(L, q) || spins == NULL || thr == NULL || colour < 0 || colour > 8) return ORACLE_EINVAL;
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            if (3 * (y % 3) + (x % 3) != colour) continue;
+            const int xl = (x + L - 1) % L, xr = (x + 1) % L, yu = (y + L - 1) % L, yd = (y + 1) % L;
+            const uint8_t nb1[4] = {spins[(size_t)y * L + xr], spins[(size_t)y * L + xl], spins[(size_t)yd * L + x],
+                                    spins[(size_t)yu * L + x]};
+            const uint8_t nb2[4] = {spins[(size_t)yu * L + xl], spins[(size_t)yu * L + xr],
+                                    spins[(size_t)yd * L + xl], spins[(size_t)yd * L + xr]};
+            uint32_t w[4];
+            chunk_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), 16u + (uint32_t)colour, w);
+            const int b = (x & 3) >> 1;
+            const size_t i = (size_t)y * L + x;
+            spins[i] = (uint8_t)oracle_nnn_site_update(q, spins[i], nb1, nb2, w[2 * b], w[2 * b + 1], thr);
+        }
+    return ORACLE_OK;
+}
+
+/* e1 over the 2N nearest-neighbour bonds (right, down), e2 over the 2N
+ * diagonal bonds (down-right, down-left), and N_v. */
+int oracle_nnn_observables(int L, int q, const uint8_t *spins, int64_t *e1, int64_t *e2, int64_t *hist)
+{
+    if (!valid_nnn(L, q) || spins == NULL) return ORACLE_EINVAL;
+    int64_t b1 = 0, b2 = 0;
+    if (hist) memset(hist, 0, sizeof(int64_t) * (size_t)q);
+    for (int y = 0; y < L; ++y)
+        for (int x = 0; x < L; ++x) {
+            const uint8_t s = spins[(size_t)y * L + x];
+            const int xr = (x + 1) % L, xl = (x + L - 1) % L, yd = (y + 1) % L;
+            b1 += s == spins[(size_t)y * L + xr];
+            b1 += s == spins[(size_t)yd * L + x];
+            b2 += s == spins[(size_t)yd * L + xr];
+            b2 += s == spins[(size_t)yd * L + xl];
+            if (hist) {
+                if (s >= q) return ORACLE_EINVAL;
+                ++hist[s];
+            }
+        }
+    if (e1) *e1 = b1;
+    if (e2) *e2 = b2;
+    return ORACLE_OK;
+}
+
+int oracle_nnn_sweeps(int L, int q, uint64_t seed, uint64_t t0, int64_t nsweeps, const uint64_t thr[81],
+                      uint8_t *spins, int64_t *records)
+{
+    if (!valid_nnn(L, q) || spins == NULL || thr == NULL || nsweeps < 0) return ORACLE_EINVAL;
+    for (int64_t j = 0; j < nsweeps; ++j) {
+        const uint64_t t = t0 + (uint64_t)j;
+        for (int colour = 0; colour < 9; ++colour) {
+            const int rc = oracle_nnn_colour_pass(L, q, seed, t, colour, thr, spins);
+            if (rc) return rc;
+        }
+        if (records) {
+            int64_t *rec = records + (size_t)j * (size_t)(2 + q);
+            const int rc = oracle_nnn_observables(L, q, spins, &rec[0], &rec[1], &rec[2]);
+            if (rc) return rc;
+        }
+    }
+    return ORACLE_OK;
+}
