@@ -40,7 +40,10 @@ KERNEL_SOURCES = ["paper_1101_0876_amd/csrc/packed.hip", "paper_1101_0876_amd/cs
 CUBE_SOURCES = ["paper_1101_0876_amd/csrc/cubic_packed.hip", "paper_1101_0876_amd/csrc/cubic.hpp",
                 "paper_1101_0876_amd/csrc/sweep_row.hpp", "paper_1101_0876_amd/csrc/device.hpp",
                 "paper_1101_0876_amd/csrc/kernels.hpp"]
-SOURCES_OF = {"large": KERNEL_SOURCES, "cubic": CUBE_SOURCES}
+# the first-plus-second-neighbour workload's kernels (one sweep)
+NNN_SOURCES = ["paper_1101_0876_amd/csrc/nnn.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
+               "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
+SOURCES_OF = {"large": KERNEL_SOURCES, "cubic": CUBE_SOURCES, "nnn": NNN_SOURCES}
 
 
 def kernel_hash(sources=None) -> str:
@@ -57,8 +60,9 @@ def kernel_hash(sources=None) -> str:
 
 
 def counter_traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    --pmc summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of the dominant kernel (per sweep for the nnn
+    workload) from the committed rocprofv3 --pmc summary, if it was taken on
+    the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -598,13 +602,96 @@ def run_cubic(args):
             "event_ms": ev_ms, "cpu_baseline": cpu}
 
 
+def run_nnn(args):
+    """First plus second neighbours (Sec. 7: nine colour passes per sweep):
+    q = 9, L = 8184 (the temperature-ramp size 8192 rounded down to a
+    multiple of 12), j2 = 0.5, beta = 0.8,
+    random start, seed 1, --steps sweeps (default 100) with records every
+    sweep; the oracle's chain on an L = 1200 sample as the CPU baseline.
+    Roofline of the colour-pass kernel from HIP events on the state's stream
+    (the record kernel timed the same way)."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    torch.cuda.set_device(0)
+    L, q, seed, beta, j2 = 8184, 9, 1, 0.8, 0.5  # the ramp size rounded to L % 12 == 0
+    N = L * L
+    steps = args.steps if args.steps != 2000 else 100
+    warm = max(1, args.warmup)
+    with potts.NnnLattice(L, q, seed, potts.RANDOM) as lat:
+        st = torch.cuda.ExternalStream(lat.stream_handle())
+        lat.sweep(beta, j2, warm)
+        lat.records(lat.t - 1, 1)  # synchronizes
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        lat.sweep(beta, j2, steps)
+        ev1.record(st)
+        rec = lat.records(lat.t - 1, 1)
+        wall = time.perf_counter() - t0
+        ev1.synchronize()
+        ev_ms = ev0.elapsed_time(ev1)
+        assert int(rec[0, 2:].sum()) == N, "population sum != N"
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        Ls = 1200
+        spins = oracle.init(Ls, q, seed, oracle.RANDOM)
+        thr = oracle.nnn_table(beta, j2)
+        n, t1 = 0, time.perf_counter()
+        while True:
+            oracle.nnn_sweeps(spins, q, seed, n, 1, thr, record=True)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= args.cpu_seconds or n >= 64:
+                break
+        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+               "sample": f"L={Ls} q={q} j2={j2} nine-colour chain, random start, {n} sweeps with records, 1 thread"}
+    ns = wall * 1e9 / (steps * N)
+    sweep_s = ev_ms * 1e-3 / steps
+    # Philox work the contract fixes: one 40-op block per 4-byte chunk and
+    # colour pass, 9 passes over L/3 rows x L/4 chunks = 0.75 N blocks a sweep
+    ops_per_site = 0.75 * 40.0
+    achieved_ops = ops_per_site * N / sweep_s
+    # bytes a sweep must move: each colour pass reads its active rows and the
+    # rows above and below them (the whole lattice, N) and writes its active
+    # rows (N/3); the record reads the lattice once (N)
+    sweep_bytes = 9 * (N + N / 3) + N
+    return {"metric": "ns per spin flip", "value": ns, "unit": "ns", "n_gpus": 1, "steps": steps, "warmup": warm,
+            "ms_per_step": wall * 1e3 / steps, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "first and second neighbours (nine colours)", "q": q, "L": L, "beta": beta,
+                       "j2": j2, "seed": seed, "start": "random", "records": "every sweep"},
+            "roofline": {
+                "bound": "alu",
+                "achieved": achieved_ops / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s",
+                "frac": achieved_ops / VALU_PEAK_OPS,
+                "traffic": counter_traffic("nnn"),
+                "kernel": "one sweep: nine nnn_pass_kernel launches + nnn_measure_kernel + nnn_fold_kernel",
+                "avg_sweep_us": sweep_s * 1e6,
+                "algorithmic_ops_per_site_update": ops_per_site,
+            },
+            "hbm": {
+                "achieved_gbs": sweep_bytes / sweep_s / 1e9,
+                "peak_gbs": HBM_PEAK_GBS,
+                "frac": sweep_bytes / sweep_s / 1e9 / HBM_PEAK_GBS,
+                "algorithmic_bytes_per_sweep": sweep_bytes,
+            },
+            "event_ms": ev_ms, "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
-                                                     "metastability", "heatbath", "cubic"])
+                                                     "metastability", "heatbath", "cubic", "nnn"])
     ap.add_argument("--kernel", type=int, default=0,
                     help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split; "
                          "cubic: 0 automatic (colour-split), 1 colour-split, 2 chunk")
@@ -638,6 +725,9 @@ def main():
         return
     if args.workload == "cubic":
         print(json.dumps(run_cubic(args)), flush=True)
+        return
+    if args.workload == "nnn":
+        print(json.dumps(run_nnn(args)), flush=True)
         return
     if args.workload == "metastability":
         print(json.dumps(run_metastability(args)), flush=True)

@@ -450,6 +450,73 @@ void *potts3d_stream(const potts3d_state *s);
 /* Releases the state (synchronizes first).  NULL is a no-op. */
 void potts3d_free(potts3d_state *s);
 
+/* ---- First and second neighbours on the square lattice (Sec. 7: with
+ * second-neighbour couplings the lattice splits into nine independent
+ * sub-lattices instead of two).  Contract:
+ *   - H = -sum_<ij> delta(s_i, s_j) - j2 sum_<<ij>> delta(s_i, s_j) over the
+ *     four nearest (coupling 1) and four diagonal (coupling j2) neighbours;
+ *   - L x L periodic, row-major uint8 as the nearest-neighbour lattice,
+ *     L % 12 == 0; colour c = 3 (y mod 3) + (x mod 3); one sweep updates
+ *     colours 0..8 in turn;
+ *   - with d1 = n1(s) - n1(k) and d2 = n2(s) - n2(k) (n1/n2: nearest/diagonal
+ *     neighbours equal to a value), the 81-entry table holds at index
+ *     (d1 + 4) * 9 + (d2 + 4) the value 2^32 when d1 + j2 d2 <= 0, else
+ *     min(floor(exp(-beta (d1 + j2 d2)) 2^32), 2^32 - 1), computed in FP64 on
+ *     the host; a move is accepted iff w_acc < entry;
+ *   - one Philox4x32-10 block per 4-byte row chunk, sweep and colour: counter
+ *     (t_lo, y L/4 + x/4, t_hi, 16 + c), key (seed_lo, seed_hi); site x takes
+ *     (w[2b], w[2b+1]), b = (x & 3) >> 1, as proposal and acceptance words;
+ *   - initial conditions as potts_init;
+ *   - records {e1, e2, hist[0..q)} per sweep: satisfied nearest bonds (2N),
+ *     satisfied diagonal bonds (2N), populations.
+ * The state owns an L*L lattice, a 4096-slot record ring and a stream.  Every
+ * call returns 0 or a negative POTTS_E* code (potts_last_error()). */
+typedef struct potts_nnn_state potts_nnn_state;
+
+typedef struct {
+    int64_t t;                 /* sweeps done                               */
+    int64_t e1;                /* satisfied nearest-neighbour bonds         */
+    int64_t e2;                /* satisfied diagonal bonds                  */
+    int64_t nmax;              /* max_v hist[v]                             */
+    int32_t q;
+    int32_t L;
+    int64_t hist[POTTS_QMAX];  /* valid for v < q                           */
+} potts_nnn_obs;
+
+/* Errors: EINVAL (L < 12, L % 12 != 0, q outside 2..256, bad start, out NULL),
+ * ERANGE (L*L/4 >= 2^32), ENOMEM, EDEVICE.  On error *out is NULL. */
+int potts_nnn_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_nnn_state **out);
+
+/* The 81-entry table above.  Errors: EINVAL (beta < 0 or not finite, j2 not
+ * finite, thr NULL). */
+int potts_nnn_table(double beta, double j2, uint64_t thr[81]);
+
+/* nsweeps sweeps (nine colour passes and the record each) at (beta, j2);
+ * asynchronous on the state's stream.  Errors: EINVAL, ERANGE, EDEVICE. */
+int potts_nnn_sweep(potts_nnn_state *s, double beta, double j2, int64_t nsweeps);
+
+/* As potts_nnn_sweep with a caller table (host memory, 81 entries <= 2^32). */
+int potts_nnn_sweep_thr(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps);
+
+/* Records of sweeps t0 .. t0+n-1 into out[n*(2+q)] (synchronizes).  Errors:
+ * ERANGE if one of them is not (or no longer) in the ring (the last 4095). */
+int potts_nnn_records(potts_nnn_state *s, int64_t t0, int64_t n, int64_t *out);
+
+/* Measures the current lattice (synchronizes). */
+int potts_nnn_observables(potts_nnn_state *s, potts_nnn_obs *out);
+
+/* Copies the lattice (L*L bytes, row-major) to host memory (synchronizes). */
+int potts_nnn_get_spins(potts_nnn_state *s, uint8_t *host_out);
+
+/* Sweeps done so far, or -1 for NULL. */
+int64_t potts_nnn_time(const potts_nnn_state *s);
+
+/* The state's stream (a hipStream_t; NULL for NULL). */
+void *potts_nnn_stream(const potts_nnn_state *s);
+
+/* Releases the state (synchronizes first).  NULL is a no-op. */
+void potts_nnn_free(potts_nnn_state *s);
+
 const char *potts_strerror(int code);
 const char *potts_last_error(void);
 

@@ -13,14 +13,14 @@ from typing import Optional
 
 import numpy as np
 
-from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, PottsObs, PottsRequest,
+from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, PottsNnnObs, PottsObs, PottsRequest,
                       PottsServed, PottsServerCfg, PottsSummary, check, load)
 
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "Cube", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
-           "threshold_table6", "ORDERED", "RANDOM", "load"]
+__all__ = ["Lattice", "Cube", "NnnLattice", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
+           "threshold_table6", "nnn_table", "ORDERED", "RANDOM", "load"]
 
 
 def threshold_table(beta: float) -> np.ndarray:
@@ -247,6 +247,79 @@ class Cube:
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:
             self._lib.potts3d_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def nnn_table(beta: float, j2: float) -> np.ndarray:
+    """The 81 acceptance entries of the first-plus-second-neighbour lattice,
+    index (d1 + 4) * 9 + (d2 + 4) (host FP64)."""
+    thr = np.zeros(81, dtype=np.uint64)
+    check(load().potts_nnn_table(float(beta), float(j2), thr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    return thr
+
+
+class NnnLattice:
+    """One L x L lattice with nearest (coupling 1) and diagonal (coupling j2)
+    neighbours on the GPU (a potts_nnn_state): nine colour passes per sweep,
+    records {e1, e2, hist}."""
+
+    def __init__(self, L: int, q: int, seed: int = 1, start: int = RANDOM):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        check(self._lib.potts_nnn_init(int(L), int(q), int(seed), int(start), ctypes.byref(self._h)))
+        self.L = int(L)
+        self.q = int(q)
+        self.seed = int(seed)
+
+    def sweep(self, beta: float, j2: float, nsweeps: int = 1) -> None:
+        check(self._lib.potts_nnn_sweep(self._h, float(beta), float(j2), int(nsweeps)))
+
+    def sweep_thr(self, thr, nsweeps: int = 1) -> None:
+        t = np.ascontiguousarray(thr, dtype=np.uint64)
+        if t.size != 81:
+            raise ValueError("the table has 81 entries")
+        check(self._lib.potts_nnn_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                            int(nsweeps)))
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.potts_nnn_time(self._h))
+
+    def stream_handle(self) -> int:
+        return int(self._lib.potts_nnn_stream(self._h) or 0)
+
+    def observables(self) -> dict:
+        o = PottsNnnObs()
+        check(self._lib.potts_nnn_observables(self._h, ctypes.byref(o)))
+        return {"t": o.t, "e1": o.e1, "e2": o.e2, "nmax": o.nmax,
+                "hist": np.array(o.hist[: self.q], dtype=np.int64)}
+
+    def records(self, t0: int, n: int) -> np.ndarray:
+        out = np.zeros((n, 2 + self.q), dtype=np.int64)
+        check(self._lib.potts_nnn_records(self._h, int(t0), int(n),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return out
+
+    def spins(self) -> np.ndarray:
+        out = np.zeros(self.L * self.L, dtype=np.uint8)
+        check(self._lib.potts_nnn_get_spins(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out.reshape(self.L, self.L)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.potts_nnn_free(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -109,6 +109,18 @@ class PottsServed(ctypes.Structure):
     ]
 
 
+class PottsNnnObs(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_int64),
+        ("e1", ctypes.c_int64),
+        ("e2", ctypes.c_int64),
+        ("nmax", ctypes.c_int64),
+        ("q", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("hist", ctypes.c_int64 * POTTS_QMAX),
+    ]
+
+
 _lib = None
 
 # (name, restype, argtypes) for every exported symbol declared in include/potts.h
@@ -165,6 +177,17 @@ SIGNATURES = [
     ("potts_server_iterations", ctypes.c_int64, [_VP]),
     ("potts_server_stop", ctypes.c_int, [_VP]),
     ("potts_free", None, [_VP]),
+    ("potts_nnn_init", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.POINTER(_VP)]),
+    ("potts_nnn_table", ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]),
+    ("potts_nnn_sweep", ctypes.c_int, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_int64]),
+    ("potts_nnn_sweep_thr", ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64]),
+    ("potts_nnn_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
+    ("potts_nnn_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsNnnObs)]),
+    ("potts_nnn_get_spins", ctypes.c_int, [_VP, _U8P]),
+    ("potts_nnn_time", ctypes.c_int64, [_VP]),
+    ("potts_nnn_stream", _VP, [_VP]),
+    ("potts_nnn_free", None, [_VP]),
     ("potts3d_init", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int,
                                     ctypes.POINTER(_VP)]),
     ("potts3d_threshold_table", ctypes.c_int, [ctypes.c_double, _U32P]),

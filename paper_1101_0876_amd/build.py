@@ -5,7 +5,7 @@ import os
 import subprocess
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["capi.hip", "kernels.hip", "strip.hip", "packed.hip", "resident.hip", "stats.hip", "batch.hip", "server.hip", "cubic.hip", "cubic_packed.hip"]
+SOURCES = ["capi.hip", "kernels.hip", "strip.hip", "packed.hip", "resident.hip", "stats.hip", "batch.hip", "server.hip", "cubic.hip", "cubic_packed.hip", "nnn.hip"]
 LIB_PATH = os.path.join(_HERE, "libpotts.so")
 
 

@@ -1,0 +1,464 @@
+// nnn.hip -- the square lattice with first and second neighbours (Sec. 7:
+// with second-neighbour couplings the lattice splits into nine independent
+// sub-lattices instead of two).  Contract:
+//   - H = -sum_<ij> delta - j2 sum_<<ij>> delta over the four nearest and the
+//     four diagonal neighbours (Eq. 1 extended);
+//   - L x L periodic, L % 12 == 0; colour c = 3 (y mod 3) + (x mod 3), one
+//     sweep = colours 0..8 in turn;
+//   - table entry (d1 + 4) * 9 + (d2 + 4), d1/d2 = the drops in equal
+//     nearest/diagonal neighbours from the current value to the proposal:
+//     2^32 when d1 + j2 d2 <= 0, else min(floor(exp(-beta (d1 + j2 d2)) 2^32),
+//     2^32 - 1); accept iff w_acc < entry;
+//   - Philox block per (4-byte row chunk, sweep, colour): counter (t_lo,
+//     y L/4 + x/4, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
+//     b = (x & 3) >> 1; initial conditions as on the nearest-neighbour lattice;
+//   - records {e1, e2, hist[q]} per sweep: nearest and diagonal satisfied
+//     bonds (2N each) and the populations.
+//
+// Kernels: a colour pass runs one thread per 4-byte chunk of the rows of its
+// colour (each holds one or two active sites, served by one Philox block); all
+// eight neighbours are bytes of the chunk's own dword and its two neighbours
+// in rows y-1, y, y+1, shifted into place with v_alignbyte, and compared four
+// sites at a time.  Bytes of the same row that a neighbouring
+// thread rewrites are never neighbours of an active site (they hold other
+// colours and are written back unchanged), so the pass is race-free.  The
+// record of a sweep comes from one measurement kernel after its nine passes
+// (partial sums in striped slots, folded by a one-block kernel).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/potts.h"
+#include "device.hpp"
+#include "sweep_row.hpp"
+
+struct potts_nnn_state {
+  int32_t L = 0, q = 0;
+  uint64_t seed = 0;
+  int64_t t = 0;
+  uint8_t *spins = nullptr;
+  hipStream_t stream = nullptr;
+  unsigned long long *records = nullptr;  // ring of rec_cap slots of 2 + q
+  int64_t rec_cap = 0;
+  unsigned long long *scratch = nullptr;  // 2 + q words for measurements
+  unsigned long long *stripes = nullptr;  // kStripes partial records of 2 + q words, kept zero between sweeps
+  bool have_thr = false;
+  double thr_beta = 0.0, thr_j2 = 0.0;
+  uint64_t thr[81] = {};
+};
+
+namespace potts {
+int record_error(int code, const std::string &msg);
+}
+
+namespace {
+
+using potts::PhiloxHead;
+using potts::row::diff_pattern;
+using potts::Words;
+using potts::byte_of;
+using potts::count_equal;
+using potts::philox4x32_10;
+using potts::philox_head;
+using potts::philox_tail;
+using potts::scale_to_q;
+using potts::wave_sum;
+using potts::zero_bytes;
+
+constexpr int kBlock = 256;
+constexpr int64_t kRingSlots = 4096;
+
+struct NnnLattice {
+  uint8_t *spins;
+  uint32_t L, q;
+  uint32_t k0, k1;
+};
+
+struct NnnPass {
+  NnnLattice g;
+  uint32_t t_lo, t_hi;
+  uint32_t colour;
+  uint64_t thr[81];
+};
+
+__device__ __forceinline__ uint32_t alignb(uint32_t hi, uint32_t lo, uint32_t shift) {
+  return __builtin_amdgcn_alignbyte(hi, lo, shift);
+}
+
+// Grid: x over the chunks of a row, y over the rows of the pass's colour.
+// The four neighbour groups are compared with the current value and the
+// proposal as byte-wise "differs" flag patterns (bits 7..4 of every byte, the
+// row kernels' diff_pattern, CMP by q); an active byte's counts are the
+// popcounts of its pattern byte: d1 = n1(s) - n1(k) = diff1(k) - diff1(s).
+template <int CMP>
+__global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
+  __shared__ uint64_t table[81];
+  for (uint32_t i = threadIdx.x; i < 81; i += kBlock) table[i] = p.thr[i];
+  __syncthreads();
+  const uint32_t L = p.g.L, cpr = L >> 2;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= cpr) return;
+  const uint32_t cy = p.colour / 3, cx = p.colour - 3 * cy;
+  const uint32_t y = 3 * blockIdx.y + cy;
+  const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+  const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
+  uint32_t *row = reinterpret_cast<uint32_t *>(p.g.spins + (size_t)y * L);
+  const uint32_t *up = reinterpret_cast<const uint32_t *>(p.g.spins + (size_t)yu * L);
+  const uint32_t *dn = reinterpret_cast<const uint32_t *>(p.g.spins + (size_t)yd * L);
+  const uint32_t cur = row[j];
+  const uint32_t U = up[j], D = dn[j];
+  // byte i of each: the neighbour of site x = 4j + i
+  const uint32_t left = alignb(cur, row[jl], 3), right = alignb(row[jr], cur, 1);
+  const uint32_t ul = alignb(U, up[jl], 3), ur = alignb(up[jr], U, 1);
+  const uint32_t dl = alignb(D, dn[jl], 3), dr = alignb(dn[jr], D, 1);
+
+  const PhiloxHead h = philox_head(p.t_lo, p.t_hi, 16u + p.colour, p.g.k0, p.g.k1);
+  const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
+  // active bytes: x = 4j + i with x mod 3 == cx (4j mod 3 == j mod 3); the
+  // first at i0, a second at byte 3 when i0 == 0
+  const uint32_t i0 = (cx + 3u - j % 3u) % 3u;
+  const uint32_t k0 = scale_to_q(i0 == 2 ? w.w2 : w.w0, p.g.q);
+  const bool two = i0 == 0;
+  uint32_t prop = (cur & ~(0xFFu << (8 * i0))) | (k0 << (8 * i0));
+  if (two) prop = (prop & 0x00FFFFFFu) | (scale_to_q(w.w2, p.g.q) << 24);
+  const uint32_t s1 = diff_pattern<CMP>(cur, left, right, U, D), k1 = diff_pattern<CMP>(prop, left, right, U, D);
+  const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
+  uint32_t out = cur;
+  {
+    const uint32_t m = 0xF0u << (8 * i0);
+    const int d1 = __popc(k1 & m) - __popc(s1 & m), d2 = __popc(k2 & m) - __popc(s2 & m);
+    const uint32_t wacc = i0 == 2 ? w.w3 : w.w1;
+    const uint32_t bm = 0xFFu << (8 * i0);
+    if ((uint64_t)wacc < table[(d1 + 4) * 9 + (d2 + 4)]) out = (prop & bm) | (out & ~bm);
+  }
+  if (two) {
+    const uint32_t m = 0xF0000000u;
+    const int d1 = __popc(k1 & m) - __popc(s1 & m), d2 = __popc(k2 & m) - __popc(s2 & m);
+    if ((uint64_t)w.w3 < table[(d1 + 4) * 9 + (d2 + 4)]) out = (out & 0x00FFFFFFu) | (prop & 0xFF000000u);
+  }
+  row[j] = out;
+}
+
+// e1 (right, down), e2 (down-right, down-left) and populations of the
+// lattice, added to one of kStripes partial records (block number mod
+// kStripes, so that no record word takes more than a few hundred atomics);
+// nnn_fold_kernel then sums the stripes into the record and clears them.
+// Grid: x over the chunks of a row, y strided over bands of kMeasureRows rows
+// (a band's loads are issued together).  PRIV (q <= 64): populations counted
+// in lane-private LDS columns (no two lanes share a counter); else q shared
+// bins.
+constexpr uint32_t kMeasureRows = 8;
+constexpr uint32_t kPrivMaxQ = 64;
+constexpr uint32_t kStripes = 32;
+constexpr uint32_t kMeasureBlocks = 2048;
+
+template <bool PRIV>
+__global__ __launch_bounds__(kBlock) void nnn_measure_kernel(NnnLattice g, unsigned long long *stripes) {
+  __shared__ __align__(16) uint32_t hist[PRIV ? 64 * kPrivMaxQ : 256];
+  __shared__ uint32_t part[256 + 2];
+  const uint32_t q = g.q, lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  for (uint32_t i = threadIdx.x; i < (PRIV ? 64 * q : q); i += kBlock) hist[i] = 0;
+  if (threadIdx.x < 2) part[256 + threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t L = g.L, cpr = L >> 2;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t nbands = (L + kMeasureRows - 1) / kMeasureRows;
+  uint32_t e1 = 0, e2 = 0;
+  if (j < cpr) {
+    const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
+    uint8_t *hb = reinterpret_cast<uint8_t *>(hist);
+    for (uint32_t band = blockIdx.y; band < nbands; band += gridDim.y) {
+      const uint32_t y0 = band * kMeasureRows;
+      const uint32_t rows = L - y0 < kMeasureRows ? L - y0 : kMeasureRows;
+      uint32_t c[kMeasureRows + 1], r[kMeasureRows + 1], l[kMeasureRows + 1];
+#pragma unroll
+      for (uint32_t k = 0; k <= kMeasureRows; ++k) {
+        if (k <= rows) {
+          const uint32_t y = y0 + k >= L ? y0 + k - L : y0 + k;
+          const uint32_t *row = reinterpret_cast<const uint32_t *>(g.spins + (size_t)y * L);
+          c[k] = row[j];
+          r[k] = row[jr];
+          l[k] = row[jl];
+        }
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kMeasureRows; ++k) {
+        if (k < rows) {
+          const uint32_t cur = c[k], D = c[k + 1];
+          const uint32_t right = alignb(r[k], cur, 1);
+          const uint32_t dr = alignb(r[k + 1], D, 1), dl = alignb(D, l[k + 1], 3);
+          e1 += __popc(zero_bytes(cur ^ right)) + __popc(zero_bytes(cur ^ D));
+          e2 += __popc(zero_bytes(cur ^ dr)) + __popc(zero_bytes(cur ^ dl));
+          if (PRIV) {
+#pragma unroll
+            for (uint32_t b = 0; b < 4; ++b)
+              atomicAdd(reinterpret_cast<uint32_t *>(
+                            hb + __builtin_amdgcn_perm(cur, lane * 4u, 0x0C0C0000u | ((4u + b) << 8))),
+                        1u);
+          } else {
+            for (uint32_t b = 0; b < 4; ++b) atomicAdd(&hist[byte_of(cur, b)], 1u);
+          }
+        }
+      }
+    }
+  }
+  e1 = wave_sum(e1);
+  e2 = wave_sum(e2);
+  if (lane == 0) {
+    if (e1) atomicAdd(&part[256], e1);
+    if (e2) atomicAdd(&part[257], e2);
+  }
+  __syncthreads();
+  if (PRIV) {
+    for (uint32_t v = wave; v < q; v += kBlock / 64) {
+      const uint32_t n = wave_sum(hist[v * 64u + lane]);
+      if (lane == 0) part[v] = n;
+    }
+    __syncthreads();
+  }
+  unsigned long long *dst = stripes + ((blockIdx.y * gridDim.x + blockIdx.x) % kStripes) * (uint64_t)(q + 2);
+  for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
+    const uint32_t n = PRIV ? part[v] : hist[v];
+    if (n) atomicAdd(&dst[2 + v], (unsigned long long)n);
+  }
+  if (threadIdx.x < 2 && part[256 + threadIdx.x])
+    atomicAdd(&dst[threadIdx.x], (unsigned long long)part[256 + threadIdx.x]);
+}
+
+// rec[i] = sum over the stripes of word i, then the stripes are cleared; every
+// (stripe, word) pair is loaded by its own thread
+__global__ __launch_bounds__(kBlock) void nnn_fold_kernel(unsigned long long *stripes, uint32_t words,
+                                                          unsigned long long *rec) {
+  __shared__ unsigned long long acc[258];
+  for (uint32_t i = threadIdx.x; i < words; i += kBlock) acc[i] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < kStripes * words; k += kBlock) {
+    const unsigned long long v = stripes[k];
+    if (v) {
+      atomicAdd(&acc[k % words], v);
+      stripes[k] = 0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < words; i += kBlock) rec[i] = acc[i];
+}
+
+void launch_measure(const NnnLattice &g, unsigned long long *stripes, unsigned long long *rec,
+                    hipStream_t stream) {
+  const uint32_t bx = ((g.L >> 2) + kBlock - 1) / kBlock;
+  const uint32_t nbands = (g.L + kMeasureRows - 1) / kMeasureRows;
+  const uint32_t by = std::max<uint32_t>(1u, std::min<uint32_t>(nbands, kMeasureBlocks / bx));
+  if (g.q <= kPrivMaxQ)
+    hipLaunchKernelGGL(nnn_measure_kernel<true>, dim3(bx, by), dim3(kBlock), 0, stream, g, stripes);
+  else
+    hipLaunchKernelGGL(nnn_measure_kernel<false>, dim3(bx, by), dim3(kBlock), 0, stream, g, stripes);
+  hipLaunchKernelGGL(nnn_fold_kernel, dim3(1), dim3(kBlock), 0, stream, stripes, g.q + 2, rec);
+}
+
+__global__ __launch_bounds__(kBlock) void nnn_init_kernel(NnnLattice g, int random) {
+  const uint64_t c = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t cpr = g.L >> 2;
+  if (c >= (uint64_t)g.L * cpr) return;
+  uint32_t out = 0;
+  if (random) {
+    const Words w = philox4x32_10(0u, (uint32_t)c, 0u, 2u, g.k0, g.k1);
+    out = scale_to_q(w.w0, g.q) | (scale_to_q(w.w1, g.q) << 8) | (scale_to_q(w.w2, g.q) << 16) |
+          (scale_to_q(w.w3, g.q) << 24);
+  }
+  reinterpret_cast<uint32_t *>(g.spins)[c] = out;
+}
+
+int fail(int code, const std::string &msg) { return potts::record_error(code, msg); }
+
+#define NNN_TRY(call)                                                                                \
+  do {                                                                                               \
+    hipError_t e_ = (call);                                                                          \
+    if (e_ != hipSuccess) return fail(POTTS_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+NnnLattice lattice_of(const potts_nnn_state *s) {
+  NnnLattice g;
+  g.spins = s->spins;
+  g.L = (uint32_t)s->L;
+  g.q = (uint32_t)s->q;
+  g.k0 = (uint32_t)s->seed;
+  g.k1 = (uint32_t)(s->seed >> 32);
+  return g;
+}
+
+void release(potts_nnn_state *s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->spins) (void)hipFree(s->spins);
+  if (s->records) (void)hipFree(s->records);
+  if (s->scratch) (void)hipFree(s->scratch);
+  if (s->stripes) (void)hipFree(s->stripes);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+int table81(double beta, double j2, uint64_t thr[81]) {
+  if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
+  if (!(beta >= 0.0) || !isfinite(beta)) return fail(POTTS_EINVAL, "beta must be finite and >= 0");
+  if (!isfinite(j2)) return fail(POTTS_EINVAL, "j2 must be finite");
+  for (int d1 = -4; d1 <= 4; ++d1)
+    for (int d2 = -4; d2 <= 4; ++d2) {
+      const double de = (double)d1 + j2 * (double)d2;
+      uint64_t v = 1ull << 32;
+      if (de > 0.0) {
+        const double scaled = floor(ldexp(exp(-beta * de), 32));
+        v = scaled >= 4294967295.0 ? 4294967295ull : (uint64_t)scaled;
+      }
+      thr[(d1 + 4) * 9 + (d2 + 4)] = v;
+    }
+  return POTTS_OK;
+}
+
+int run(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
+  if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
+  for (int i = 0; i < 81; ++i)
+    if (thr[i] > (1ull << 32)) return fail(POTTS_EINVAL, "table entries must be <= 2^32");
+  if (nsweeps == 0) return POTTS_OK;
+  const int64_t rl = s->q + 2;
+  NnnPass p{};
+  p.g = lattice_of(s);
+  for (int i = 0; i < 81; ++i) p.thr[i] = thr[i];
+  const uint32_t L = (uint32_t)s->L;
+  const dim3 pass_grid(((L >> 2) + kBlock - 1) / kBlock, L / 3);
+  for (int64_t k = 0; k < nsweeps; ++k) {
+    const int64_t t = s->t + k;
+    p.t_lo = (uint32_t)(uint64_t)t;
+    p.t_hi = (uint32_t)((uint64_t)t >> 32);
+    for (uint32_t c = 0; c < 9; ++c) {
+      p.colour = c;
+      if (s->q <= 16)
+        hipLaunchKernelGGL(nnn_pass_kernel<0>, pass_grid, dim3(kBlock), 0, s->stream, p);
+      else if (s->q <= 128)
+        hipLaunchKernelGGL(nnn_pass_kernel<1>, pass_grid, dim3(kBlock), 0, s->stream, p);
+      else
+        hipLaunchKernelGGL(nnn_pass_kernel<2>, pass_grid, dim3(kBlock), 0, s->stream, p);
+    }
+    launch_measure(p.g, s->stripes, s->records + (t & (s->rec_cap - 1)) * rl, s->stream);
+    NNN_TRY(hipGetLastError());
+  }
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int potts_nnn_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_nnn_state **out) {
+  if (!out) return fail(POTTS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (L < 12 || L % 12 || q < 2 || q > POTTS_QMAX || (start != POTTS_ORDERED && start != POTTS_RANDOM))
+    return fail(POTTS_EINVAL, "need L >= 12, L % 12 == 0, 2 <= q <= 256 and a valid start");
+  if ((uint64_t)L * L / 4 >= (1ull << 32)) return fail(POTTS_ERANGE, "L*L/4 must be below 2^32");
+  potts_nnn_state *s = new (std::nothrow) potts_nnn_state();
+  if (!s) return fail(POTTS_ENOMEM, "host allocation failed");
+  s->L = L;
+  s->q = q;
+  s->seed = seed;
+  s->rec_cap = kRingSlots;
+  if (hipStreamCreate(&s->stream) != hipSuccess || hipMalloc(&s->spins, (size_t)L * L) != hipSuccess ||
+      hipMalloc(&s->records, (size_t)kRingSlots * (q + 2) * 8) != hipSuccess ||
+      hipMalloc(&s->scratch, (size_t)(q + 2) * 8) != hipSuccess ||
+      hipMalloc(&s->stripes, (size_t)kStripes * (q + 2) * 8) != hipSuccess) {
+    (void)hipGetLastError();
+    release(s);
+    return fail(POTTS_ENOMEM, "device allocation failed");
+  }
+  const NnnLattice g = lattice_of(s);
+  const uint64_t chunks = (uint64_t)L * (L >> 2);
+  hipLaunchKernelGGL(nnn_init_kernel, dim3((unsigned)((chunks + kBlock - 1) / kBlock)), dim3(kBlock), 0, s->stream,
+                     g, start == POTTS_RANDOM ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(s->stripes, 0, (size_t)kStripes * (q + 2) * 8, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    release(s);
+    return fail(POTTS_EDEVICE, std::string("nnn_init_kernel: ") + hipGetErrorString(e));
+  }
+  *out = s;
+  return POTTS_OK;
+}
+
+int potts_nnn_table(double beta, double j2, uint64_t thr[81]) { return table81(beta, j2, thr); }
+
+int potts_nnn_sweep(potts_nnn_state *s, double beta, double j2, int64_t nsweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (!s->have_thr || s->thr_beta != beta || s->thr_j2 != j2) {
+    uint64_t thr[81];
+    const int rc = table81(beta, j2, thr);
+    if (rc) return rc;
+    std::copy(thr, thr + 81, s->thr);
+    s->thr_beta = beta;
+    s->thr_j2 = j2;
+    s->have_thr = true;
+  }
+  return run(s, s->thr, nsweeps);
+}
+
+int potts_nnn_sweep_thr(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
+  if (!thr) return fail(POTTS_EINVAL, "thr is NULL");
+  return run(s, thr, nsweeps);
+}
+
+int potts_nnn_records(potts_nnn_state *s, int64_t t0, int64_t n, int64_t *out) {
+  if (!s || (!out && n > 0)) return fail(POTTS_EINVAL, "NULL argument");
+  if (n < 0 || t0 < 0) return fail(POTTS_EINVAL, "negative record index or count");
+  const int64_t oldest = s->t - s->rec_cap + 1;
+  if (t0 < (oldest > 0 ? oldest : 0) || t0 + n > s->t) return fail(POTTS_ERANGE, "requested records are not in the ring");
+  const int64_t rl = s->q + 2;
+  for (int64_t done = 0; done < n;) {
+    const int64_t slot = (t0 + done) & (s->rec_cap - 1);
+    const int64_t run_n = std::min<int64_t>(n - done, s->rec_cap - slot);
+    NNN_TRY(hipMemcpyAsync(out + done * rl, s->records + slot * rl, (size_t)(run_n * rl) * 8,
+                           hipMemcpyDeviceToHost, s->stream));
+    done += run_n;
+  }
+  NNN_TRY(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+int potts_nnn_observables(potts_nnn_state *s, potts_nnn_obs *out) {
+  if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
+  const int64_t rl = s->q + 2;
+  launch_measure(lattice_of(s), s->stripes, s->scratch, s->stream);
+  NNN_TRY(hipGetLastError());
+  std::vector<int64_t> rec((size_t)rl);
+  NNN_TRY(hipMemcpyAsync(rec.data(), s->scratch, (size_t)rl * 8, hipMemcpyDeviceToHost, s->stream));
+  NNN_TRY(hipStreamSynchronize(s->stream));
+  out->t = s->t;
+  out->e1 = rec[0];
+  out->e2 = rec[1];
+  out->q = s->q;
+  out->L = s->L;
+  out->nmax = 0;
+  for (int v = 0; v < POTTS_QMAX; ++v) out->hist[v] = v < s->q ? rec[2 + v] : 0;
+  for (int v = 0; v < s->q; ++v) out->nmax = rec[2 + v] > out->nmax ? rec[2 + v] : out->nmax;
+  return POTTS_OK;
+}
+
+int potts_nnn_get_spins(potts_nnn_state *s, uint8_t *host_out) {
+  if (!s || !host_out) return fail(POTTS_EINVAL, "NULL argument");
+  NNN_TRY(hipMemcpyAsync(host_out, s->spins, (size_t)s->L * s->L, hipMemcpyDeviceToHost, s->stream));
+  NNN_TRY(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+int64_t potts_nnn_time(const potts_nnn_state *s) { return s ? s->t : -1; }
+
+void *potts_nnn_stream(const potts_nnn_state *s) { return s ? (void *)s->stream : nullptr; }
+
+void potts_nnn_free(potts_nnn_state *s) { release(s); }
+
+}  // extern "C"

@@ -129,6 +129,36 @@ def test_cubic_null_state(lib):
     lib.potts3d_free(None)
 
 
+@pytest.mark.parametrize("beta,j2", [(0.0, 0.5), (0.3, 0.5), (0.7, -0.4), (1.1, 1.0), (2.0, 0.25), (40.0, 0.1)])
+def test_nnn_table_matches_oracle(oracle_lib, beta, j2):
+    import paper_1101_0876_amd as p
+
+    assert np.array_equal(p.nnn_table(beta, j2), oracle_lib.nnn_table(beta, j2))
+
+
+@pytest.mark.parametrize("L,q,start", [(0, 3, 1), (8, 3, 1), (18, 3, 1), (24, 1, 1), (24, 257, 1), (24, 3, 4),
+                                       (131076, 3, 1)])
+def test_nnn_init_rejects_bad_shapes_without_device(lib, L, q, start):
+    h = ctypes.c_void_p()
+    rc = lib.potts_nnn_init(L, q, 1, start, ctypes.byref(h))
+    assert rc in (-1, -4) and not h.value
+    assert lib.potts_last_error()
+
+
+def test_nnn_null_state(lib):
+    thr = (ctypes.c_uint64 * 81)()
+    assert lib.potts_nnn_table(-1.0, 0.5, thr) == -1
+    assert lib.potts_nnn_table(0.5, float("nan"), thr) == -1
+    assert lib.potts_nnn_table(0.5, 0.5, None) == -1
+    assert lib.potts_nnn_sweep(None, 1.0, 0.5, 1) == -1
+    assert lib.potts_nnn_sweep_thr(None, thr, 1) == -1
+    assert lib.potts_nnn_observables(None, None) == -1
+    assert lib.potts_nnn_records(None, 0, 1, None) == -1
+    assert lib.potts_nnn_time(None) == -1
+    assert lib.potts_nnn_stream(None) is None
+    lib.potts_nnn_free(None)
+
+
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5, -99):
         assert lib.potts_strerror(code)
