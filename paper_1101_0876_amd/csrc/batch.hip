@@ -2,10 +2,13 @@
 // together: the C ABI potts_batch_* of include/potts.h.
 //
 // Jobs with L <= 256 run in the LDS-resident kernel, one workgroup each, all
-// their sweeps in one launch.  Larger jobs run in the strip kernel through a
-// tile table (workgroup -> job, item range), so one launch per colour advances
-// every one of them by one sweep.  Because the random numbers are keyed by
-// (seed, site, sweep), every job gives exactly the bits it gives alone.
+// their sweeps in one launch.  Larger jobs run through a tile table
+// (workgroup -> job, item range), so one launch per colour advances every one
+// of them by one sweep: jobs with L % 32 == 0 in the colour-split kernel on a
+// copy of their lattice split into its two colour planes (packed before a run,
+// unpacked after it), the others in the row-major strip kernel.  Because the
+// random numbers are keyed by (seed, site, sweep), every job gives exactly the
+// bits it gives alone.
 //
 // Launch shape: an in-run autotuner times the candidate strip heights per
 // lattice size on the first sweeps of the run (these are real sweeps: the
@@ -58,9 +61,10 @@ int64_t pow2_at_least(int64_t n) {
 int q_class(uint32_t q) { return q <= 16 ? 0 : q <= potts::kPrivateHistMaxQ ? 1 : q <= 128 ? 2 : 3; }
 uint32_t class_max_q(int c) { return c == 0 ? 16 : c == 1 ? potts::kPrivateHistMaxQ : c == 2 ? 128 : 256; }
 
-struct StripGroup {  // strip jobs sharing a kernel instantiation
+struct StripGroup {  // strip or colour-split jobs sharing a kernel instantiation
   int qc = 0;
   bool wide = false;
+  bool packed = false;    // colour-split kernel on the jobs' colour planes
   std::vector<int> jobs;  // job indices
 };
 
@@ -79,9 +83,12 @@ struct potts_batch {
   hipStream_t stream = nullptr, side = nullptr;
   bool owns_stream = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
-  uint8_t *arena = nullptr;                 // all lattices
+  uint8_t *arena = nullptr;                 // all lattices (row-major)
+  uint8_t *planes = nullptr;                // colour-split copies of the colour-split jobs
   unsigned long long *rec_arena = nullptr;  // all record rings
   std::vector<size_t> lat_off, rec_off;     // per job offsets
+  std::vector<size_t> plane_off;            // per colour-split job (others unused)
+  std::vector<char> packed;                 // per job: runs in the colour-split kernel
   std::vector<int64_t> ring;                // slots per job (power of two)
   std::vector<int64_t> done;                // sweeps done per job
   std::vector<int64_t> target;              // sweeps each job has when the current run ends
@@ -111,7 +118,7 @@ void release(potts_batch *b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (void *p : {(void *)b->arena, (void *)b->rec_arena, (void *)b->d_strip, (void *)b->d_tiles,
+  for (void *p : {(void *)b->arena, (void *)b->planes, (void *)b->rec_arena, (void *)b->d_strip, (void *)b->d_tiles,
                   (void *)b->d_res, (void *)b->d_stats, (void *)b->d_stats_out})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev_t0, b->ev_t1})
@@ -122,6 +129,8 @@ void release(potts_batch *b) {
 }
 
 bool resident_job(const potts_job &j) { return potts::resident_fits((uint32_t)j.L, (uint32_t)j.q); }
+
+bool packed_job(const potts_job &j) { return !resident_job(j) && j.L % 32 == 0; }
 
 // Candidate strip heights for an L (even divisors up to 32).
 std::vector<uint32_t> row_candidates(uint32_t L) {
@@ -141,8 +150,14 @@ void build_strip_tables(const potts_batch *b, const StripGroup &g, std::vector<p
     const int j = g.jobs[k];
     const potts_job &job = b->jobs[j];
     potts::StripParams p{};
-    potts::fill_strip_params(p, b->arena + b->lat_off[j], (uint32_t)job.L, (uint32_t)job.q, job.seed,
-                             &b->thr[(size_t)j * 4], b->rows[j]);
+    if (g.packed) {
+      potts::fill_strip_params(p, b->planes + b->plane_off[j], (uint32_t)job.L, (uint32_t)job.q, job.seed,
+                               &b->thr[(size_t)j * 4], b->rows[j]);
+      potts::set_items(p, (uint32_t)job.L / 32, (uint32_t)job.L, b->rows[j]);
+    } else {
+      potts::fill_strip_params(p, b->arena + b->lat_off[j], (uint32_t)job.L, (uint32_t)job.q, job.seed,
+                               &b->thr[(size_t)j * 4], b->rows[j]);
+    }
     p.t0 = (uint64_t)b->done[j];
     p.nsweeps = (uint64_t)(b->target[j] - b->done[j] > 0 ? b->target[j] - b->done[j] : 0);
     p.ring = b->rec_arena + b->rec_off[j];
@@ -170,8 +185,13 @@ int launch_strip_sweep(potts_batch *b, const StripGroup &g, const potts::StripPa
   l.jobs = d_desc;
   l.tiles = d_tiles;
   l.sweep = s;
-  HIP_TRY(potts::launch_strip(l, 0, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
-  HIP_TRY(potts::launch_strip(l, 1, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+  if (g.packed) {
+    HIP_TRY(potts::launch_packed(l, 0, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+    HIP_TRY(potts::launch_packed(l, 1, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+  } else {
+    HIP_TRY(potts::launch_strip(l, 0, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+    HIP_TRY(potts::launch_strip(l, 1, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+  }
   return POTTS_OK;
 }
 
@@ -336,6 +356,20 @@ int queue_rest(potts_batch *b) {
   return POTTS_OK;
 }
 
+// The colour-split jobs' lattices into their colour planes (before a run's
+// sweeps) or back (after them), on the batch stream.
+int convert_packed(potts_batch *b, bool to_planes) {
+  for (size_t j = 0; j < b->jobs.size(); ++j) {
+    if (!b->packed[j]) continue;
+    const uint32_t L = (uint32_t)b->jobs[j].L;
+    if (to_planes)
+      HIP_TRY(potts::launch_pack(b->arena + b->lat_off[j], b->planes + b->plane_off[j], L, b->stream));
+    else
+      HIP_TRY(potts::launch_unpack(b->planes + b->plane_off[j], b->arena + b->lat_off[j], L, b->stream));
+  }
+  return POTTS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -391,21 +425,30 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
   B_TRY(hipEventCreate(&b->ev_t1));
 
   // memory: lattices and record rings (every sweep of a run kept)
-  size_t lat_bytes = 0, rec_words = 0;
+  size_t lat_bytes = 0, rec_words = 0, plane_bytes = 0;
   b->lat_off.resize(n);
   b->rec_off.resize(n);
+  b->plane_off.assign(n, 0);
+  b->packed.assign(n, 0);
   for (int32_t i = 0; i < n; ++i) {
     const potts_job &j = jobs[i];
     b->lat_off[i] = lat_bytes;
     lat_bytes += ((size_t)j.L * j.L + 255) / 256 * 256;
+    if (packed_job(j)) {
+      b->packed[i] = 1;
+      b->plane_off[i] = plane_bytes;
+      plane_bytes += ((size_t)j.L * j.L + 255) / 256 * 256;
+    }
     b->ring[i] = pow2_at_least(std::max<int64_t>(j.nsweeps + 1, b->opts.window + 1));
     b->rec_off[i] = rec_words;
     rec_words += (size_t)b->ring[i] * (size_t)(j.q + 1);
   }
-  if (hipMalloc(&b->arena, lat_bytes) != hipSuccess || hipMalloc(&b->rec_arena, rec_words * 8) != hipSuccess) {
+  if (hipMalloc(&b->arena, lat_bytes) != hipSuccess || hipMalloc(&b->rec_arena, rec_words * 8) != hipSuccess ||
+      (plane_bytes && hipMalloc(&b->planes, plane_bytes) != hipSuccess)) {
     (void)hipGetLastError();
     release(b);
-    return record_error(POTTS_ENOMEM, "batch arena allocation failed (" + std::to_string(lat_bytes + rec_words * 8) + " bytes)");
+    return record_error(POTTS_ENOMEM, "batch arena allocation failed (" +
+                                          std::to_string(lat_bytes + plane_bytes + rec_words * 8) + " bytes)");
   }
   B_TRY(potts::launch_fill_u64(b->rec_arena, rec_words, 0ull, b->stream));
 
@@ -427,10 +470,11 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
       g.max_L = std::max<uint32_t>(g.max_L, (uint32_t)j.L);
       g.max_q = std::max<uint32_t>(g.max_q, (uint32_t)j.q);
     } else {
-      auto key = std::make_pair(qc, wide);
+      const bool pk = b->packed[i] != 0;
+      auto key = std::make_pair(qc * 2 + (pk ? 1 : 0), wide);
       if (!sg.count(key)) {
         sg[key] = b->strip_groups.size();
-        b->strip_groups.push_back(StripGroup{qc, wide, {}});
+        b->strip_groups.push_back(StripGroup{qc, wide, pk, {}});
       }
       b->strip_groups[sg[key]].jobs.push_back(i);
       b->rows[i] = b->opts.strip_rows && j.L % b->opts.strip_rows == 0 && b->opts.strip_rows % 2 == 0
@@ -484,9 +528,10 @@ int potts_batch_run(potts_batch *b) {
   hipEvent_t mark = nullptr;
   HIP_TRY(hipEventCreate(&mark));
   HIP_TRY(hipEventRecord(mark, b->stream));
-  int rc = POTTS_OK;
-  if (b->opts.tune) rc = autotune(b);
+  int rc = convert_packed(b, true);
+  if (!rc && b->opts.tune) rc = autotune(b);
   if (!rc) rc = queue_rest(b);
+  if (!rc) rc = convert_packed(b, false);
   if (!rc) {
     hipError_t e = hipEventRecord(b->ev_t1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(b->ev_t1);

@@ -350,8 +350,8 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     p.nsweeps = (uint64_t)count;
     for (int64_t j = 0; j < count; ++j) {
       l.sweep = (uint32_t)j;
-      HIP_TRY(potts::launch_packed(l, 0, grid, wide, s->stream));
-      HIP_TRY(potts::launch_packed(l, 1, grid, wide, s->stream));
+      HIP_TRY(potts::launch_packed(l, 0, grid, l.single.q, wide, s->stream));
+      HIP_TRY(potts::launch_packed(l, 1, grid, l.single.q, wide, s->stream));
     }
     HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
   }

@@ -154,7 +154,10 @@ hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_
                         hipStream_t stream);
 // colour-split single-lattice kernel (packed.hip): l.single describes the
 // split copy (spins = its two planes, ipr = L/32); pack/unpack convert
-hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, bool wide, hipStream_t stream);
+// qmax: the largest q of the launch's jobs (selects the comparison mode and
+// histogram form); l.tiles set: batched jobs through the tile table
+hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
+                         hipStream_t stream);
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream);
 hipError_t launch_unpack(const uint8_t *packed, uint8_t *row_major, uint32_t L, hipStream_t stream);
 // folds stripe set t & 1 of p into ring slot t and clears it

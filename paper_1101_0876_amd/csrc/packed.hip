@@ -18,6 +18,7 @@
 // Work item: 16 packed bytes (16 active sites) of R consecutive rows of the
 // active plane, walked downwards like the strip kernel: each passive row is
 // loaded once and serves as the down, the same-row and the up neighbour.
+// Batches of lattices run the same kernel through a tile table.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -82,16 +83,23 @@ __device__ __forceinline__ void packed_row(const StripParams &p, const PhiloxHea
 
 // p.spins: the packed lattice; p.ipr = L/32 items per row band; the whole
 // lattice (no slab mode); records through p.stripes when set, else the slot.
-template <int COLOUR, int CMP, bool PRIV, bool WIDE>
+// TILED: workgroup -> (job, item range) from the tile table (batched
+// lattices, as in the strip kernel); otherwise the single descriptor with a
+// grid-stride loop.
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
 __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   __shared__ __align__(16) uint32_t table_words[512];
   constexpr uint32_t kHistWords = PRIV ? 64u * (CMP == 0 ? 16u : kPrivateHistMaxQ) : 256u;
   __shared__ __align__(16) uint32_t hist[kHistWords];
   __shared__ uint32_t partial[257];
-  const StripParams &p = launch.single;
   // colour 1 walks the workgroups bottom-up (see strip.hip)
   const uint32_t bid = COLOUR == 1 ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
-  const bool lead = bid == 0;
+  const StripTile tile = TILED ? launch.tiles[bid] : StripTile{0, 0, 0, 0};
+  const StripParams &p = TILED ? launch.jobs[tile.job] : launch.single;
+  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * kBlock + threadIdx.x;
+  const uint32_t end = TILED ? tile.first + tile.count : p.nitems;
+  const uint32_t stride = TILED ? (uint32_t)kBlock : gridDim.x * kBlock;
+  const bool lead = TILED ? tile.lead != 0 : bid == 0;
   if (launch.sweep >= p.nsweeps) return;
   const uint64_t t = p.t0 + launch.sweep;
   const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), (uint32_t)COLOUR, p.k0, p.k1);
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   const uint32_t rows = p.rows;
   PSums sums{0, 0};
 
-  for (uint32_t item = bid * kBlock + threadIdx.x; item < p.nitems; item += gridDim.x * kBlock) {
+  for (uint32_t item = first; item < end; item += stride) {
     const uint32_t rb = p.item_shift >= 0 ? item >> p.item_shift
                                           : (uint32_t)__umul64hi((uint64_t)item, p.item_magic);
     const uint32_t xi = item - rb * p.ipr;
@@ -223,26 +231,33 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(const uint8_t *src, uint
   out[1] = hi;
 }
 
-template <int COLOUR, bool WIDE>
+template <int COLOUR, bool WIDE, bool TILED>
 hipError_t launch_w(const StripLaunch &l, unsigned grid, uint32_t q, hipStream_t stream) {
   if (q <= 16)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 0, true, WIDE>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 0, true, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
   else if (q <= kPrivateHistMaxQ)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, true, WIDE>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, true, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
   else if (q <= 128)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, false, WIDE>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, false, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
   else
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 2, false, WIDE>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 2, false, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
   return hipGetLastError();
+}
+
+template <bool TILED>
+hipError_t launch_c(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide, hipStream_t stream) {
+  if (colour == 0)
+    return wide ? launch_w<0, true, TILED>(l, grid, qmax, stream) : launch_w<0, false, TILED>(l, grid, qmax, stream);
+  return wide ? launch_w<1, true, TILED>(l, grid, qmax, stream) : launch_w<1, false, TILED>(l, grid, qmax, stream);
 }
 
 }  // namespace
 
-hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, bool wide, hipStream_t stream) {
+hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
+                         hipStream_t stream) {
   if (grid == 0) return hipSuccess;
-  const uint32_t q = l.single.q;
-  if (colour == 0) return wide ? launch_w<0, true>(l, grid, q, stream) : launch_w<0, false>(l, grid, q, stream);
-  return wide ? launch_w<1, true>(l, grid, q, stream) : launch_w<1, false>(l, grid, q, stream);
+  return l.tiles ? launch_c<true>(l, colour, grid, qmax, wide, stream)
+                 : launch_c<false>(l, colour, grid, qmax, wide, stream);
 }
 
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream) {

@@ -26,8 +26,9 @@ def potts():
     return p
 
 
-# resident (L <= 256) and strip (L >= 512) jobs, every comparison class,
-# a zero threshold (beta = 9), uneven sweep counts, both starts
+# resident (L <= 256), colour-split (L >= 512, L % 32 == 0) and strip
+# (L % 32 == 16) jobs, every comparison class, zero thresholds (beta = 9),
+# uneven sweep counts, both starts
 MIX = [
     dict(L=16, q=3, seed=11, start=1, beta=1.0, nsweeps=9),
     dict(L=64, q=9, seed=12, start=0, beta=1.02 * math.log(4.0), nsweeps=12),
@@ -41,6 +42,9 @@ MIX = [
     dict(L=528, q=40, seed=20, start=1, beta=9.0, nsweeps=7),
     dict(L=512, q=130, seed=21, start=1, beta=1.1, nsweeps=4),
     dict(L=544, q=5, seed=22, start=1, beta=1.2, nsweeps=0),
+    dict(L=576, q=40, seed=23, start=0, beta=9.0, nsweeps=5),     # colour-split, wide, private bins
+    dict(L=512, q=100, seed=24, start=1, beta=1.0, nsweeps=6),    # colour-split, shared bins
+    dict(L=560, q=7, seed=25, start=1, beta=beta_c(7), nsweeps=5),  # strip, q <= 16
 ]
 
 
