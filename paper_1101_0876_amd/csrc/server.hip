@@ -157,11 +157,22 @@ size_t job_bytes(const Job &j) {
   return ((size_t)j.req.L * j.req.L + 255) / 256 * 256 + (size_t)j.cap * (size_t)(j.req.q + 1) * 8;
 }
 
+// Frees a job's device memory (failure paths; synchronous).
+void release_job_memory(Job &j) {
+  for (void *p : {(void *)j.lat, (void *)j.ring})
+    if (p) (void)hipFree(p);
+  j.lat = nullptr;
+  j.ring = nullptr;
+}
+
 // Allocates and initializes an admitted job on the server stream.
 bool admit(potts_server *s, Job &j, std::string &err) {
   hipError_t e = hipMallocAsync((void **)&j.lat, ((size_t)j.req.L * j.req.L + 255) / 256 * 256, s->stream);
   if (e == hipSuccess) e = hipMallocAsync((void **)&j.ring, (size_t)j.cap * (j.req.q + 1) * 8, s->stream);
   if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(s->stream);
+    release_job_memory(j);
     err = std::string("allocation failed: ") + herr(e);
     return false;
   }
@@ -176,6 +187,8 @@ bool admit(potts_server *s, Job &j, std::string &err) {
   e = potts::launch_init(p, s->stream);
   if (e == hipSuccess) e = potts::launch_fill_u64(j.ring, (uint64_t)j.cap * (j.req.q + 1), 0ull, s->stream);
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s->stream);
+    release_job_memory(j);
     err = std::string("initialization failed: ") + herr(e);
     return false;
   }
@@ -419,6 +432,7 @@ void fail_all(potts_server *s, int code, const std::string &msg) {
   s->failed = code;
   s->fail_msg = msg;
   auto finish = [&](std::unique_ptr<Job> jp) {
+    release_job_memory(*jp);
     jp->info.status = code;
     jp->info.t_done = seconds_since(s);
     s->done_order.push_back(jp->ticket);
