@@ -60,6 +60,8 @@ namespace {
 
 using potts::PhiloxHead;
 using potts::row::diff_pattern;
+using potts::row::lattice_rsrc;
+using potts::row::load4;
 using potts::Words;
 using potts::byte_of;
 using potts::count_equal;
@@ -107,15 +109,18 @@ __global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
   const uint32_t y = 3 * blockIdx.y + cy;
   const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
   const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
-  uint32_t *row = reinterpret_cast<uint32_t *>(p.g.spins + (size_t)y * L);
-  const uint32_t *up = reinterpret_cast<const uint32_t *>(p.g.spins + (size_t)yu * L);
-  const uint32_t *dn = reinterpret_cast<const uint32_t *>(p.g.spins + (size_t)yd * L);
-  const uint32_t cur = row[j];
-  const uint32_t U = up[j], D = dn[j];
+  // the three rows are the same for the whole workgroup: one buffer resource
+  // each (scalar registers), 32-bit lane offsets, no 64-bit address math
+  const __amdgpu_buffer_rsrc_t row = lattice_rsrc(p.g.spins + (size_t)y * L);
+  const __amdgpu_buffer_rsrc_t up = lattice_rsrc(p.g.spins + (size_t)yu * L);
+  const __amdgpu_buffer_rsrc_t dn = lattice_rsrc(p.g.spins + (size_t)yd * L);
+  const uint32_t oj = 4 * j, ol = 4 * jl, orr = 4 * jr;
+  const uint32_t cur = load4(row, oj);
+  const uint32_t U = load4(up, oj), D = load4(dn, oj);
   // byte i of each: the neighbour of site x = 4j + i
-  const uint32_t left = alignb(cur, row[jl], 3), right = alignb(row[jr], cur, 1);
-  const uint32_t ul = alignb(U, up[jl], 3), ur = alignb(up[jr], U, 1);
-  const uint32_t dl = alignb(D, dn[jl], 3), dr = alignb(dn[jr], D, 1);
+  const uint32_t left = alignb(cur, load4(row, ol), 3), right = alignb(load4(row, orr), cur, 1);
+  const uint32_t ul = alignb(U, load4(up, ol), 3), ur = alignb(load4(up, orr), U, 1);
+  const uint32_t dl = alignb(D, load4(dn, ol), 3), dr = alignb(load4(dn, orr), D, 1);
 
   const PhiloxHead h = philox_head(p.t_lo, p.t_hi, 16u + p.colour, p.g.k0, p.g.k1);
   const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
     const int d1 = __popc(k1 & m) - __popc(s1 & m), d2 = __popc(k2 & m) - __popc(s2 & m);
     if ((uint64_t)w.w3 < table[(d1 + 4) * 9 + (d2 + 4)]) out = (out & 0x00FFFFFFu) | (prop & 0xFF000000u);
   }
-  row[j] = out;
+  __builtin_amdgcn_raw_buffer_store_b32(out, row, oj, 0, 0);
 }
 
 // e1 (right, down), e2 (down-right, down-left) and populations of the
