@@ -514,12 +514,26 @@ def run_heatbath(args):
                 break
         cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
                "sample": f"L={Ls} q={q} heat-bath, random start, {n} sweeps with records, 1 thread"}
+    ev_ms = ev0.elapsed_time(ev1)
+    per_launch_s = ev_ms * 1e-3 / (2 * steps)
+    achieved_ops = ALGO_OPS_PER_SITE * (L * L / 2) / per_launch_s
     return {"metric": "ns per spin flip", "value": wall * 1e9 / (steps * L * L), "unit": "ns", "n_gpus": 1,
             "steps": steps, "warmup": max(1, args.warmup), "ms_per_step": wall * 1e3 / steps,
             "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "heat-bath sweeps", "q": q, "L": L, "beta": beta, "seed": seed,
                        "start": "random", "records": "every sweep"},
-            "event_ms": ev0.elapsed_time(ev1), "cpu_baseline": cpu}
+            "roofline": {
+                "bound": "alu",
+                "achieved": achieved_ops / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s",
+                "frac": achieved_ops / VALU_PEAK_OPS,
+                "traffic": None,
+                "kernel": "heatbath4_kernel (chunk half sweep)",
+                "avg_launch_us": per_launch_s * 1e6,
+                "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
+            },
+            "event_ms": ev_ms, "cpu_baseline": cpu}
 
 
 def run_cubic(args):

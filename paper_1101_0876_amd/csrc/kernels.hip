@@ -12,6 +12,8 @@
 // and populations (every site is final then; every bond joins the colours).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void sweep4_kernel(SweepParams p) {
 // value outside the (at most four) neighbour values is found by fixed-point
 // iteration of k = j + #{excluded values <= k}.
 __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                                  uint32_t w, const Thresholds &thr) {
+                                                  uint32_t w, const Thresholds &thr, const double inv[4]) {
   const uint32_t na = 1 + (a == b) + (a == c) + (a == d);
   const uint32_t nb = 1 + (b == a) + (b == c) + (b == d);
   const uint32_t nc = 1 + (c == a) + (c == b) + (c == d);
@@ -123,7 +125,7 @@ __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32
   const uint64_t wb = fb ? weight(nmax - nb) : 0;
   const uint64_t wc = fc ? weight(nmax - nc) : 0;
   const uint64_t wd = fd ? weight(nmax - nd) : 0;
-  const uint64_t w0 = weight(nmax);  // each value no neighbour holds
+  const uint64_t w0 = weight(nmax);  // each value no neighbour holds (nmax >= 1: a threshold)
   const uint64_t S = wa + wb + wc + wd;
   const uint64_t Z = S + (uint64_t)(q - m) * w0;  // < 2^41
   // r = floor(w Z / 2^32), exactly, from the two halves of Z
@@ -132,56 +134,65 @@ __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32
   if (r < wa + wb) return b;
   if (r < wa + wb + wc) return c;
   if (r < S) return d;
-  const uint64_t j = (r - S) / w0;  // w0 > 0 here: r < Z
-  uint32_t k = (uint32_t)j;
+  // j = floor(X / w0) for X = r - S < (q - m) w0 (so w0 > 0 and j < 256): X
+  // and w0 are exact doubles and inv = 1/w0 rounded, so X * inv is within a
+  // few ulp of X / w0 and its floor is j - 1, j or j + 1; one integer check
+  // each way makes it exact
+  const uint64_t X = r - S;
+  uint32_t j = (uint32_t)((double)X * inv[nmax - 1]);
+  if ((uint64_t)j * w0 > X) --j;
+  else if ((uint64_t)(j + 1) * w0 <= X) ++j;
+  uint32_t k = j;
 #pragma unroll
   for (int it = 0; it < 5; ++it)
-    k = (uint32_t)j + (a <= k) + (fb && b <= k) + (fc && c <= k) + (fd && d <= k);
+    k = j + (a <= k) + (fb && b <= k) + (fc && c <= k) + (fd && d <= k);
   return k;
 }
 
+// Grid: x over the chunks of a row, y strided over the rows (no division per
+// chunk); the Philox head of the half sweep is the same for every lane.
 template <int COLOUR>
 __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t esum;
   for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
   if (threadIdx.x == 0) esum = 0;
-  if (COLOUR == 1 && blockIdx.x == 0 && p.rec_clear) {
+  if (COLOUR == 1 && blockIdx.x == 0 && blockIdx.y == 0 && p.rec_clear) {
     for (uint32_t i = threadIdx.x; i < p.q + 1; i += kBlock) p.rec_clear[i] = 0;
   }
   __syncthreads();
 
-  const uint32_t cpr = p.L >> 2;
+  const uint32_t L = p.L, cpr = L >> 2;
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const PhiloxHead h = philox_head(p.t_lo, p.t_hi, (uint32_t)COLOUR + 4u, p.k0, p.k1);
   uint32_t e = 0;
-  for (uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x; g < p.nchunks;
-       g += (uint64_t)gridDim.x * kBlock) {
-    const uint32_t y = (uint32_t)(g / cpr);
-    const uint32_t j = (uint32_t)(g - (uint64_t)y * cpr);
-    const uint32_t yu = y == 0 ? p.L - 1 : y - 1;
-    const uint32_t yd = y + 1 == p.L ? 0 : y + 1;
-    uint32_t *row = reinterpret_cast<uint32_t *>(p.spins + (size_t)y * p.L);
-    const uint32_t up = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yu * p.L)[j];
-    const uint32_t dn = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * p.L)[j];
-    const uint32_t cur = row[j];
-    const uint32_t lf = row[j == 0 ? cpr - 1 : j - 1];
-    const uint32_t rt = row[j + 1 == cpr ? 0 : j + 1];
-    const uint32_t left = (cur << 8) | (lf >> 24);   // byte i: spin at x-1
-    const uint32_t right = (cur >> 8) | (rt << 24);  // byte i: spin at x+1
+  if (j < cpr) {
+    const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
+    for (uint32_t y = blockIdx.y; y < L; y += gridDim.y) {
+      const uint32_t yu = y == 0 ? L - 1 : y - 1;
+      const uint32_t yd = y + 1 == L ? 0 : y + 1;
+      uint32_t *row = reinterpret_cast<uint32_t *>(p.spins + (size_t)y * L);
+      const uint32_t up = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yu * L)[j];
+      const uint32_t dn = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * L)[j];
+      const uint32_t cur = row[j];
+      const uint32_t left = __builtin_amdgcn_alignbyte(cur, row[jl], 3);   // byte i: spin at x-1
+      const uint32_t right = __builtin_amdgcn_alignbyte(row[jr], cur, 1);  // byte i: spin at x+1
 
-    const Words w = philox4x32_10(p.t_lo, (uint32_t)g, p.t_hi, (uint32_t)COLOUR + 4u, p.k0, p.k1);
-    const uint32_t o = (COLOUR + y) & 1u;  // byte of the first active site; the second is o + 2
-    uint32_t out = cur;
+      const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
+      const uint32_t o = (COLOUR + y) & 1u;  // byte of the first active site; the second is o + 2
+      uint32_t out = cur;
 #pragma unroll
-    for (uint32_t s = 0; s < 2; ++s) {
-      const uint32_t i = o + 2 * s;
-      const uint32_t a = byte_of(up, i), b = byte_of(dn, i), c = byte_of(left, i), d = byte_of(right, i);
-      const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, p.thr);
-      out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
-      if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
+      for (uint32_t s = 0; s < 2; ++s) {
+        const uint32_t i = o + 2 * s;
+        const uint32_t a = byte_of(up, i), b = byte_of(dn, i), c = byte_of(left, i), d = byte_of(right, i);
+        const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, p.thr, p.inv_thr);
+        out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
+        if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
+      }
+      row[j] = out;
+      if (COLOUR == 1)
+        for (uint32_t bb = 0; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
     }
-    row[j] = out;
-    if (COLOUR == 1)
-      for (uint32_t bb = 0; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
   }
   if (COLOUR == 1) {
     e = wave_sum(e);
@@ -278,11 +289,14 @@ hipError_t launch_half_sweep(const SweepParams &p, int colour, hipStream_t strea
 }
 
 hipError_t launch_heatbath(const SweepParams &p, int colour, hipStream_t stream) {
-  const unsigned grid = persistent_grid(p.nchunks, 4096);
+  SweepParams h = p;
+  for (int d = 0; d < 4; ++d) h.inv_thr[d] = h.thr.v[d] ? 1.0 / (double)h.thr.v[d] : 0.0;
+  const uint32_t bx = ((p.L >> 2) + kBlock - 1) / kBlock;
+  const uint32_t by = std::max<uint32_t>(1u, std::min<uint32_t>(p.L, 4096u / bx));
   if (colour == 0)
-    hipLaunchKernelGGL(heatbath4_kernel<0>, dim3(grid), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL(heatbath4_kernel<0>, dim3(bx, by), dim3(kBlock), 0, stream, h);
   else
-    hipLaunchKernelGGL(heatbath4_kernel<1>, dim3(grid), dim3(kBlock), 0, stream, p);
+    hipLaunchKernelGGL(heatbath4_kernel<1>, dim3(bx, by), dim3(kBlock), 0, stream, h);
   return hipGetLastError();
 }
 

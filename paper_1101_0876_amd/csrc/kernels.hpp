@@ -19,6 +19,7 @@ struct SweepParams {
   Thresholds thr;
   unsigned long long *rec;        // record of this sweep: [0] e_sat, [1+v] N_v
   unsigned long long *rec_clear;  // record slot to zero for the next sweep, or null
+  double inv_thr[4];              // heat bath: 1/thr[d] rounded (0 where thr[d] == 0), set by its launcher
 };
 
 // Main path (L % 16 == 0, L <= 65520): a work item is a 16-byte-wide strip of
