@@ -261,16 +261,17 @@ def test_oracle_observables_of_large_lattice(potts, oracle_lib):
 
 
 # q at the edges of the kernels' comparison modes (<=16, <=128, <=256) and of
-# the lane-private histogram (<=32); L with power-of-two and other row widths
-@pytest.mark.parametrize("L,q", [(48, 16), (48, 17), (80, 32), (80, 33), (96, 64), (96, 65), (96, 128),
-                                 (112, 129), (208, 256), (1040, 9), (64, 2), (128, 3), (16, 7),
-                                 (224, 256), (1056, 9), (320, 33)])
-@pytest.mark.parametrize("kernel", [1, 3, 4])
+# the lane-private histogram (<=32); L with power-of-two and other row widths;
+# every kernel that takes the shape: 1 strip (any L % 16 == 0), 3 LDS-resident
+# (L <= 256), 4 colour-split (L % 32 == 0)
+Q_EDGE_SHAPES = [(48, 16), (48, 17), (80, 32), (80, 33), (96, 64), (96, 65), (96, 128), (112, 129), (208, 256),
+                 (1040, 9), (64, 2), (128, 3), (16, 7), (224, 256), (1056, 9), (320, 33)]
+Q_EDGE_CASES = [(L, q, k) for (L, q) in Q_EDGE_SHAPES for k in (1, 3, 4)
+                if not (k == 3 and L > 256) and not (k == 4 and L % 32)]
+
+
+@pytest.mark.parametrize("L,q,kernel", Q_EDGE_CASES)
 def test_kernel_q_edges(potts, oracle_lib, L, q, kernel):
-    if kernel == 3 and L > 256:
-        pytest.skip("LDS-resident kernel holds L <= 256")
-    if kernel == 4 and L % 32:
-        pytest.skip("colour-split kernel needs L % 32 == 0")
     seed, beta, n = 6, 0.9, 7
     _say(f"q-edge L={L} q={q} kernel={kernel}")
     want_spins, want_rec = oracle_lib.run(L, q, seed, 1, beta, n)
