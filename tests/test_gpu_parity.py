@@ -171,13 +171,18 @@ def test_derived_stats_match_oracle(potts, oracle_lib, window):
         assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-300), k
 
 
-def test_large_lattice_sampled_windows(potts, oracle_lib):
-    """L = 32768 (the single-large-lattice workload): sampled windows against the
-    oracle's window restriction, plus whole-lattice invariants."""
+@pytest.mark.parametrize("start,torch_buffers", [(1, False), (0, True)])
+def test_large_lattice_sampled_windows(potts, oracle_lib, start, torch_buffers):
+    """L = 32768 (the single-large-lattice workload, both of its starts; the
+    ordered one on torch-owned buffers and stream, as the benchmark builds
+    it): sampled windows against the oracle's window restriction, plus
+    whole-lattice invariants."""
     L, q, seed, beta, n = 32768, 6, 1, beta_c(6), 2
-    _say(f"large L={L} q={q} n={n}")
+    _say(f"large L={L} q={q} n={n} start={start}")
     thr = oracle_lib.threshold_table(beta)
-    with potts.Lattice(L, q, seed, 1) as lat:
+    make = potts.Lattice.from_torch if torch_buffers else potts.Lattice
+    with make(L, q, seed, start) as lat:
+        lat.tune(kernel=0)
         lat.sweep(beta, n)
         rec = lat.records(0, n)
         spins = lat.spins()
@@ -189,7 +194,7 @@ def test_large_lattice_sampled_windows(potts, oracle_lib):
     r = 2 * n
     for (x0, y0) in [(0, 0), (L - 20, L - 13), (12345, 777), (L // 2, L - 30), (4096, 0)]:
         h = w = 48
-        win = oracle_lib.window(L, q, seed, 1, n, thr, x0, y0, h, w)
+        win = oracle_lib.window(L, q, seed, start, n, thr, x0, y0, h, w)
         ys = (y0 + np.arange(r, h - r)) % L
         xs = (x0 + np.arange(r, w - r)) % L
         assert np.array_equal(win[r:h - r, r:w - r], spins[np.ix_(ys, xs)]), (x0, y0)
