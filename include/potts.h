@@ -235,7 +235,11 @@ int potts_ramp(potts_state *s, const double *betas, int32_t npoints, int64_t t_e
 int potts_get_spins(potts_state *s, uint8_t *host_out);
 int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t);
 
-/* Device pointer of the current lattice (valid until the next sweep call). */
+/* Device pointer of the current lattice, row-major (valid until the next
+ * sweep call).  After colour-split sweeps this first queues the kernel that
+ * rebuilds the row-major lattice on the state's stream: read the buffer on
+ * that stream or after synchronizing it.  NULL if s is NULL or the kernel
+ * could not be queued. */
 void *potts_device_spins(potts_state *s);
 int64_t potts_time(const potts_state *s);
 

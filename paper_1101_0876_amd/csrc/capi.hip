@@ -34,6 +34,11 @@ struct potts_state {
   int kernel = 0;          // 0 automatic, 1 strip, 2 chunk, 3 LDS-resident
   uint32_t rows = 0;       // strip rows per work item, 0 = automatic
   unsigned max_groups = 0; // persistent grid size, 0 = automatic
+  // The colour-split kernel works on a copy of the lattice in spins2 split
+  // into its two colour planes; the row-major lattice in spins is rebuilt
+  // only when something reads it, and the copy only when it is stale.
+  bool spins_valid = true;    // spins holds the current configuration
+  bool planes_valid = false;  // spins2 holds it, colour-split
 };
 
 namespace {
@@ -65,6 +70,14 @@ int hip_fail(hipError_t e, const char *what) {
     hipError_t hip_err_ = (call);                      \
     if (hip_err_ != hipSuccess) return hip_fail(hip_err_, #call); \
   } while (0)
+
+// Makes the row-major lattice current (queued on the state's stream).
+int sync_spins(potts_state *s) {
+  if (s->spins_valid) return POTTS_OK;
+  HIP_TRY(potts::launch_unpack(s->spins2, s->spins, (uint32_t)s->L, s->stream));
+  s->spins_valid = true;
+  return POTTS_OK;
+}
 
 // The ring holds a power-of-two number of slots (>= the capacity asked for),
 // so kernels find a sweep's slot with a mask.
@@ -329,7 +342,11 @@ uint32_t packed_rows(const potts_state *s) {
 // sweep, unpack; records as the strip path (striped partial records).
 int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   const uint32_t L = (uint32_t)s->L;
-  HIP_TRY(potts::launch_pack(s->spins, s->spins2, L, s->stream));
+  if (!s->planes_valid) {
+    HIP_TRY(potts::launch_pack(s->spins, s->spins2, L, s->stream));
+    s->planes_valid = true;
+  }
+  s->spins_valid = false;
   potts::StripLaunch l{};
   potts::StripParams &p = l.single;
   const uint32_t rows = packed_rows(s);
@@ -355,7 +372,6 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     }
     HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
   }
-  HIP_TRY(potts::launch_unpack(s->spins2, s->spins, L, s->stream));
   s->t += nsweeps;
   return POTTS_OK;
 }
@@ -365,6 +381,12 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
+  if (!use_packed(s)) {
+    // every other kernel sweeps the row-major lattice
+    const int rc = sync_spins(s);
+    if (rc) return rc;
+    s->planes_valid = false;
+  }
   if (use_resident(s)) return run_resident(s, thr, nsweeps);
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
@@ -427,6 +449,11 @@ int run_heatbath(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
+  {
+    const int rc = sync_spins(s);
+    if (rc) return rc;
+    s->planes_valid = false;
+  }
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
   potts::SweepParams p{};
@@ -593,6 +620,8 @@ int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_g
 
 int potts_measure(potts_state *s, potts_obs *out) {
   if (!s || !out) return fail(POTTS_EINVAL, "NULL argument");
+  const int rc = sync_spins(s);
+  if (rc) return rc;
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->scratch, (uint64_t)rl, 0ull, s->stream));
   potts::MeasureParams p{};
@@ -774,6 +803,8 @@ int potts_ramp(potts_state *s, const double *betas, int32_t npoints, int64_t t_e
 
 int potts_get_spins(potts_state *s, uint8_t *host_out) {
   if (!s || !host_out) return fail(POTTS_EINVAL, "NULL argument");
+  const int rc = sync_spins(s);
+  if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(host_out, s->spins, (size_t)n_sites(s), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return POTTS_OK;
@@ -787,12 +818,17 @@ int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t) {
     if (host_in[i] >= s->q) return fail(POTTS_EINVAL, "spin value >= q");
   HIP_TRY(hipMemcpyAsync(s->spins, host_in, (size_t)n, hipMemcpyHostToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  s->spins_valid = true;
+  s->planes_valid = false;
   s->t = t;
   s->rec_from = t;
   return POTTS_OK;
 }
 
-void *potts_device_spins(potts_state *s) { return s ? (void *)s->spins : nullptr; }
+void *potts_device_spins(potts_state *s) {
+  if (!s || sync_spins(s)) return nullptr;
+  return (void *)s->spins;
+}
 
 int64_t potts_time(const potts_state *s) { return s ? s->t : -1; }
 

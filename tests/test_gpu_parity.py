@@ -149,11 +149,61 @@ def test_torch_buffers_and_stream(potts, oracle_lib):
     lat = potts.Lattice.from_torch(L, q, seed, 1, stream=stream)
     with lat:
         lat.sweep(beta, n)
+        ptr = lat.device_ptr()  # may queue work on the stream: synchronize after it
         stream.synchronize()
         a, _, _ = lat._keep
-        assert lat.device_ptr() == a.data_ptr()
+        assert ptr == a.data_ptr()
         assert np.array_equal(a.cpu().numpy().reshape(L, L), want_spins)
         assert np.array_equal(lat.records(0, n), want_rec)
+
+
+def test_colour_split_copy_stays_in_step(potts, oracle_lib):
+    """Single colour-split sweeps keep the lattice split into colour planes
+    between calls; every read (spins, measure, device pointer), a switch to
+    other kernels and set_spins must see and continue the same chain."""
+    import torch
+
+    L, q, seed, beta = 512, 7, 29, beta_c(7)
+    thr = oracle_lib.threshold_table(beta)
+    s = oracle_lib.init(L, q, seed, 1)
+    t = 0
+
+    def oracle_sweeps(n):
+        nonlocal t
+        oracle_lib.sweeps(s, q, seed, t, n, thr, record=False)
+        t += n
+
+    with potts.Lattice.from_torch(L, q, seed, 1) as lat:
+        for n in (1, 1, 2):
+            lat.sweep(beta, n)
+            oracle_sweeps(n)
+        assert np.array_equal(lat.spins(), s)
+        lat.sweep(beta, 1)
+        oracle_sweeps(1)
+        e, hist = oracle_lib.observables(s, q)
+        m = lat.measure()
+        assert m["e_sat"] == e and np.array_equal(m["hist"], hist)
+        lat.sweep(beta, 1)
+        oracle_sweeps(1)
+        a, b, _ = lat._keep
+        ptr = lat.device_ptr()
+        torch.cuda.synchronize()
+        cur = a if ptr == a.data_ptr() else b
+        assert np.array_equal(cur[:L * L].cpu().numpy().reshape(L, L), s)
+        for kernel, n in ((1, 2), (4, 1), (2, 1), (0, 3)):
+            lat.tune(kernel=kernel)
+            lat.sweep(beta, n)
+            oracle_sweeps(n)
+        lat.sweep(beta, 1)
+        oracle_sweeps(1)
+        # overwrite the lattice mid-chain and continue from a new counter
+        s[:] = np.random.default_rng(3).integers(0, q, (L, L), dtype=np.uint8)
+        t = 40
+        lat.set_spins(s, t)
+        lat.sweep(beta, 2)
+        oracle_sweeps(2)
+        assert lat.t == t
+        assert np.array_equal(lat.spins(), s)
 
 
 @pytest.mark.parametrize("window", [(0, 200), (150, 400), (7, 8)])
