@@ -2,7 +2,8 @@
 exact values the paper prints.
 
 Table 2 lists, for q = 6, 9, 15, 96, the exact energies per site of the
-ordered and disordered phases at T_c (Eq. 2, Eq. 3, Eq. 6).  At beta_c an
+ordered and disordered phases at T_c (Eq. 2, Eq. 3, Eq. 6) and the jump of
+the order parameter (Eq. 8).  At beta_c an
 ordered start stays in the ordered phase and a random start in the disordered
 one on these time scales (first-order transition, L much larger than the
 correlation length), so the mean energy of the second half of the run must
@@ -31,6 +32,10 @@ def table2():
         if parts and parts[0] == "table2":
             out[int(parts[1])] = (-float(parts[2]), -float(parts[3]))  # (e_o, e_d)
     return out
+
+
+def table2_dm():
+    return {int(p[1]): float(p[2]) for p in (line.split() for line in open(GOLDEN)) if p and p[0] == "table2dm"}
 
 
 @pytest.fixture(scope="module")
@@ -62,3 +67,25 @@ def test_table2_phase_energies_at_beta_c(potts, q, n, tol, start):
     # the other phase is far away: the run did not switch phase
     other = e_d if start == potts.ORDERED else e_o
     assert abs(s["e"] - other) > 0.1
+
+
+@pytest.mark.parametrize("q,n,tol", [(9, 100000, 1.5e-3), (15, 20000, 6e-4), (96, 20000, 1e-4)])
+def test_table2_order_parameter_jump(potts, q, n, tol):
+    """The jump of the order parameter (Eq. 7) at T_c, as Table 2 reads it:
+    <m> of the ordered phase (ordered start at beta_c, second half of the run)
+    against the exact Delta m, the disordered phase (random start) having
+    <m> -> 0 (here only the O(1/L) excess of the largest population).
+    Measured on MI355X: m_o - Delta m = -5.6e-4, -2.1e-4, +3.2e-5 and m_d =
+    2.0e-3, 7.6e-4, 1.7e-4 for q = 9, 15, 96; the tolerances are about three
+    times those deviations."""
+    L, seed = 2048, 11
+    m = {}
+    for start in (0, 1):
+        print(f"table2 dm q={q} start={start} n={n}", flush=True)
+        with potts.Lattice(L, q, seed, start) as lat:
+            lat.reserve_records(n // 2 + 2)
+            lat.sweep(beta_c(q), n)
+            m[start] = lat.stats(n - n // 2, n // 2, beta_c(q))["m"]
+    print(f"q={q} m_o={m[0]:.6f} m_d={m[1]:.6f} want={table2_dm()[q]}", flush=True)
+    assert abs(m[0] - table2_dm()[q]) < tol, (m, table2_dm()[q])
+    assert 0.0 <= m[1] < 5e-3, m
