@@ -699,13 +699,79 @@ def run_nnn(args):
             "event_ms": ev_ms, "cpu_baseline": cpu}
 
 
+def run_e2e(args):
+    """The paper's end-to-end run (Sec. 5): q = 9, L = 1024, 3 samples, T from
+    0.71 to 0.73 in steps of 0.002 (11 points), at each point 2000
+    equilibration and 8000 measurement sweeps, heating from the ordered start
+    (Sec. 3), the state carried from point to point; the three samples run
+    concurrently (one host thread and stream each).  Every measurement sweep
+    is recorded (the paper samples every 50th).  Value: wall seconds of the
+    whole run (all samples, all points, per-point statistics included); the
+    paper's own run took 193 s on its GPU and 8115 s on its CPU.  The oracle
+    times a bounded sample of the same protocol on one host core."""
+    import paper_1101_0876_amd as potts
+
+    L, q, samples = 1024, 9, 3
+    temps = [0.71 + 0.002 * k for k in range(11)]
+    betas = [1.0 / T for T in temps]
+    t_tran, t_max = 2000, 8000
+    # warm-up: one short ramp on a throwaway lattice (module load, first launches)
+    with potts.Lattice(L, q, 99, potts.ORDERED) as lat:
+        lat.ramp(betas[:2], 2, 2)
+    # the samples are independent: one host thread and one state (own stream)
+    # each, so their launches and kernels overlap
+    from concurrent.futures import ThreadPoolExecutor
+
+    lats = [potts.Lattice(L, q, s + 1, potts.ORDERED) for s in range(samples)]
+    for lat in lats:
+        lat.reserve_records(t_max + 2)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=samples) as pool:
+        curves = list(pool.map(lambda lat: lat.ramp(betas, t_tran, t_max), lats))
+    wall = time.perf_counter() - t0
+    for lat in lats:
+        lat.close()
+    sweeps = samples * len(temps) * (t_tran + t_max)
+    e_mean = [sum(c[k]["e"] for c in curves) / samples for k in range(len(temps))]
+    m_mean = [sum(c[k]["m"] for c in curves) / samples for k in range(len(temps))]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        # the same protocol on the oracle: first point, first sample, as many
+        # sweeps as fit the time budget
+        spins = oracle.init(L, q, 1, oracle.ORDERED)
+        thr = oracle.threshold_table(betas[0])
+        n, t1 = 0, time.perf_counter()
+        while True:
+            oracle.sweeps(spins, q, 1, n, 1, thr, record=True)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= args.cpu_seconds or n >= 200:
+                break
+        per_sweep = el / n
+        cpu = {"value": per_sweep * sweeps, "unit": "s (extrapolated whole run)", "cores": 1, "kind": "oracle",
+               "sample": f"L={L} q={q} T={temps[0]} ordered start, {n} sweeps with records timed, "
+                         f"x {sweeps} sweeps of the run, 1 thread"}
+    return {"metric": "end-to-end run time", "value": wall, "unit": "s", "n_gpus": 1, "steps": sweeps, "warmup": 1,
+            "ms_per_step": wall * 1e3 / sweeps, "higher_is_better": False, "scaling": "strong",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "end-to-end heating ramp", "q": q, "L": L, "samples": samples,
+                       "T": [round(T, 3) for T in temps], "t_tran": t_tran, "t_max": t_max,
+                       "start": "ordered", "records": "every sweep"},
+            "ns_per_spin_flip": wall * 1e9 / (sweeps * L * L),
+            "curve": {"T": [round(T, 3) for T in temps], "e": e_mean, "m": m_mean},
+            "paper_context": {"gpu_s": 193, "cpu_s": 8115, "hardware": "GTX 280 / Core 2 Duo E8400"},
+            "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
-                                                     "metastability", "heatbath", "cubic", "nnn"])
+                                                     "metastability", "heatbath", "cubic", "nnn", "e2e"])
     ap.add_argument("--kernel", type=int, default=0,
                     help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split; "
                          "cubic: 0 automatic (colour-split), 1 colour-split, 2 chunk")
@@ -742,6 +808,9 @@ def main():
         return
     if args.workload == "nnn":
         print(json.dumps(run_nnn(args)), flush=True)
+        return
+    if args.workload == "e2e":
+        print(json.dumps(run_e2e(args)), flush=True)
         return
     if args.workload == "metastability":
         print(json.dumps(run_metastability(args)), flush=True)
