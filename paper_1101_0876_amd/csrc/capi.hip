@@ -329,13 +329,16 @@ uint32_t strip_rows(const potts_state *s) {
 // rows per item of the colour-split kernel (32 sites per item row): the
 // tallest of 32, 16, 8 that still gives 2^20 items (4096 workgroups), else 4.
 // Measured on MI355X (q = 6): L = 4096 / 8192 / 16384 / 32768 run at
-// 1.69 / 0.95 / 0.82 / 0.85 ps per site update with 4 / 4 / 8 / 32 rows.
+// 1.69 / 0.95 / 0.82 / 0.85 ps per site update with 4 / 4 / 8 / 32 rows.  Up to
+// L = 4096 a sweep is bound by launch and per-workgroup overheads, and the
+// shortest walk (most workgroups) wins: q = 9, L = 1024 / 2048 / 4096 take
+// 12.8 / 14.3 / 27.4 us per sweep with 2 rows, 17.3 / 18.5 / 29.0 with 4.
 uint32_t packed_rows(const potts_state *s) {
   if (s->rows) return s->rows;
   const uint32_t L = (uint32_t)s->L;
   for (uint32_t r = 32; r >= 8; r /= 2)
     if (L % r == 0 && (uint64_t)(L / r) * (L / 32) >= (1ull << 20)) return r;
-  return 4;
+  return L <= 4096 ? 2 : 4;
 }
 
 // Sweeps on the colour-split copy in the second buffer (packed.hip): pack,
