@@ -12,8 +12,10 @@
 // sweep_row.hpp takes, which is reused unchanged (its Philox block and word
 // for active index i, chunk y*(L/4) + i/2 and pair i & 1, are the contract's).
 //
-// A run packs the lattice into the state's second buffer, sweeps there and
-// unpacks it at the end; both copies are plain streaming kernels.
+// A single lattice is packed into the state's second buffer before its first
+// colour-split sweep and unpacked only when the row-major lattice is read
+// (capi.hip); batches pack their jobs before a run and unpack them after it.
+// Both copies are plain streaming kernels.
 //
 // Work item: 16 packed bytes (16 active sites) of R consecutive rows of the
 // active plane, walked downwards like the strip kernel: each passive row is
