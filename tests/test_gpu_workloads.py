@@ -1,0 +1,53 @@
+"""The batched-replicas workload at its full configuration, in the launch
+configuration the benchmark times (1024 jobs of L = 128 .. 4096, 500 sweeps,
+one batch with hipGraph and in-run tuning): sampled jobs against the oracle
+(the smallest lattices, every record and the final spins), the largest jobs
+against the same job run alone, and properties of every job."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def potts():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1101_0876_amd as p
+
+    p.load()
+    return p
+
+
+def test_batch_full_configuration(potts, oracle_lib):
+    from paper_1101_0876_amd.workloads import batch_jobs
+
+    jobs = batch_jobs()
+    assert len(jobs) == 1024 and all(j["nsweeps"] == 500 for j in jobs)
+    print("batch full configuration: 1024 jobs", flush=True)
+    by_size = sorted(range(len(jobs)), key=lambda i: (jobs[i]["L"], i))
+    small, large = by_size[:3], by_size[-2:]
+    with potts.Batch(jobs, graph=True, tune=True) as b:
+        b.run()
+        res = b.results()
+        for i, (r, j) in enumerate(zip(res, jobs)):
+            assert r["t"] == 500
+            last = b.records(i, 499, 1)
+            assert int(last[0, 1:].sum()) == j["L"] ** 2, i
+            assert r["e_sat"] == last[0, 0] and 0 <= r["e_sat"] <= 2 * j["L"] ** 2
+        for i in small:
+            j = jobs[i]
+            print(f"oracle job {i}: L={j['L']} q={j['q']}", flush=True)
+            s = oracle_lib.init(j["L"], j["q"], j["seed"], j["start"])
+            rec = oracle_lib.sweeps(s, j["q"], j["seed"], 0, 500, oracle_lib.threshold_table(j["beta"]))
+            assert np.array_equal(b.records(i, 0, 500), rec), i
+            assert np.array_equal(b.spins(i), s), i
+        for i in large:
+            j = jobs[i]
+            print(f"alone job {i}: L={j['L']} q={j['q']}", flush=True)
+            with potts.Lattice(j["L"], j["q"], j["seed"], j["start"]) as lat:
+                lat.sweep(j["beta"], 500)
+                assert np.array_equal(lat.records(0, 500), b.records(i, 0, 500)), i
+                assert np.array_equal(lat.spins(), b.spins(i)), i
