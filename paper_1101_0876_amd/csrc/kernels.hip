@@ -108,6 +108,10 @@ __global__ __launch_bounds__(kBlock) void sweep4_kernel(SweepParams p) {
 // weigh D[n_max], so that run is indexed with one division and the j-th
 // value outside the (at most four) neighbour values is found by fixed-point
 // iteration of k = j + #{excluded values <= k}.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(uint8_t *p) {
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)0xFFFFFFFFu, 0x00020000);
+}
+
 __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
                                                   uint32_t w, const Thresholds &thr, const double inv[4]) {
   const uint32_t na = 1 + (a == b) + (a == c) + (a == d);
@@ -130,23 +134,37 @@ __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32
   const uint64_t Z = S + (uint64_t)(q - m) * w0;  // < 2^41
   // r = floor(w Z / 2^32), exactly, from the two halves of Z
   const uint64_t r = (uint64_t)w * (Z >> 32) + (((uint64_t)w * (Z & 0xFFFFFFFFull)) >> 32);
-  if (r < wa) return a;
-  if (r < wa + wb) return b;
-  if (r < wa + wb + wc) return c;
-  if (r < S) return d;
-  // j = floor(X / w0) for X = r - S < (q - m) w0 (so w0 > 0 and j < 256): X
-  // and w0 are exact doubles and inv = 1/w0 rounded, so X * inv is within a
-  // few ulp of X / w0 and its floor is j - 1, j or j + 1; one integer check
-  // each way makes it exact
-  const uint64_t X = r - S;
+  // past the neighbour values: j = floor(X / w0) for X = r - S < (q - m) w0
+  // (so w0 > 0 and j < 256).  X and w0 are exact doubles and inv = 1/w0
+  // rounded, so X * inv is within a few ulp of X / w0 and its floor is j - 1,
+  // j or j + 1; one integer check each way makes it exact.  Computed for every
+  // lane (no divergent branch); lanes that stopped earlier discard it.
+  const uint64_t X = r >= S ? r - S : 0;
   uint32_t j = (uint32_t)((double)X * inv[nmax - 1]);
   if ((uint64_t)j * w0 > X) --j;
   else if ((uint64_t)(j + 1) * w0 <= X) ++j;
+  // the j-th value that no neighbour holds: with the (at most four) distinct
+  // neighbour values in ascending order, each one at or below the running
+  // candidate moves it up by one
+  const uint32_t kNone = 0x100u;  // above every value
+  uint32_t e0 = a, e1 = fb ? b : kNone, e2 = fc ? c : kNone, e3 = fd ? d : kNone;
+  auto order = [](uint32_t &x, uint32_t &y) {
+    const uint32_t lo = min(x, y), hi = max(x, y);
+    x = lo;
+    y = hi;
+  };
+  order(e0, e1);
+  order(e2, e3);
+  order(e0, e2);
+  order(e1, e3);
+  order(e1, e2);
   uint32_t k = j;
-#pragma unroll
-  for (int it = 0; it < 5; ++it)
-    k = j + (a <= k) + (fb && b <= k) + (fc && c <= k) + (fd && d <= k);
-  return k;
+  k += e0 <= k;
+  k += e1 <= k;
+  k += e2 <= k;
+  k += e3 <= k;
+  const uint64_t sab = wa + wb, sabc = sab + wc;
+  return r < wa ? a : r < sab ? b : r < sabc ? c : r < S ? d : k;
 }
 
 // Grid: x over the chunks of a row, y strided over the rows (no division per
@@ -168,15 +186,20 @@ __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
   uint32_t e = 0;
   if (j < cpr) {
     const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
+    const uint32_t oj = 4 * j, ol = 4 * jl, orr = 4 * jr;
     for (uint32_t y = blockIdx.y; y < L; y += gridDim.y) {
       const uint32_t yu = y == 0 ? L - 1 : y - 1;
       const uint32_t yd = y + 1 == L ? 0 : y + 1;
-      uint32_t *row = reinterpret_cast<uint32_t *>(p.spins + (size_t)y * L);
-      const uint32_t up = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yu * L)[j];
-      const uint32_t dn = reinterpret_cast<const uint32_t *>(p.spins + (size_t)yd * L)[j];
-      const uint32_t cur = row[j];
-      const uint32_t left = __builtin_amdgcn_alignbyte(cur, row[jl], 3);   // byte i: spin at x-1
-      const uint32_t right = __builtin_amdgcn_alignbyte(row[jr], cur, 1);  // byte i: spin at x+1
+      // the rows are the same for the whole workgroup: buffer resources in
+      // scalar registers, 32-bit lane offsets
+      const __amdgpu_buffer_rsrc_t row = row_rsrc(p.spins + (size_t)y * L);
+      const uint32_t up = __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(p.spins + (size_t)yu * L), oj, 0, 0);
+      const uint32_t dn = __builtin_amdgcn_raw_buffer_load_b32(row_rsrc(p.spins + (size_t)yd * L), oj, 0, 0);
+      const uint32_t cur = __builtin_amdgcn_raw_buffer_load_b32(row, oj, 0, 0);
+      const uint32_t left =  // byte i: spin at x-1
+          __builtin_amdgcn_alignbyte(cur, __builtin_amdgcn_raw_buffer_load_b32(row, ol, 0, 0), 3);
+      const uint32_t right =  // byte i: spin at x+1
+          __builtin_amdgcn_alignbyte(__builtin_amdgcn_raw_buffer_load_b32(row, orr, 0, 0), cur, 1);
 
       const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
       const uint32_t o = (COLOUR + y) & 1u;  // byte of the first active site; the second is o + 2
@@ -189,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
         out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
         if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
       }
-      row[j] = out;
+      __builtin_amdgcn_raw_buffer_store_b32(out, row, oj, 0, 0);
       if (COLOUR == 1)
         for (uint32_t bb = 0; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
     }
