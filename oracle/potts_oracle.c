@@ -586,13 +586,20 @@ int oracle3d_window(int L, int q, uint64_t seed, int start, int64_t nsweeps, con
  *     (d1 + 4) * 9 + (d2 + 4) = 2^32 when dE <= 0 (always accept), else
  *     min(floor(exp(-beta dE) 2^32), 2^32 - 1); a move is accepted iff
  *     w_acc < entry;
- *   - Philox block per (4-byte row chunk, sweep, colour): counter
- *     (t_lo, y L/4 + x/4, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
- *     b = (x & 3) >> 1 (the only two sites of one colour in a chunk sit at
- *     x & 3 = 0 and 3);
+ *   - Philox block per (6-byte row segment, sweep, colour): counter
+ *     (t_lo, y L/6 + x/6, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
+ *     b = (x/3) & 1 (a segment holds exactly two sites of each colour, at
+ *     x mod 6 = x mod 3 and x mod 3 + 3);
  *   - the initial conditions are those of the nearest-neighbour lattice;
  *   - records {e1, e2, hist[q]}: satisfied nearest-neighbour bonds (2N),
  *     satisfied diagonal bonds (2N) and the populations. */
+static void segment_words(int L, int x, int y, uint64_t seed, uint32_t c0, uint32_t c2, uint32_t c3, uint32_t w[4])
+{
+    const uint32_t ctr[4] = {c0, (uint32_t)((uint64_t)y * (uint64_t)(L / 6) + (uint64_t)(x / 6)), c2, c3};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, w);
+}
+
 static int valid_nnn(int L, int q)
 {
     return L >= 12 && L % 12 == 0 && (uint64_t)L * (uint64_t)L / 4 < ((uint64_t)1 << 32) && q >= 2 && q <= 256;
@@ -646,8 +653,8 @@ int oracle_nnn_colour_pass(int L, int q, uint64_t seed, uint64_t t, int colour, 
             const uint8_t nb2[4] = {spins[(size_t)yu * L + xl], spins[(size_t)yu * L + xr],
                                     spins[(size_t)yd * L + xl], spins[(size_t)yd * L + xr]};
             uint32_t w[4];
-            chunk_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), 16u + (uint32_t)colour, w);
-            const int b = (x & 3) >> 1;
+            segment_words(L, x, y, seed, (uint32_t)t, (uint32_t)(t >> 32), 16u + (uint32_t)colour, w);
+            const int b = (x / 3) & 1;
             const size_t i = (size_t)y * L + x;
             spins[i] = (uint8_t)oracle_nnn_site_update(q, spins[i], nb1, nb2, w[2 * b], w[2 * b + 1], thr);
         }

@@ -123,13 +123,27 @@ def test_colour_pass_wiring(oracle_lib, colour):
             if 3 * (y % 3) + (x % 3) != colour:
                 assert after[y, x] == before[y, x]
                 continue
-            w = oracle_lib.philox4x32_10([t & 0xFFFFFFFF, y * (L // 4) + x // 4, t >> 32, 16 + colour], key)
-            b = (x & 3) >> 1
+            w = oracle_lib.philox4x32_10([t & 0xFFFFFFFF, y * (L // 6) + x // 6, t >> 32, 16 + colour], key)
+            b = (x // 3) & 1
             want = oracle_lib.nnn_site_update(q, int(before[y, x]), [n[y, x] for n in near], [n[y, x] for n in diag],
                                               int(w[2 * b]), int(w[2 * b + 1]), thr)
             assert after[y, x] == want, (x, y)
             moved += want != before[y, x]
     assert moved > 0
+
+
+def test_each_block_serves_two_sites_per_colour():
+    """The counter layout: within one colour pass every Philox block (row y,
+    segment x // 6) serves exactly two sites, with the two word pairs."""
+    L = 36
+    for colour in range(9):
+        cy, cx = divmod(colour, 3)
+        seen = {}
+        for y in range(cy, L, 3):
+            for x in range(cx, L, 3):
+                seen.setdefault(y * (L // 6) + x // 6, []).append((x // 3) & 1)
+        assert all(sorted(v) == [0, 1] for v in seen.values())
+        assert len(seen) == (L // 3) * (L // 3) // 2
 
 
 def test_observables_brute_force(oracle_lib):
