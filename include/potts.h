@@ -467,9 +467,10 @@ void potts3d_free(potts3d_state *s);
  *     (d1 + 4) * 9 + (d2 + 4) the value 2^32 when d1 + j2 d2 <= 0, else
  *     min(floor(exp(-beta (d1 + j2 d2)) 2^32), 2^32 - 1), computed in FP64 on
  *     the host; a move is accepted iff w_acc < entry;
- *   - one Philox4x32-10 block per 4-byte row chunk, sweep and colour: counter
- *     (t_lo, y L/4 + x/4, t_hi, 16 + c), key (seed_lo, seed_hi); site x takes
- *     (w[2b], w[2b+1]), b = (x & 3) >> 1, as proposal and acceptance words;
+ *   - one Philox4x32-10 block per 6-byte row segment, sweep and colour:
+ *     counter (t_lo, y L/6 + x/6, t_hi, 16 + c), key (seed_lo, seed_hi); site
+ *     x takes (w[2b], w[2b+1]), b = (x/3) & 1, as proposal and acceptance
+ *     words (a segment holds two sites of each colour);
  *   - initial conditions as potts_init;
  *   - records {e1, e2, hist[0..q)} per sweep: satisfied nearest bonds (2N),
  *     satisfied diagonal bonds (2N), populations.
@@ -511,6 +512,13 @@ int potts_nnn_observables(potts_nnn_state *s, potts_nnn_obs *out);
 
 /* Copies the lattice (L*L bytes, row-major) to host memory (synchronizes). */
 int potts_nnn_get_spins(potts_nnn_state *s, uint8_t *host_out);
+
+/* Kernel choice for later sweeps; every choice gives identical spins and
+ * records.  0: automatic (1 when L <= 16380, else 2); 1: one launch per row
+ * class y mod 3 doing its three colours with rows y-1, y, y+1 staged in LDS;
+ * 2: one launch per colour, reading the lattice in place.  Errors: EINVAL
+ * (kernel outside 0..2, kernel 1 with L > 16380). */
+int potts_nnn_tune(potts_nnn_state *s, int32_t kernel);
 
 /* Sweeps done so far, or -1 for NULL. */
 int64_t potts_nnn_time(const potts_nnn_state *s);

@@ -293,6 +293,11 @@ class NnnLattice:
         check(self._lib.potts_nnn_sweep_thr(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                             int(nsweeps)))
 
+    def tune(self, kernel: int = 0) -> None:
+        """0 automatic, 1 row class staged in LDS (L <= 16380), 2 one launch
+        per colour; all give identical results."""
+        check(self._lib.potts_nnn_tune(self._h, int(kernel)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts_nnn_time(self._h))

@@ -185,6 +185,7 @@ SIGNATURES = [
     ("potts_nnn_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
     ("potts_nnn_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsNnnObs)]),
     ("potts_nnn_get_spins", ctypes.c_int, [_VP, _U8P]),
+    ("potts_nnn_tune", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("potts_nnn_time", ctypes.c_int64, [_VP]),
     ("potts_nnn_stream", _VP, [_VP]),
     ("potts_nnn_free", None, [_VP]),

@@ -9,21 +9,24 @@
 //     nearest/diagonal neighbours from the current value to the proposal:
 //     2^32 when d1 + j2 d2 <= 0, else min(floor(exp(-beta (d1 + j2 d2)) 2^32),
 //     2^32 - 1); accept iff w_acc < entry;
-//   - Philox block per (4-byte row chunk, sweep, colour): counter (t_lo,
-//     y L/4 + x/4, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
-//     b = (x & 3) >> 1; initial conditions as on the nearest-neighbour lattice;
+//   - Philox block per (6-byte row segment, sweep, colour): counter (t_lo,
+//     y L/6 + x/6, t_hi, 16 + colour); site x takes (w[2b], w[2b+1]),
+//     b = (x/3) & 1 (a segment holds two sites of each colour); initial
+//     conditions as on the nearest-neighbour lattice;
 //   - records {e1, e2, hist[q]} per sweep: nearest and diagonal satisfied
 //     bonds (2N each) and the populations.
 //
-// Kernels: a colour pass runs one thread per 4-byte chunk of the rows of its
-// colour (each holds one or two active sites, served by one Philox block); all
-// eight neighbours are bytes of the chunk's own dword and its two neighbours
-// in rows y-1, y, y+1, shifted into place with v_alignbyte, and compared four
-// sites at a time.  Bytes of the same row that a neighbouring
-// thread rewrites are never neighbours of an active site (they hold other
-// colours and are written back unchanged), so the pass is race-free.  The
-// record of a sweep comes from one measurement kernel after its nine passes
-// (partial sums in striped slots, folded by a one-block kernel).
+// Kernels: up to L = 16380 one launch per row class (y mod 3) does the
+// three colours of that class with the three rows around each active row in
+// LDS (below).  Beyond that, a colour pass runs one thread per 6-byte segment
+// of the rows of its colour: the segment's two active sites (x0 = 6m + cx and x0 + 3) and
+// their neighbours are the six bytes x0-1 .. x0+4 of rows y-1, y, y+1, read
+// as three dwords per row and shifted into place with v_alignbyte and v_perm
+// (byte 0: the first site's view, byte 1: the second's); both sites are
+// compared at once as flag patterns and written back with byte stores, so
+// neighbouring threads never rewrite each other's bytes.  The record of a
+// sweep comes from one measurement kernel after its nine passes (partial sums
+// in striped slots, folded by a one-block kernel).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -47,6 +50,7 @@ struct potts_nnn_state {
   int64_t rec_cap = 0;
   unsigned long long *scratch = nullptr;  // 2 + q words for measurements
   unsigned long long *stripes = nullptr;  // kStripes partial records of 2 + q words, kept zero between sweeps
+  int32_t kernel = 0;  // 0 automatic, 1 row class in LDS, 2 segment per colour
   bool have_thr = false;
   double thr_beta = 0.0, thr_j2 = 0.0;
   uint64_t thr[81] = {};
@@ -60,8 +64,10 @@ namespace {
 
 using potts::PhiloxHead;
 using potts::row::diff_pattern;
+using potts::row::alignbyte;
 using potts::row::lattice_rsrc;
 using potts::row::load4;
+using potts::row::perm;
 using potts::Words;
 using potts::byte_of;
 using potts::count_equal;
@@ -92,61 +98,165 @@ __device__ __forceinline__ uint32_t alignb(uint32_t hi, uint32_t lo, uint32_t sh
   return __builtin_amdgcn_alignbyte(hi, lo, shift);
 }
 
-// Grid: x over the chunks of a row, y over the rows of the pass's colour.
-// The four neighbour groups are compared with the current value and the
-// proposal as byte-wise "differs" flag patterns (bits 7..4 of every byte, the
-// row kernels' diff_pattern, CMP by q); an active byte's counts are the
-// popcounts of its pattern byte: d1 = n1(s) - n1(k) = diff1(k) - diff1(s).
+// Grid: x over the segments of a row, y over the rows of the pass's colour.
+// The four neighbour groups are compared with the current values and the
+// proposals as byte-wise "differs" flag patterns (bits 7..4 of every byte, the
+// row kernels' diff_pattern, CMP by q); a site's counts are the popcounts of
+// its pattern byte: d1 = n1(s) - n1(k) = diff1(k) - diff1(s).
 template <int CMP>
 __global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
   __shared__ uint64_t table[81];
   for (uint32_t i = threadIdx.x; i < 81; i += kBlock) table[i] = p.thr[i];
   __syncthreads();
-  const uint32_t L = p.g.L, cpr = L >> 2;
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= cpr) return;
+  const uint32_t L = p.g.L, cpr = L >> 2, spr = L / 6;
+  const uint32_t m = blockIdx.x * kBlock + threadIdx.x;
+  if (m >= spr) return;
   const uint32_t cy = p.colour / 3, cx = p.colour - 3 * cy;
   const uint32_t y = 3 * blockIdx.y + cy;
   const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
-  const uint32_t jl = j == 0 ? cpr - 1 : j - 1, jr = j + 1 == cpr ? 0 : j + 1;
-  // the three rows are the same for the whole workgroup: one buffer resource
-  // each (scalar registers), 32-bit lane offsets, no 64-bit address math
+  // the rows are the same for the whole workgroup: buffer resources in scalar
+  // registers, 32-bit lane offsets
   const __amdgpu_buffer_rsrc_t row = lattice_rsrc(p.g.spins + (size_t)y * L);
   const __amdgpu_buffer_rsrc_t up = lattice_rsrc(p.g.spins + (size_t)yu * L);
   const __amdgpu_buffer_rsrc_t dn = lattice_rsrc(p.g.spins + (size_t)yd * L);
-  const uint32_t oj = 4 * j, ol = 4 * jl, orr = 4 * jr;
-  const uint32_t cur = load4(row, oj);
-  const uint32_t U = load4(up, oj), D = load4(dn, oj);
-  // byte i of each: the neighbour of site x = 4j + i
-  const uint32_t left = alignb(cur, load4(row, ol), 3), right = alignb(load4(row, orr), cur, 1);
-  const uint32_t ul = alignb(U, load4(up, ol), 3), ur = alignb(load4(up, orr), U, 1);
-  const uint32_t dl = alignb(D, load4(dn, ol), 3), dr = alignb(load4(dn, orr), D, 1);
+  // window: bytes x0-1 .. x0+4 (periodic), from three dwords starting at d0
+  const uint32_t x0 = 6 * m + cx;
+  const uint32_t w0 = x0 == 0 ? L - 1 : x0 - 1;
+  const uint32_t d0 = w0 >> 2, sh = w0 & 3u;
+  const uint32_t o0 = 4 * d0, o1 = 4 * (d0 + 1 == cpr ? 0 : d0 + 1), o2 = 4 * (d0 + 2 >= cpr ? d0 + 2 - cpr : d0 + 2);
+  // per row: (centre, left, right) dwords whose byte 0 is the first site's
+  // view (x0 + 0, -1, +1) and byte 1 the second site's (x0 + 3 + 0, -1, +1)
+  auto views = [&](const __amdgpu_buffer_rsrc_t &r, uint32_t &c, uint32_t &l, uint32_t &rt) {
+    const uint32_t a = load4(r, o0), b = load4(r, o1), d = load4(r, o2);
+    const uint32_t lo = alignbyte(b, a, sh), hi = alignbyte(d, b, sh);  // window bytes 0..3, 4..7
+    c = perm(hi, lo, 0x0C0C0401u);   // bytes 1, 4
+    l = perm(hi, lo, 0x0C0C0300u);   // bytes 0, 3
+    rt = perm(hi, lo, 0x0C0C0502u);  // bytes 2, 5
+  };
+  uint32_t cur, left, right, U, ul, ur, D, dl, dr;
+  views(row, cur, left, right);
+  views(up, U, ul, ur);
+  views(dn, D, dl, dr);
 
   const PhiloxHead h = philox_head(p.t_lo, p.t_hi, 16u + p.colour, p.g.k0, p.g.k1);
-  const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
-  // active bytes: x = 4j + i with x mod 3 == cx (4j mod 3 == j mod 3); the
-  // first at i0, a second at byte 3 when i0 == 0
-  const uint32_t i0 = (cx + 3u - j % 3u) % 3u;
-  const uint32_t k0 = scale_to_q(i0 == 2 ? w.w2 : w.w0, p.g.q);
-  const bool two = i0 == 0;
-  uint32_t prop = (cur & ~(0xFFu << (8 * i0))) | (k0 << (8 * i0));
-  if (two) prop = (prop & 0x00FFFFFFu) | (scale_to_q(w.w2, p.g.q) << 24);
+  const Words w = philox_tail(h.a0 ^ (y * spr + m), h);  // segment x0 / 6 == m
+  const uint32_t prop = scale_to_q(w.w0, p.g.q) | (scale_to_q(w.w2, p.g.q) << 8);
   const uint32_t s1 = diff_pattern<CMP>(cur, left, right, U, D), k1 = diff_pattern<CMP>(prop, left, right, U, D);
   const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
-  uint32_t out = cur;
-  {
-    const uint32_t m = 0xF0u << (8 * i0);
-    const int d1 = __popc(k1 & m) - __popc(s1 & m), d2 = __popc(k2 & m) - __popc(s2 & m);
-    const uint32_t wacc = i0 == 2 ? w.w3 : w.w1;
-    const uint32_t bm = 0xFFu << (8 * i0);
-    if ((uint64_t)wacc < table[(d1 + 4) * 9 + (d2 + 4)]) out = (prop & bm) | (out & ~bm);
+  const uint32_t x1 = x0 + 3;
+#pragma unroll
+  for (uint32_t i = 0; i < 2; ++i) {
+    const uint32_t mk = 0xF0u << (8 * i);
+    const int d1 = __popc(k1 & mk) - __popc(s1 & mk), d2 = __popc(k2 & mk) - __popc(s2 & mk);
+    const uint32_t wacc = i == 0 ? w.w1 : w.w3;
+    if ((uint64_t)wacc < table[(d1 + 4) * 9 + (d2 + 4)])
+      __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(prop >> (8 * i)), row, i == 0 ? x0 : x1, 0, 0);
   }
-  if (two) {
-    const uint32_t m = 0xF0000000u;
-    const int d1 = __popc(k1 & m) - __popc(s1 & m), d2 = __popc(k2 & m) - __popc(s2 & m);
-    if ((uint64_t)w.w3 < table[(d1 + 4) * 9 + (d2 + 4)]) out = (out & 0x00FFFFFFu) | (prop & 0xFF000000u);
+}
+
+// The three colours of one row class (y mod 3 == cy) in one launch: a
+// workgroup per active row y holds rows y-1, y, y+1 in LDS (each padded with
+// the periodic dword on both ends) and runs the sub-passes cx = 0, 1, 2 with a
+// barrier between them (a site's neighbours in row y have the other residues
+// mod 3, rows y +- 1 are not updated by this class), then writes row y back.
+// Within a sub-pass a thread takes a 12-byte block of row y: its four sites
+// x = 12k + cx + 3j (j = 0..3), the two Philox blocks of segments 2k and
+// 2k + 1, and all four sites compared at once.  Lattices up to kRowsMaxL.
+constexpr uint32_t kRowsMaxL = 16380;
+
+// bytes R0..R3 of the five dwords d[0..4] (byte r = d[r/4].byte(r%4))
+template <int R0, int R1, int R2, int R3>
+__device__ __forceinline__ uint32_t gather4(const uint32_t d[5]) {
+  constexpr uint32_t s01 = 0x0C0C0000u | (uint32_t)(R0 % 4) | ((uint32_t)(R1 / 4 == R0 / 4 ? R1 % 4 : 4 + R1 % 4) << 8);
+  constexpr uint32_t s23 = 0x0C0C0000u | (uint32_t)(R2 % 4) | ((uint32_t)(R3 / 4 == R2 / 4 ? R3 % 4 : 4 + R3 % 4) << 8);
+  const uint32_t lo = perm(d[R1 / 4], d[R0 / 4], s01);
+  const uint32_t hi = perm(d[R3 / 4], d[R2 / 4], s23);
+  return perm(hi, lo, 0x05040100u);
+}
+
+// left, centre and right views of the four sites for sub-pass CX: byte j of
+// each is the byte at x - 1, x, x + 1 for site j (dword 0 starts at 12k - 4)
+template <int CX>
+__device__ __forceinline__ void row_views(const uint32_t d[5], uint32_t &l, uint32_t &c, uint32_t &r) {
+  l = gather4<3 + CX, 6 + CX, 9 + CX, 12 + CX>(d);
+  c = gather4<4 + CX, 7 + CX, 10 + CX, 13 + CX>(d);
+  r = gather4<5 + CX, 8 + CX, 11 + CX, 14 + CX>(d);
+}
+
+template <int CMP, int CX>
+__device__ __forceinline__ void rows_subpass(const NnnPass &p, uint32_t y, uint32_t *ru, uint32_t *rc, uint32_t *rd,
+                                             const uint64_t *table) {
+  const uint32_t L = p.g.L, nblk = L / 12, spr = L / 6;
+  const PhiloxHead h = philox_head(p.t_lo, p.t_hi, 16u + 3u * p.colour + CX, p.g.k0, p.g.k1);
+  uint8_t *rcb = reinterpret_cast<uint8_t *>(rc);
+  for (uint32_t k = threadIdx.x; k < nblk; k += kBlock) {
+    // padded dwords 3k .. 3k+4 hold x = 12k - 4 .. 12k + 15
+    uint32_t du[5], dc[5], dd[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      du[i] = ru[3 * k + i];
+      dc[i] = rc[3 * k + i];
+      dd[i] = rd[3 * k + i];
+    }
+    uint32_t left, cur, right, ul, U, ur, dl, D, dr;
+    row_views<CX>(dc, left, cur, right);
+    row_views<CX>(du, ul, U, ur);
+    row_views<CX>(dd, dl, D, dr);
+    const uint32_t seg = y * spr + 2 * k;
+    const Words a = philox_tail(h.a0 ^ seg, h);
+    const Words b = philox_tail(h.a0 ^ (seg + 1), h);
+    const uint32_t q = p.g.q;
+    const uint32_t prop = scale_to_q(a.w0, q) | (scale_to_q(a.w2, q) << 8) | (scale_to_q(b.w0, q) << 16) |
+                          (scale_to_q(b.w2, q) << 24);
+    const uint32_t s1 = diff_pattern<CMP>(cur, left, right, U, D), k1 = diff_pattern<CMP>(prop, left, right, U, D);
+    const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
+    const uint32_t wacc[4] = {a.w1, a.w3, b.w1, b.w3};
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      const uint32_t mk = 0xF0u << (8 * j);
+      const int d1 = __popc(k1 & mk) - __popc(s1 & mk), d2 = __popc(k2 & mk) - __popc(s2 & mk);
+      if ((uint64_t)wacc[j] < table[(d1 + 4) * 9 + (d2 + 4)]) rcb[4 + 12 * k + CX + 3 * j] = (uint8_t)(prop >> (8 * j));
+    }
   }
-  __builtin_amdgcn_raw_buffer_store_b32(out, row, oj, 0, 0);
+}
+
+template <int CMP>
+__global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
+  extern __shared__ uint32_t rows_lds[];
+  __shared__ uint64_t table[81];
+  for (uint32_t i = threadIdx.x; i < 81; i += kBlock) table[i] = p.thr[i];
+  const uint32_t L = p.g.L, cpr = L >> 2, W = cpr + 2;
+  const uint32_t y = 3 * blockIdx.x + p.colour;  // p.colour: the row class cy
+  const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
+  uint32_t *ru = rows_lds, *rc = rows_lds + W, *rd = rows_lds + 2 * W;
+  const __amdgpu_buffer_rsrc_t grow = lattice_rsrc(p.g.spins + (size_t)y * L);
+  const __amdgpu_buffer_rsrc_t gup = lattice_rsrc(p.g.spins + (size_t)yu * L);
+  const __amdgpu_buffer_rsrc_t gdn = lattice_rsrc(p.g.spins + (size_t)yd * L);
+  for (uint32_t i = threadIdx.x; i < W; i += kBlock) {
+    const uint32_t src = i == 0 ? cpr - 1 : i == W - 1 ? 0u : i - 1;  // periodic padding
+    ru[i] = load4(gup, 4 * src);
+    rc[i] = load4(grow, 4 * src);
+    rd[i] = load4(gdn, 4 * src);
+  }
+  __syncthreads();
+  rows_subpass<CMP, 0>(p, y, ru, rc, rd, table);
+  __syncthreads();
+  // the padding dwords of row y mirror its ends: refresh them after each sub-pass
+  if (threadIdx.x == 0) {
+    rc[0] = rc[cpr];
+    rc[W - 1] = rc[1];
+  }
+  __syncthreads();
+  rows_subpass<CMP, 1>(p, y, ru, rc, rd, table);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rc[0] = rc[cpr];
+    rc[W - 1] = rc[1];
+  }
+  __syncthreads();
+  rows_subpass<CMP, 2>(p, y, ru, rc, rd, table);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < cpr; i += kBlock) __builtin_amdgcn_raw_buffer_store_b32(rc[i + 1], grow, 4 * i, 0, 0);
 }
 
 // e1 (right, down), e2 (down-right, down-left) and populations of the
@@ -336,12 +446,23 @@ int run(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
   p.g = lattice_of(s);
   for (int i = 0; i < 81; ++i) p.thr[i] = thr[i];
   const uint32_t L = (uint32_t)s->L;
-  const dim3 pass_grid(((L >> 2) + kBlock - 1) / kBlock, L / 3);
+  const dim3 pass_grid((L / 6 + kBlock - 1) / kBlock, L / 3);
+  const bool rows = s->kernel == 1 || (s->kernel == 0 && L <= kRowsMaxL);
+  const size_t rows_lds = (size_t)3 * ((L >> 2) + 2) * 4;
   for (int64_t k = 0; k < nsweeps; ++k) {
     const int64_t t = s->t + k;
     p.t_lo = (uint32_t)(uint64_t)t;
     p.t_hi = (uint32_t)((uint64_t)t >> 32);
-    for (uint32_t c = 0; c < 9; ++c) {
+    for (uint32_t c = 0; rows && c < 3; ++c) {
+      p.colour = c;  // the row class
+      if (s->q <= 16)
+        hipLaunchKernelGGL(nnn_rows_kernel<0>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+      else if (s->q <= 128)
+        hipLaunchKernelGGL(nnn_rows_kernel<1>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+      else
+        hipLaunchKernelGGL(nnn_rows_kernel<2>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+    }
+    for (uint32_t c = 0; !rows && c < 9; ++c) {
       p.colour = c;
       if (s->q <= 16)
         hipLaunchKernelGGL(nnn_pass_kernel<0>, pass_grid, dim3(kBlock), 0, s->stream, p);
@@ -457,6 +578,14 @@ int potts_nnn_get_spins(potts_nnn_state *s, uint8_t *host_out) {
   if (!s || !host_out) return fail(POTTS_EINVAL, "NULL argument");
   NNN_TRY(hipMemcpyAsync(host_out, s->spins, (size_t)s->L * s->L, hipMemcpyDeviceToHost, s->stream));
   NNN_TRY(hipStreamSynchronize(s->stream));
+  return POTTS_OK;
+}
+
+int potts_nnn_tune(potts_nnn_state *s, int32_t kernel) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (kernel < 0 || kernel > 2) return fail(POTTS_EINVAL, "kernel must be 0, 1 or 2");
+  if (kernel == 1 && (uint32_t)s->L > kRowsMaxL) return fail(POTTS_EINVAL, "the row-class kernel needs L <= 16380");
+  s->kernel = kernel;
   return POTTS_OK;
 }
 

@@ -26,24 +26,26 @@ def potts():
 
 CASES = [
     # L, q, seed, start, beta, j2, sweeps
-    (12, 2, 1, 1, 0.3, 0.5, 8),        # three chunks per row, one workgroup
+    (12, 2, 1, 1, 0.3, 0.5, 8),        # one 12-byte block per row, wrap on both sides
     (24, 3, 2, 1, 0.7, -0.4, 6),       # frustrating second neighbours
-    (36, 9, 3, 0, 1.0, 0.5, 5),        # nine chunks per row: the active byte cycles
+    (36, 9, 3, 0, 1.0, 0.5, 5),
     (48, 256, 4, 1, 2.0, 1.0, 4),
     (60, 17, 5, 1, 1.2, 0.25, 4),
     (96, 100, 6, 1, 9.0, 0.5, 3),      # entries 0 for every dE > 0
     (120, 7, 7, 1, 0.0, 0.5, 3),       # beta = 0
     (600, 5, 8, 1, 0.9, 0.3, 3),
-    (2400, 4, 9, 1, 0.8, 0.5, 1),      # 5.8 M sites, many workgroups per pass
+    (3084, 4, 9, 1, 0.8, 0.5, 1),      # 9.5 M sites: 257 blocks per row, more than one per thread
 ]
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("L,q,seed,start,beta,j2,n", CASES)
-def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, j2, n):
-    _say(f"nnn L={L} q={q} beta={beta} j2={j2} n={n}")
+def test_sweeps_match_oracle(potts, oracle_lib, L, q, seed, start, beta, j2, n, kernel):
+    _say(f"nnn L={L} q={q} beta={beta} j2={j2} n={n} kernel={kernel}")
     s = oracle_lib.init(L, q, seed, start)
     rec = oracle_lib.nnn_sweeps(s, q, seed, 0, n, oracle_lib.nnn_table(beta, j2))
     with potts.NnnLattice(L, q, seed, start) as lat:
+        lat.tune(kernel)
         lat.sweep(beta, j2, n)
         assert lat.t == n
         assert np.array_equal(lat.records(0, n), rec)
@@ -94,6 +96,34 @@ def test_record_ring(potts):
         assert list(r[-1]) == [obs["e1"], obs["e2"], *obs["hist"]]
 
 
+@pytest.mark.parametrize("L,q", [(16380, 3), (16392, 200)])
+def test_row_class_limit(potts, oracle_lib, L, q):
+    """The largest lattice the row-class kernel takes (three rows of 16380
+    bytes in LDS) against the per-colour kernel, and the first one past it
+    (automatic choice: per colour, row-class refused) against the oracle."""
+    seed, beta, j2 = 5, 0.9, 0.4
+    _say(f"nnn row-class limit L={L} q={q}")
+    with potts.NnnLattice(L, q, seed, 1) as a:
+        if L <= 16380:
+            a.tune(1)
+        else:
+            with pytest.raises(potts.PottsError):
+                a.tune(1)
+        a.sweep(beta, j2, 1)
+        got = a.spins()
+        rec = a.records(0, 1)
+    if L <= 16380:
+        with potts.NnnLattice(L, q, seed, 1) as b:
+            b.tune(2)
+            b.sweep(beta, j2, 1)
+            assert np.array_equal(b.records(0, 1), rec)
+            assert np.array_equal(b.spins(), got)
+        return
+    s = oracle_lib.init(L, q, seed, 1)
+    assert np.array_equal(oracle_lib.nnn_sweeps(s, q, seed, 0, 1, oracle_lib.nnn_table(beta, j2)), rec)
+    assert np.array_equal(s, got)
+
+
 # the largest lattice: L % 12 == 0 with L^2/4 below 2^32 (17.2 GB)
 L_MAX = 131064
 
@@ -112,6 +142,10 @@ def test_maximum_lattice_frozen_ground_state(potts):
 
 
 def test_rejects_bad_arguments(potts):
+    with potts.NnnLattice(12, 3, 1, 1) as lat:
+        for k in (-1, 3):
+            with pytest.raises(potts.PottsError):
+                lat.tune(k)
     for L, q in [(18, 3), (8, 3), (24, 1), (24, 257)]:
         with pytest.raises(potts.PottsError):
             potts.NnnLattice(L, q, 1, 1)
