@@ -106,14 +106,16 @@ __global__ __launch_bounds__(kBlock) void sweep4_kernel(SweepParams p) {
 // right), then the other values ascending; r = floor(w Z / 2^32) picks the
 // first value whose cumulative weight exceeds r.  Non-neighbour values all
 // weigh D[n_max], so that run is indexed with one division and the j-th
-// value outside the (at most four) neighbour values is found by fixed-point
-// iteration of k = j + #{excluded values <= k}.
+// value outside the (at most four) neighbour values comes from one pass over
+// those values in ascending order.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(uint8_t *p) {
   return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)0xFFFFFFFFu, 0x00020000);
 }
 
+// D[0..5] = {2^32, thr[0..3], 0} (weight by gap to n_max; 5: no weight) and
+// inv[0..3] = 1/thr[d] in FP32, read from LDS by per-lane index.
 __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                                  uint32_t w, const Thresholds &thr, const double inv[4]) {
+                                                  uint32_t w, const uint64_t *D, const float *inv) {
   const uint32_t na = 1 + (a == b) + (a == c) + (a == d);
   const uint32_t nb = 1 + (b == a) + (b == c) + (b == d);
   const uint32_t nc = 1 + (c == a) + (c == b) + (c == d);
@@ -122,27 +124,26 @@ __device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32
   // first appearances
   const bool fb = b != a, fc = c != a && c != b, fd = d != a && d != b && d != c;
   const uint32_t m = 1 + fb + fc + fd;
-  auto weight = [&](uint32_t gap) -> uint64_t {
-    return gap == 0 ? (1ull << 32) : (uint64_t)thr.v[gap - 1];
-  };
-  const uint64_t wa = weight(nmax - na);
-  const uint64_t wb = fb ? weight(nmax - nb) : 0;
-  const uint64_t wc = fc ? weight(nmax - nc) : 0;
-  const uint64_t wd = fd ? weight(nmax - nd) : 0;
-  const uint64_t w0 = weight(nmax);  // each value no neighbour holds (nmax >= 1: a threshold)
+  const uint64_t wa = D[nmax - na];
+  const uint64_t wb = D[fb ? nmax - nb : 5u];
+  const uint64_t wc = D[fc ? nmax - nc : 5u];
+  const uint64_t wd = D[fd ? nmax - nd : 5u];
+  const uint32_t w0 = (uint32_t)D[nmax];  // each value no neighbour holds (nmax >= 1: a threshold, < 2^32)
   const uint64_t S = wa + wb + wc + wd;
   const uint64_t Z = S + (uint64_t)(q - m) * w0;  // < 2^41
   // r = floor(w Z / 2^32), exactly, from the two halves of Z
   const uint64_t r = (uint64_t)w * (Z >> 32) + (((uint64_t)w * (Z & 0xFFFFFFFFull)) >> 32);
   // past the neighbour values: j = floor(X / w0) for X = r - S < (q - m) w0
-  // (so w0 > 0 and j < 256).  X and w0 are exact doubles and inv = 1/w0
-  // rounded, so X * inv is within a few ulp of X / w0 and its floor is j - 1,
-  // j or j + 1; one integer check each way makes it exact.  Computed for every
-  // lane (no divergent branch); lanes that stopped earlier discard it.
+  // (so w0 > 0 and j < 256).  X in FP32 (two conversions and one fma) times
+  // the FP32 reciprocal is within 4e-7 relative, 1e-4 absolute, of X / w0,
+  // so its floor is j - 1, j or j + 1; one integer check each way, taken from
+  // the estimate, makes it exact.  Computed for every lane (no divergent
+  // branch); lanes that stopped earlier discard it.
   const uint64_t X = r >= S ? r - S : 0;
-  uint32_t j = (uint32_t)((double)X * inv[nmax - 1]);
-  if ((uint64_t)j * w0 > X) --j;
-  else if ((uint64_t)(j + 1) * w0 <= X) ++j;
+  const float xf = __builtin_fmaf((float)(uint32_t)(X >> 32), 4294967296.0f, (float)(uint32_t)X);
+  uint32_t j = (uint32_t)(xf * inv[nmax - 1]);
+  const uint64_t jw = (uint64_t)j * w0;
+  j = j - (uint32_t)(jw > X) + (uint32_t)(jw + w0 <= X);
   // the j-th value that no neighbour holds: with the (at most four) distinct
   // neighbour values in ascending order, each one at or below the running
   // candidate moves it up by one
@@ -173,8 +174,12 @@ template <int COLOUR>
 __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t esum;
+  __shared__ uint64_t D[6];
+  __shared__ float inv[4];
   for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
   if (threadIdx.x == 0) esum = 0;
+  if (threadIdx.x < 6) D[threadIdx.x] = threadIdx.x == 0 ? (1ull << 32) : threadIdx.x == 5 ? 0 : p.thr.v[threadIdx.x - 1];
+  if (threadIdx.x < 4) inv[threadIdx.x] = (float)p.inv_thr[threadIdx.x];
   if (COLOUR == 1 && blockIdx.x == 0 && blockIdx.y == 0 && p.rec_clear) {
     for (uint32_t i = threadIdx.x; i < p.q + 1; i += kBlock) p.rec_clear[i] = 0;
   }
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
       for (uint32_t s = 0; s < 2; ++s) {
         const uint32_t i = o + 2 * s;
         const uint32_t a = byte_of(up, i), b = byte_of(dn, i), c = byte_of(left, i), d = byte_of(right, i);
-        const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, p.thr, p.inv_thr);
+        const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, D, inv);
         out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
         if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
       }
