@@ -112,74 +112,126 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(uint8_t *p) {
   return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)0xFFFFFFFFu, 0x00020000);
 }
 
-// D[0..5] = {2^32, thr[0..3], 0} (weight by gap to n_max; 5: no weight) and
-// inv[0..3] = 1/thr[d] in FP32, read from LDS by per-lane index.
-__device__ __forceinline__ uint32_t heatbath_draw(uint32_t q, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                                  uint32_t w, const uint64_t *D, const float *inv) {
-  const uint32_t na = 1 + (a == b) + (a == c) + (a == d);
-  const uint32_t nb = 1 + (b == a) + (b == c) + (b == d);
-  const uint32_t nc = 1 + (c == a) + (c == b) + (c == d);
-  const uint32_t nd = 1 + (d == a) + (d == b) + (d == c);
+// Everything of the draw that depends only on which of the four neighbours
+// are equal comes from a 64-entry LDS table indexed by the six "differs"
+// flags (ab, ac, ad, bc, bd, cd; a = up, b = down, c = left, d = right),
+// built per workgroup from the thresholds: the cumulative weights of the
+// ranked neighbour values (a, then b, c, d where they appear first; a value
+// seen before weighs 0 there), S (their total), Z = S + (q - m) w0 (m distinct
+// neighbour values, w0 = D[n_max] the weight of each other value) and the FP32
+// reciprocal of w0.  Field-major (one array of 64 per field), so that lanes
+// reading different entries share a bank only when the entries agree mod 16.
+enum HbField { kSa, kSab, kSabc, kS, kZ, kW0Inv, kHbFields };
+
+__device__ void fill_heatbath_entry(uint64_t (*tab)[64], uint32_t pat, uint32_t q, const Thresholds &thr,
+                                    const double *inv) {
+  const uint32_t eab = !(pat & 32u), eac = !(pat & 16u), ead = !(pat & 8u);
+  const uint32_t ebc = !(pat & 4u), ebd = !(pat & 2u), ecd = !(pat & 1u);
+  const uint32_t na = 1 + eab + eac + ead, nb = 1 + eab + ebc + ebd;
+  const uint32_t nc = 1 + eac + ebc + ecd, nd = 1 + ead + ebd + ecd;
   const uint32_t nmax = max(max(na, nb), max(nc, nd));
-  // first appearances
-  const bool fb = b != a, fc = c != a && c != b, fd = d != a && d != b && d != c;
+  const bool fb = !eab, fc = !eac && !ebc, fd = !ead && !ebd && !ecd;
+  auto weight = [&](uint32_t gap) -> uint64_t { return gap == 0 ? (1ull << 32) : (uint64_t)thr.v[gap - 1]; };
+  const uint64_t wa = weight(nmax - na);
+  const uint64_t wb = fb ? weight(nmax - nb) : 0;
+  const uint64_t wc = fc ? weight(nmax - nc) : 0;
+  const uint64_t wd = fd ? weight(nmax - nd) : 0;
   const uint32_t m = 1 + fb + fc + fd;
-  const uint64_t wa = D[nmax - na];
-  const uint64_t wb = D[fb ? nmax - nb : 5u];
-  const uint64_t wc = D[fc ? nmax - nc : 5u];
-  const uint64_t wd = D[fd ? nmax - nd : 5u];
-  const uint32_t w0 = (uint32_t)D[nmax];  // each value no neighbour holds (nmax >= 1: a threshold, < 2^32)
-  const uint64_t S = wa + wb + wc + wd;
-  const uint64_t Z = S + (uint64_t)(q - m) * w0;  // < 2^41
+  const uint32_t w0 = thr.v[nmax - 1];
+  const uint64_t s = wa + wb + wc + wd;
+  tab[kSa][pat] = wa;
+  tab[kSab][pat] = wa + wb;
+  tab[kSabc][pat] = wa + wb + wc;
+  tab[kS][pat] = s;
+  // patterns no four values can show (equality is transitive) are never
+  // looked up; their entries are whatever the formulas give
+  tab[kZ][pat] = s + (uint64_t)(q - m) * w0;
+  tab[kW0Inv][pat] = w0 | (uint64_t)__float_as_uint((float)inv[nmax - 1]) << 32;
+}
+
+// Per byte of up/down/left/right: the six "differs" flags at bits 7..2 (ab,
+// ac, ad, bc, bd, cd), bits 1..0 clear.  CMP as in the row kernels: 0 for
+// values below 16 (x + 0x7F/0x3F/0x1F/0x0F sets exactly bit 7/6/5/4 when
+// x != 0), 1 below 128 (x + 0x7F flags bit 7), 2 for any byte (exact test).
+template <int CMP>
+__device__ __forceinline__ uint32_t pair_flags(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  auto bfi = [](uint32_t mask, uint32_t x, uint32_t y) { return (x & mask) | (y & ~mask); };
+  uint32_t hi, lo;  // flags ab, ac, ad, bc at bits 7..4; bd, cd at bits 7..6
+  if (CMP == 0) {
+    hi = bfi(0xE0E0E0E0u, bfi(0xC0C0C0C0u, bfi(0x80808080u, (a ^ b) + 0x7F7F7F7Fu, (a ^ c) + 0x3F3F3F3Fu),
+                              (a ^ d) + 0x1F1F1F1Fu),
+             (b ^ c) + 0x0F0F0F0Fu);
+    lo = bfi(0x80808080u, (b ^ d) + 0x7F7F7F7Fu, (c ^ d) + 0x3F3F3F3Fu);
+  } else {
+    auto f = [](uint32_t x) {
+      return CMP == 1 ? x + 0x7F7F7F7Fu : (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x);
+    };
+    hi = bfi(0xE0E0E0E0u, bfi(0xC0C0C0C0u, bfi(0x80808080u, f(a ^ b), f(a ^ c) >> 1), f(a ^ d) >> 2),
+             f(b ^ c) >> 3);
+    lo = bfi(0x80808080u, f(b ^ d), f(c ^ d) >> 1);
+  }
+  return bfi(0xF0F0F0F0u, hi, lo >> 4) & 0xFCFCFCFCu;
+}
+
+// One draw from the table entries of the site's pattern.
+__device__ __forceinline__ uint32_t heatbath_draw(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t w,
+                                                  const uint64_t (*tab)[64], uint32_t pat) {
+  const uint64_t sa = tab[kSa][pat], sab = tab[kSab][pat];
+  const uint64_t sabc = tab[kSabc][pat], S = tab[kS][pat];
+  const uint64_t Z = tab[kZ][pat];  // < 2^41
+  const uint64_t wi = tab[kW0Inv][pat];
+  const uint32_t w0 = (uint32_t)wi;
+  const float inv = __uint_as_float((uint32_t)(wi >> 32));
   // r = floor(w Z / 2^32), exactly, from the two halves of Z
   const uint64_t r = (uint64_t)w * (Z >> 32) + (((uint64_t)w * (Z & 0xFFFFFFFFull)) >> 32);
   // past the neighbour values: j = floor(X / w0) for X = r - S < (q - m) w0
   // (so w0 > 0 and j < 256).  X in FP32 (two conversions and one fma) times
-  // the FP32 reciprocal is within 4e-7 relative, 1e-4 absolute, of X / w0,
+  // the FP32 reciprocal is within 1e-6 relative, 3e-4 absolute, of X / w0,
   // so its floor is j - 1, j or j + 1; one integer check each way, taken from
   // the estimate, makes it exact.  Computed for every lane (no divergent
   // branch); lanes that stopped earlier discard it.
   const uint64_t X = r >= S ? r - S : 0;
   const float xf = __builtin_fmaf((float)(uint32_t)(X >> 32), 4294967296.0f, (float)(uint32_t)X);
-  uint32_t j = (uint32_t)(xf * inv[nmax - 1]);
+  uint32_t j = (uint32_t)(xf * inv);
   const uint64_t jw = (uint64_t)j * w0;
   j = j - (uint32_t)(jw > X) + (uint32_t)(jw + w0 <= X);
-  // the j-th value that no neighbour holds: with the (at most four) distinct
-  // neighbour values in ascending order, each one at or below the running
-  // candidate moves it up by one
-  const uint32_t kNone = 0x100u;  // above every value
-  uint32_t e0 = a, e1 = fb ? b : kNone, e2 = fc ? c : kNone, e3 = fd ? d : kNone;
+  // the j-th value that no neighbour holds: with the neighbour values in
+  // ascending order, each one at or below the running candidate that is not a
+  // repeat of the one before moves it up by one
+  uint32_t e[4] = {a, b, c, d};
   auto order = [](uint32_t &x, uint32_t &y) {
     const uint32_t lo = min(x, y), hi = max(x, y);
     x = lo;
     y = hi;
   };
-  order(e0, e1);
-  order(e2, e3);
-  order(e0, e2);
-  order(e1, e3);
-  order(e1, e2);
+  order(e[0], e[1]);
+  order(e[2], e[3]);
+  order(e[0], e[2]);
+  order(e[1], e[3]);
+  order(e[1], e[2]);
   uint32_t k = j;
-  k += e0 <= k;
-  k += e1 <= k;
-  k += e2 <= k;
-  k += e3 <= k;
-  const uint64_t sab = wa + wb, sabc = sab + wc;
-  return r < wa ? a : r < sab ? b : r < sabc ? c : r < S ? d : k;
+  k += e[0] <= k;
+  k += e[1] != e[0] && e[1] <= k;
+  k += e[2] != e[1] && e[2] <= k;
+  k += e[3] != e[2] && e[3] <= k;
+  return r < sa ? a : r < sab ? b : r < sabc ? c : r < S ? d : k;
 }
 
 // Grid: x over the chunks of a row, y strided over the rows (no division per
 // chunk); the Philox head of the half sweep is the same for every lane.
-template <int COLOUR>
+// Populations (colour 1) in q shared LDS bins: a chunk whose four bytes are
+// equal adds 4 with one atomic.  (Lane-private columns, value * 64 + lane,
+// were far slower here: the adds of one instruction to a shared bin are
+// cheaper than 64 adds to distinct addresses.)
+template <int COLOUR, int CMP>
 __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t esum;
-  __shared__ uint64_t D[6];
-  __shared__ float inv[4];
+  __shared__ uint64_t table[kHbFields][64];
+  const uint32_t lane = threadIdx.x & 63u;
   for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) hist[v] = 0;
   if (threadIdx.x == 0) esum = 0;
-  if (threadIdx.x < 6) D[threadIdx.x] = threadIdx.x == 0 ? (1ull << 32) : threadIdx.x == 5 ? 0 : p.thr.v[threadIdx.x - 1];
-  if (threadIdx.x < 4) inv[threadIdx.x] = (float)p.inv_thr[threadIdx.x];
+  if (threadIdx.x < 64) fill_heatbath_entry(table, threadIdx.x, p.q, p.thr, p.inv_thr);
   if (COLOUR == 1 && blockIdx.x == 0 && blockIdx.y == 0 && p.rec_clear) {
     for (uint32_t i = threadIdx.x; i < p.q + 1; i += kBlock) p.rec_clear[i] = 0;
   }
@@ -208,23 +260,29 @@ __global__ __launch_bounds__(kBlock) void heatbath4_kernel(SweepParams p) {
 
       const Words w = philox_tail(h.a0 ^ (y * cpr + j), h);
       const uint32_t o = (COLOUR + y) & 1u;  // byte of the first active site; the second is o + 2
+      const uint32_t pat = pair_flags<CMP>(up, dn, left, right);
       uint32_t out = cur;
 #pragma unroll
       for (uint32_t s = 0; s < 2; ++s) {
         const uint32_t i = o + 2 * s;
         const uint32_t a = byte_of(up, i), b = byte_of(dn, i), c = byte_of(left, i), d = byte_of(right, i);
-        const uint32_t k = heatbath_draw(p.q, a, b, c, d, s == 0 ? w.w0 : w.w2, D, inv);
+        const uint32_t k = heatbath_draw(a, b, c, d, s == 0 ? w.w0 : w.w2, table, byte_of(pat, i) >> 2);
         out = (out & ~(0xFFu << (8 * i))) | (k << (8 * i));
         if (COLOUR == 1) e += (k == a) + (k == b) + (k == c) + (k == d);
       }
       __builtin_amdgcn_raw_buffer_store_b32(out, row, oj, 0, 0);
-      if (COLOUR == 1)
-        for (uint32_t bb = 0; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
+      if (COLOUR == 1) {
+        const uint32_t v0 = out & 0xFFu;
+        const bool same = out == v0 * 0x01010101u;
+        atomicAdd(&hist[v0], same ? 4u : 1u);
+        if (!same)
+          for (uint32_t bb = 1; bb < 4; ++bb) atomicAdd(&hist[byte_of(out, bb)], 1u);
+      }
     }
   }
   if (COLOUR == 1) {
     e = wave_sum(e);
-    if ((threadIdx.x & 63) == 0 && e) atomicAdd(&esum, e);
+    if (lane == 0 && e) atomicAdd(&esum, e);
     __syncthreads();
     for (uint32_t v = threadIdx.x; v < p.q; v += kBlock) {
       const uint32_t cnt = hist[v];
@@ -321,10 +379,17 @@ hipError_t launch_heatbath(const SweepParams &p, int colour, hipStream_t stream)
   for (int d = 0; d < 4; ++d) h.inv_thr[d] = h.thr.v[d] ? 1.0 / (double)h.thr.v[d] : 0.0;
   const uint32_t bx = ((p.L >> 2) + kBlock - 1) / kBlock;
   const uint32_t by = std::max<uint32_t>(1u, std::min<uint32_t>(p.L, 4096u / bx));
-  if (colour == 0)
-    hipLaunchKernelGGL(heatbath4_kernel<0>, dim3(bx, by), dim3(kBlock), 0, stream, h);
-  else
-    hipLaunchKernelGGL(heatbath4_kernel<1>, dim3(bx, by), dim3(kBlock), 0, stream, h);
+  const dim3 grid(bx, by);
+  const int cmp = p.q <= 16 ? 0 : p.q <= 128 ? 1 : 2;
+  if (colour == 0) {
+    if (cmp == 0) hipLaunchKernelGGL((heatbath4_kernel<0, 0>), grid, dim3(kBlock), 0, stream, h);
+    else if (cmp == 1) hipLaunchKernelGGL((heatbath4_kernel<0, 1>), grid, dim3(kBlock), 0, stream, h);
+    else hipLaunchKernelGGL((heatbath4_kernel<0, 2>), grid, dim3(kBlock), 0, stream, h);
+  } else {
+    if (cmp == 0) hipLaunchKernelGGL((heatbath4_kernel<1, 0>), grid, dim3(kBlock), 0, stream, h);
+    else if (cmp == 1) hipLaunchKernelGGL((heatbath4_kernel<1, 1>), grid, dim3(kBlock), 0, stream, h);
+    else hipLaunchKernelGGL((heatbath4_kernel<1, 2>), grid, dim3(kBlock), 0, stream, h);
+  }
   return hipGetLastError();
 }
 

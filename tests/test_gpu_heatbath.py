@@ -34,6 +34,11 @@ CASES = [
     (48, 200, 6, 0, 9.0, 4),         # zero thresholds: only the best neighbour counts
     (128, 6, 7, 1, 0.0, 3),          # beta = 0: uniform draws
     (256, 15, 8, 1, beta_c(15), 5),
+    # the edges of the byte-wise equality tests (values below 16, below 128, any)
+    (36, 16, 9, 1, 1.3, 4),
+    (40, 17, 10, 1, 1.2, 4),
+    (44, 128, 11, 1, 1.5, 3),
+    (52, 129, 12, 1, 1.5, 3),
 ]
 
 
@@ -47,6 +52,24 @@ def test_heatbath_matches_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
         assert lat.t == n
         assert np.array_equal(lat.spins(), s)
         assert np.array_equal(lat.records(0, n), rec)
+
+
+@pytest.mark.parametrize("q", [3, 16, 129])
+def test_heatbath_caller_tables(potts, oracle_lib, q):
+    """Caller tables that no temperature gives: zeros, 1, 2^32 - 1 and values
+    out of order, so that w0 (the weight of a value no neighbour holds) is 0
+    for some counts and tiny for others."""
+    L, seed = 48, 21
+    tables = [np.array(t, dtype=np.uint32) for t in
+              ([1, 0, 7, 0xFFFFFFFF], [0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF], [0, 0, 0, 0],
+               [3, 0xFFFFFFFE, 1, 2])]
+    s = oracle_lib.init(L, q, seed, 1)
+    recs = [oracle_lib.heatbath_sweeps(s, q, seed, 2 * i, 2, t) for i, t in enumerate(tables)]
+    with potts.Lattice(L, q, seed, 1) as lat:
+        for t in tables:
+            lat.sweep_heatbath_thr(t, 2)
+        assert np.array_equal(lat.records(0, 2 * len(tables)), np.concatenate(recs))
+        assert np.array_equal(lat.spins(), s)
 
 
 @pytest.mark.parametrize("L", [64, 512, 100])  # resident, strip, chunk Metropolis paths
