@@ -103,6 +103,14 @@ __device__ __forceinline__ uint32_t alignb(uint32_t hi, uint32_t lo, uint32_t sh
 // proposals as byte-wise "differs" flag patterns (bits 7..4 of every byte, the
 // row kernels' diff_pattern, CMP by q); a site's counts are the popcounts of
 // its pattern byte: d1 = n1(s) - n1(k) = diff1(k) - diff1(s).
+// k: "differs from the proposal" flags, s: "differs from the current value"
+// flags, at bits 7..4 of every byte (bits 3..0 garbage): per byte, the
+// proposal's flags above and the current value's "equal" flags below, so
+// that the popcount of byte j is 4 - n(k) + n(s) = d + 4 for its site.
+__device__ __forceinline__ uint32_t count_flags(uint32_t k, uint32_t s) {
+  return (k & 0xF0F0F0F0u) | ((~s >> 4) & 0x0F0F0F0Fu);
+}
+
 template <int CMP>
 __global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
   __shared__ uint64_t table[81];
@@ -144,12 +152,12 @@ __global__ __launch_bounds__(kBlock) void nnn_pass_kernel(NnnPass p) {
   const uint32_t s1 = diff_pattern<CMP>(cur, left, right, U, D), k1 = diff_pattern<CMP>(prop, left, right, U, D);
   const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
   const uint32_t x1 = x0 + 3;
+  const uint32_t c1 = count_flags(k1, s1), c2 = count_flags(k2, s2);
 #pragma unroll
   for (uint32_t i = 0; i < 2; ++i) {
-    const uint32_t mk = 0xF0u << (8 * i);
-    const int d1 = __popc(k1 & mk) - __popc(s1 & mk), d2 = __popc(k2 & mk) - __popc(s2 & mk);
+    const uint32_t mk = 0xFFu << (8 * i);
     const uint32_t wacc = i == 0 ? w.w1 : w.w3;
-    if ((uint64_t)wacc < table[(d1 + 4) * 9 + (d2 + 4)])
+    if ((uint64_t)wacc < table[__popc(c1 & mk) * 9 + __popc(c2 & mk)])
       __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(prop >> (8 * i)), row, i == 0 ? x0 : x1, 0, 0);
   }
 }
@@ -210,33 +218,54 @@ __device__ __forceinline__ void rows_subpass(const NnnPass &p, uint32_t y, uint3
                           (scale_to_q(b.w2, q) << 24);
     const uint32_t s1 = diff_pattern<CMP>(cur, left, right, U, D), k1 = diff_pattern<CMP>(prop, left, right, U, D);
     const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
+    const uint32_t c1 = count_flags(k1, s1), c2 = count_flags(k2, s2);
     const uint32_t wacc[4] = {a.w1, a.w3, b.w1, b.w3};
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) {
-      const uint32_t mk = 0xF0u << (8 * j);
-      const int d1 = __popc(k1 & mk) - __popc(s1 & mk), d2 = __popc(k2 & mk) - __popc(s2 & mk);
-      if ((uint64_t)wacc[j] < table[(d1 + 4) * 9 + (d2 + 4)]) rcb[4 + 12 * k + CX + 3 * j] = (uint8_t)(prop >> (8 * j));
+      const uint32_t mk = 0xFFu << (8 * j);
+      if ((uint64_t)wacc[j] < table[__popc(c1 & mk) * 9 + __popc(c2 & mk)])
+        rcb[4 + 12 * k + CX + 3 * j] = (uint8_t)(prop >> (8 * j));
     }
   }
 }
+
+// LDS row stride of the row-class kernel: the three rows are copied in
+// chunks of 64 dwords to dwords 1 .. 64 * ceil(L/256) of their LDS rows, with
+// the periodic dwords at 0 and L/4 + 1.
+__host__ __device__ inline uint32_t rows_stride(uint32_t L) { return 64u * (((L >> 2) + 63u) >> 6) + 2u; }
 
 template <int CMP>
 __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
   extern __shared__ uint32_t rows_lds[];
   __shared__ uint64_t table[81];
   for (uint32_t i = threadIdx.x; i < 81; i += kBlock) table[i] = p.thr[i];
-  const uint32_t L = p.g.L, cpr = L >> 2, W = cpr + 2;
+  const uint32_t L = p.g.L, cpr = L >> 2, W = rows_stride(L);
   const uint32_t y = 3 * blockIdx.x + p.colour;  // p.colour: the row class cy
   const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
   uint32_t *ru = rows_lds, *rc = rows_lds + W, *rd = rows_lds + 2 * W;
-  const __amdgpu_buffer_rsrc_t grow = lattice_rsrc(p.g.spins + (size_t)y * L);
-  const __amdgpu_buffer_rsrc_t gup = lattice_rsrc(p.g.spins + (size_t)yu * L);
-  const __amdgpu_buffer_rsrc_t gdn = lattice_rsrc(p.g.spins + (size_t)yd * L);
-  for (uint32_t i = threadIdx.x; i < W; i += kBlock) {
-    const uint32_t src = i == 0 ? cpr - 1 : i == W - 1 ? 0u : i - 1;  // periodic padding
-    ru[i] = load4(gup, 4 * src);
-    rc[i] = load4(grow, 4 * src);
-    rd[i] = load4(gdn, 4 * src);
+  // row resources that end with the row: the lanes of a chunk past its end
+  // read zeros, which land in the slack of the LDS row
+  const __amdgpu_buffer_rsrc_t grow = __builtin_amdgcn_make_buffer_rsrc(p.g.spins + (size_t)y * L, 0, (int)L, 0x00020000);
+  const __amdgpu_buffer_rsrc_t gup = __builtin_amdgcn_make_buffer_rsrc(p.g.spins + (size_t)yu * L, 0, (int)L, 0x00020000);
+  const __amdgpu_buffer_rsrc_t gdn = __builtin_amdgcn_make_buffer_rsrc(p.g.spins + (size_t)yd * L, 0, (int)L, 0x00020000);
+  // straight from memory into LDS, 64 dwords per wave instruction, with no
+  // register round trip and no wait before the barrier
+  const uint32_t lane = threadIdx.x & 63u;
+  typedef __attribute__((address_space(3))) void *lds_ptr;
+  for (uint32_t c = threadIdx.x >> 6; c < (cpr + 63) >> 6; c += kBlock / 64) {
+    const uint32_t off = 4 * (64 * c + lane);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(gup, (lds_ptr)(ru + 1 + 64 * c), 4, off, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(grow, (lds_ptr)(rc + 1 + 64 * c), 4, off, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(gdn, (lds_ptr)(rd + 1 + 64 * c), 4, off, 0, 0, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // periodic padding
+    ru[0] = ru[cpr];
+    ru[cpr + 1] = ru[1];
+    rc[0] = rc[cpr];
+    rc[cpr + 1] = rc[1];
+    rd[0] = rd[cpr];
+    rd[cpr + 1] = rd[1];
   }
   __syncthreads();
   rows_subpass<CMP, 0>(p, y, ru, rc, rd, table);
@@ -244,14 +273,14 @@ __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
   // the padding dwords of row y mirror its ends: refresh them after each sub-pass
   if (threadIdx.x == 0) {
     rc[0] = rc[cpr];
-    rc[W - 1] = rc[1];
+    rc[cpr + 1] = rc[1];
   }
   __syncthreads();
   rows_subpass<CMP, 1>(p, y, ru, rc, rd, table);
   __syncthreads();
   if (threadIdx.x == 0) {
     rc[0] = rc[cpr];
-    rc[W - 1] = rc[1];
+    rc[cpr + 1] = rc[1];
   }
   __syncthreads();
   rows_subpass<CMP, 2>(p, y, ru, rc, rd, table);
@@ -448,7 +477,7 @@ int run(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
   const uint32_t L = (uint32_t)s->L;
   const dim3 pass_grid((L / 6 + kBlock - 1) / kBlock, L / 3);
   const bool rows = s->kernel == 1 || (s->kernel == 0 && L <= kRowsMaxL);
-  const size_t rows_lds = (size_t)3 * ((L >> 2) + 2) * 4;
+  const size_t rows_lds = (size_t)3 * rows_stride(L) * 4;
   for (int64_t k = 0; k < nsweeps; ++k) {
     const int64_t t = s->t + k;
     p.t_lo = (uint32_t)(uint64_t)t;
