@@ -119,8 +119,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(uint8_t *p) {
 // ranked neighbour values (a, then b, c, d where they appear first; a value
 // seen before weighs 0 there), S (their total), Z = S + (q - m) w0 (m distinct
 // neighbour values, w0 = D[n_max] the weight of each other value) and the FP32
-// reciprocal of w0.  Field-major (one array of 64 per field), so that lanes
-// reading different entries share a bank only when the entries agree mod 16.
+// reciprocal of w0.  Field-major (one array of 64 per field): lanes reading
+// different entries meet in a bank only when the entry numbers agree in
+// their low bits, where 64-byte entries put every other entry in one bank.
 enum HbField { kSa, kSab, kSabc, kS, kZ, kW0Inv, kHbFields };
 
 __device__ void fill_heatbath_entry(uint64_t (*tab)[64], uint32_t pat, uint32_t q, const Thresholds &thr,
