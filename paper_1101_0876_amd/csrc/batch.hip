@@ -179,8 +179,8 @@ int upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
 }
 
 // One launch pair (colour 0, colour 1) of a strip group for sweep s.
-int launch_strip_sweep(potts_batch *b, const StripGroup &g, const potts::StripParams *d_desc,
-                       const potts::StripTile *d_tiles, size_t ntiles, uint32_t s, hipStream_t st) {
+int launch_strip_sweep(const StripGroup &g, const potts::StripParams *d_desc, const potts::StripTile *d_tiles,
+                       size_t ntiles, uint32_t s, hipStream_t st) {
   potts::StripLaunch l{};
   l.jobs = d_desc;
   l.tiles = d_tiles;
@@ -208,7 +208,7 @@ int timed_strip_sweeps(potts_batch *b, const StripGroup &g, const std::vector<in
   if (rc) return rc;
   HIP_TRY(hipEventRecord(b->ev_t0, b->stream));
   for (int s = 0; s < reps; ++s) {
-    rc = launch_strip_sweep(b, g, b->d_strip, b->d_tiles, tiles.size(), (uint32_t)s, b->stream);
+    rc = launch_strip_sweep(g, b->d_strip, b->d_tiles, tiles.size(), (uint32_t)s, b->stream);
     if (rc) return rc;
   }
   HIP_TRY(hipEventRecord(b->ev_t1, b->stream));
@@ -333,7 +333,7 @@ int queue_rest(potts_batch *b) {
   for (int64_t s = 0; s < strip_sweeps && !err; ++s) {
     for (size_t gi = 0; gi < b->strip_groups.size() && !err; ++gi) {
       if (!b->tile_count[gi]) continue;
-      err = launch_strip_sweep(b, b->strip_groups[gi], b->d_strip + b->strip_desc_off[gi],
+      err = launch_strip_sweep(b->strip_groups[gi], b->d_strip + b->strip_desc_off[gi],
                                b->d_tiles + b->tile_off[gi], b->tile_count[gi], (uint32_t)s, st);
     }
   }
