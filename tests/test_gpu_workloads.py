@@ -1,8 +1,10 @@
-"""The batched-replicas workload at its full configuration, in the launch
-configuration the benchmark times (1024 jobs of L = 128 .. 4096, 500 sweeps,
+"""Workloads at their full configurations, in the launch configurations the
+benchmark times.  Batched replicas (1024 jobs of L = 128 .. 4096, 500 sweeps,
 one batch with hipGraph and in-run tuning): sampled jobs against the oracle
 (the smallest lattices, every record and the final spins), the largest jobs
-against the same job run alone, and properties of every job."""
+against the same job run alone, and properties of every job.  Serving: the
+1000-job burst against the single-lattice path.  Heat-bath and second
+neighbours: the benchmark lattices' first sweeps against the oracle."""
 import numpy as np
 import pytest
 
@@ -84,3 +86,34 @@ def test_serve_full_configuration(potts):
                 want = lat.stats(lat.t - w, w, beta)
                 for key in ("e", "C", "V_L", "m", "chi"):
                     assert got[i]["points"][k][key] == pytest.approx(want[key], rel=1e-14, abs=1e-300), (i, k, key)
+
+
+def test_heatbath_benchmark_configuration(potts, oracle_lib):
+    """The heat-bath workload's lattice (L = 8192, q = 9, beta = 1.02 ln 4,
+    random start, seed 1) on the path the benchmark times: the first two
+    sweeps, every spin and record against the oracle."""
+    import math
+
+    L, q, seed, n = 8192, 9, 1, 2
+    beta = 1.02 * math.log(4.0)
+    print(f"heat-bath benchmark configuration: L={L} q={q} sweeps={n}", flush=True)
+    s = oracle_lib.init(L, q, seed, 1)
+    rec = oracle_lib.heatbath_sweeps(s, q, seed, 0, n, oracle_lib.threshold_table(beta))
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep_heatbath(beta, n)
+        assert np.array_equal(lat.records(0, n), rec)
+        assert np.array_equal(lat.spins(), s)
+
+
+def test_second_neighbour_benchmark_configuration(potts, oracle_lib):
+    """The second-neighbour workload's lattice (L = 8184, q = 9, j2 = 0.5,
+    beta = 0.8, random start, seed 1) on the kernel the benchmark times: the
+    first two sweeps, every spin and record against the oracle."""
+    L, q, seed, n, beta, j2 = 8184, 9, 1, 2, 0.8, 0.5
+    print(f"second-neighbour benchmark configuration: L={L} q={q} sweeps={n}", flush=True)
+    s = oracle_lib.init(L, q, seed, 1)
+    rec = oracle_lib.nnn_sweeps(s, q, seed, 0, n, oracle_lib.nnn_table(beta, j2))
+    with potts.NnnLattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, j2, n)
+        assert np.array_equal(lat.records(0, n), rec)
+        assert np.array_equal(lat.spins(), s)
