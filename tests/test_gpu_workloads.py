@@ -4,7 +4,8 @@ one batch with hipGraph and in-run tuning): sampled jobs against the oracle
 (the smallest lattices, every record and the final spins), the largest jobs
 against the same job run alone, and properties of every job.  Serving: the
 1000-job burst against the single-lattice path.  Heat-bath and second
-neighbours: the benchmark lattices' first sweeps against the oracle."""
+neighbours: the benchmark lattices' first sweeps against the oracle.  Simple
+cubic: sampled windows of the benchmark cube against the oracle."""
 import numpy as np
 import pytest
 
@@ -117,3 +118,26 @@ def test_second_neighbour_benchmark_configuration(potts, oracle_lib):
         lat.sweep(beta, j2, n)
         assert np.array_equal(lat.records(0, n), rec)
         assert np.array_equal(lat.spins(), s)
+
+
+def test_cube_benchmark_configuration(potts, oracle_lib):
+    """The simple-cubic workload's cube (L = 1024, q = 3, beta = 0.5505, random
+    start, seed 1) on the kernel the benchmark times (automatic: colour-split):
+    two sweeps, windows at the origin, across the periodic faces and inside
+    against the oracle's window restriction, the last record against the
+    observables kernel and the populations summing to N."""
+    L, q, seed, beta, n = 1024, 3, 1, 0.5505, 2
+    print(f"cube benchmark configuration: L={L} q={q} sweeps={n}", flush=True)
+    thr = oracle_lib.threshold_table6(beta)
+    with potts.Cube(L, q, seed, 1) as c:
+        c.sweep(beta, n)
+        rec = c.records(0, n)
+        obs = c.observables()
+        spins = c.spins()
+    assert np.all(rec[:, 1:].sum(axis=1) == L**3)
+    assert rec[-1, 0] == obs["e_sat"] and np.array_equal(rec[-1, 1:], obs["hist"])
+    d, r = 16, 2 * n
+    for (x0, y0, z0) in [(0, 0, 0), (L - 8, L - 8, L - 8), (L - d, 3, L - 9), (500, 511, 512), (31, 32, 33)]:
+        win = oracle_lib.window3d(L, q, seed, 1, n, thr, x0, y0, z0, d)
+        idx = [(c0 + np.arange(r, d - r)) % L for c0 in (z0, y0, x0)]
+        assert np.array_equal(win[r:d - r, r:d - r, r:d - r], spins[np.ix_(*idx)]), (x0, y0, z0)
