@@ -5,7 +5,9 @@ one batch with hipGraph and in-run tuning): sampled jobs against the oracle
 against the same job run alone, and properties of every job.  Serving: the
 1000-job burst against the single-lattice path.  Heat-bath and second
 neighbours: the benchmark lattices' first sweeps against the oracle.  Simple
-cubic: sampled windows of the benchmark cube against the oracle."""
+cubic: sampled windows of the benchmark cube against the oracle.  Ramps: the
+first points of the benchmark's heating and cooling runs against the
+oracle."""
 import numpy as np
 import pytest
 
@@ -141,3 +143,34 @@ def test_cube_benchmark_configuration(potts, oracle_lib):
         win = oracle_lib.window3d(L, q, seed, 1, n, thr, x0, y0, z0, d)
         idx = [(c0 + np.arange(r, d - r)) % L for c0 in (z0, y0, x0)]
         assert np.array_equal(win[r:d - r, r:d - r, r:d - r], spins[np.ix_(*idx)]), (x0, y0, z0)
+
+
+@pytest.mark.parametrize("q,start", [(15, 0), (6, 1)])
+def test_ramp_benchmark_configuration(potts, oracle_lib, q, start):
+    """The ramp workload's lattice (L = 8192, the benchmark's 64-point beta grid
+    within +-2 % of beta_c(q), heating from the ordered start with beta
+    descending or cooling from the random start with beta ascending): its
+    first two points with 1 + 2 sweeps each, the spins and every point's
+    derived statistics against the oracle."""
+    from oracle.stats import derived
+    from paper_1101_0876_amd.workloads import beta_c
+
+    L, seed, t_equil, t_meas = 8192, 1, 1, 2
+    grid = beta_c(q) * (0.98 + 0.04 * np.arange(64) / 63)
+    betas = (grid[::-1] if start == 0 else grid)[:2]
+    print(f"ramp benchmark configuration: L={L} q={q} start={start}", flush=True)
+    s = oracle_lib.init(L, q, seed, start)
+    t, want = 0, []
+    for b in betas:
+        rec = oracle_lib.sweeps(s, q, seed, t, t_equil + t_meas, oracle_lib.threshold_table(b))
+        t += t_equil + t_meas
+        w = rec[t_equil:]
+        want.append(derived(w[:, 0].tolist(), w[:, 1:].max(axis=1).tolist(), L * L, q, float(b)))
+    with potts.Lattice(L, q, seed, start) as lat:
+        got = lat.ramp(betas, t_equil, t_meas)
+        assert lat.t == t
+        assert np.array_equal(lat.spins(), s)
+    for g, w in zip(got, want):
+        assert g["n"] == t_meas
+        for key in ("e", "C", "V_L", "m", "chi"):
+            assert g[key] == pytest.approx(w[key], rel=1e-12, abs=1e-300), key
