@@ -95,13 +95,22 @@ typedef struct {
  * ERANGE (L*L/4 >= 2^32), ENOMEM, EDEVICE.  On error *out is NULL. */
 int potts_init(int32_t L, int32_t q, uint64_t seed, potts_start start, potts_state **out);
 
-/* As potts_init, but on caller-owned device buffers and stream: dev_spins and
- * dev_spins2 each hold at least L*L bytes (bytes gives the size of each) and
- * must outlive the state; hip_stream is a hipStream_t (NULL = the default
- * stream).  dev_spins holds the row-major lattice between calls; dev_spins2
- * is the library's scratch (the colour-split copy a sweep call works on), so
- * neither may be touched while a call's work is in flight on the stream.  The
- * records ring is still owned by the library. */
+/* As potts_init, on the caller's stream and optionally on caller-owned device
+ * buffers.  hip_stream is a hipStream_t (NULL = the default stream); the state
+ * never destroys it.
+ *   dev_spins, dev_spins2 both non-NULL: caller-owned buffers of at least L*L
+ *     bytes each (bytes gives the size of each), which must outlive the state.
+ *     dev_spins holds the row-major lattice (byte y*L + x = site (x, y)) from
+ *     the end of every call to the start of the next one, in stream order: a
+ *     caller may read it, or write values 0..q-1 into it, between calls
+ *     (ordered on hip_stream), and the next sweep starts from what it holds.
+ *     dev_spins2 is the library's scratch (the colour-split copy a sweep call
+ *     works on).  Neither may be touched while a call's work is in flight.
+ *   both NULL: the library allocates and owns both buffers (as potts_init),
+ *     and keeps the colour-split copy between calls; the row-major lattice is
+ *     then read through potts_device_spins or potts_get_spins.
+ *   one NULL: EINVAL.
+ * The records ring is owned by the library in every case. */
 int potts_init_ex(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spins,
                   void *dev_spins2, size_t bytes, void *hip_stream, int64_t records_capacity,
                   potts_state **out);
@@ -180,6 +189,19 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
                           int64_t t, int32_t colour, const uint32_t thr[4], int64_t *dev_ring,
                           int64_t ring_slots, void *hip_stream);
 
+/* The records of a lattice swept slab by slab: record r (r = 0 .. n-1) of
+ * sweep t0 + r is the sum over the nslabs slab rings of slot (t0 + r) %
+ * ring_slots ({e_sat share, hist share}, 1+q int64 each), written to
+ * dev_out[r*(1+q) .. ].  dev_rings: device, the nslabs rings stored one after
+ * another (ring g at dev_rings + g * ring_slots * (1+q)), as the slabs' calls
+ * of potts_slab_half_sweep filled them.  Asynchronous on hip_stream (a
+ * hipStream_t, NULL = the default stream); the caller keeps the records of
+ * sweeps t0 .. t0+n-1 in the rings (n <= ring_slots - 1 of them survive a
+ * sweep).  Errors: EINVAL (NULL, nslabs < 1, q outside 2..256, ring_slots not
+ * a power of two >= 2, t0 < 0, n outside 0..ring_slots), EDEVICE. */
+int potts_slab_records(const int64_t *dev_rings, int32_t nslabs, int64_t ring_slots, int32_t q, int64_t t0,
+                       int64_t n, int64_t *dev_out, void *hip_stream);
+
 /* Observables of the current configuration (synchronizes the stream).  Uses
  * the last sweep's record, or measures the lattice if no sweep has run. */
 int potts_observables(potts_state *s, potts_obs *out);
@@ -235,13 +257,17 @@ int potts_ramp(potts_state *s, const double *betas, int32_t npoints, int64_t t_e
 int potts_get_spins(potts_state *s, uint8_t *host_out);
 int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t);
 
-/* Device pointer of the current lattice, row-major (valid until the next
- * sweep call).  After colour-split sweeps this first queues the kernel that
- * rebuilds the row-major lattice on the state's stream: read the buffer on
- * that stream or after synchronizing it.  NULL if s is NULL or the kernel
- * could not be queued. */
+/* Device pointer of the current lattice, row-major, L*L bytes (valid until the
+ * next sweep call).  After colour-split sweeps this first queues the kernel
+ * that rebuilds the row-major lattice on the state's stream: read or write the
+ * buffer on that stream or after synchronizing it.  The next sweep starts from
+ * what the buffer then holds (values must stay below q).  NULL if s is NULL or
+ * the kernel could not be queued. */
 void *potts_device_spins(potts_state *s);
 int64_t potts_time(const potts_state *s);
+/* The state's stream (a hipStream_t): the one given to potts_init_ex, or the
+ * one potts_init created.  NULL if s is NULL. */
+void *potts_stream(const potts_state *s);
 
 /* Checkpoint: (L, q, seed, t, lattice) to a file and back; a resumed state
  * continues with exactly the same random numbers.  Errors: EIO, EINVAL. */

@@ -61,6 +61,19 @@ class Lattice:
         return cls(L, q, seed, start, _handle=h, _keep=(a, b, st))
 
     @classmethod
+    def on_stream(cls, L: int, q: int, seed: int = 1, start: int = RANDOM, stream=None,
+                  records_capacity: int = 0) -> "Lattice":
+        """A state whose buffers the library owns, working on a caller's stream
+        (a torch.cuda.Stream, or None for the current one)."""
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        check(load().potts_init_ex(L, q, seed, start, None, None, 0, ctypes.c_void_p(st.cuda_stream),
+                                   int(records_capacity), ctypes.byref(h)))
+        return cls(L, q, seed, start, _handle=h, _keep=(st,))
+
+    @classmethod
     def load_checkpoint(cls, path: str) -> "Lattice":
         h = ctypes.c_void_p()
         check(load().potts_load(os.fsencode(path), ctypes.byref(h)))
@@ -156,6 +169,10 @@ class Lattice:
 
     def device_ptr(self) -> int:
         return int(self._lib.potts_device_spins(self._h) or 0)
+
+    def stream_ptr(self) -> int:
+        """The state's hipStream_t as an integer."""
+        return int(self._lib.potts_stream(self._h) or 0)
 
     def save(self, path: str) -> None:
         check(self._lib.potts_save(self._h, os.fsencode(path)))

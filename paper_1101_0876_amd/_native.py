@@ -141,6 +141,8 @@ SIGNATURES = [
     ("potts_slab_half_sweep", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _U32P, _VP,
                                              ctypes.c_int64, _VP]),
+    ("potts_slab_records", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.c_int64, _VP, _VP]),
     ("potts_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
     ("potts_measure", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
     ("potts_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
@@ -156,6 +158,7 @@ SIGNATURES = [
     ("potts_set_spins", ctypes.c_int, [_VP, _U8P, ctypes.c_int64]),
     ("potts_device_spins", _VP, [_VP]),
     ("potts_time", ctypes.c_int64, [_VP]),
+    ("potts_stream", _VP, [_VP]),
     ("potts_save", ctypes.c_int, [_VP, ctypes.c_char_p]),
     ("potts_load", ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
     ("potts_batch_create", ctypes.c_int, [ctypes.POINTER(PottsJob), ctypes.c_int32,

@@ -134,17 +134,16 @@ int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spi
   if (rec_cap < 2 || rec_cap > (1ll << 40)) return fail(POTTS_EINVAL, "records_capacity must be in 2 .. 2^40");
   rec_cap = ring_slots(rec_cap);
   const size_t nbytes = (size_t)L * (size_t)L;
-  if (external && (!dev_spins || !dev_spins2 || bytes < nbytes))
-    return fail(POTTS_EINVAL, "external buffers missing or smaller than L*L bytes");
+  // caller buffers: both or neither (neither = library-owned buffers on the caller's stream)
+  const bool ext_buffers = external && (dev_spins || dev_spins2);
+  if (ext_buffers && (!dev_spins || !dev_spins2 || bytes < nbytes))
+    return fail(POTTS_EINVAL, "give both buffers (each at least L*L bytes) or neither");
   potts_state *s = new (std::nothrow) potts_state();
   if (!s) return fail(POTTS_ENOMEM, "host allocation failed");
   s->L = L;
   s->q = q;
   s->seed = seed;
   if (external) {
-    s->owns_spins = false;
-    s->spins = (uint8_t *)dev_spins;
-    s->spins2 = (uint8_t *)dev_spins2;
     s->stream = (hipStream_t)stream;
   } else {
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -153,6 +152,12 @@ int create(int32_t L, int32_t q, uint64_t seed, potts_start start, void *dev_spi
       return hip_fail(e, "hipStreamCreateWithFlags");
     }
     s->owns_stream = true;
+  }
+  if (ext_buffers) {
+    s->owns_spins = false;
+    s->spins = (uint8_t *)dev_spins;
+    s->spins2 = (uint8_t *)dev_spins2;
+  } else {
     if (hipMalloc(&s->spins, nbytes) != hipSuccess || hipMalloc(&s->spins2, nbytes) != hipSuccess) {
       (void)hipGetLastError();
       release(s);
@@ -376,6 +381,13 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
   }
   s->t += nsweeps;
+  if (!s->owns_spins) {
+    // caller-owned buffers: the row-major lattice is current after every call,
+    // and the next call packs it again, so writes between calls are seen
+    HIP_TRY(potts::launch_unpack(s->spins2, s->spins, L, s->stream));
+    s->spins_valid = true;
+    s->planes_valid = false;
+  }
   return POTTS_OK;
 }
 
@@ -601,6 +613,20 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
   const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
   const unsigned grid = (unsigned)(need < 8192 ? need : 8192);
   HIP_TRY(potts::launch_strip(l, colour, grid, p.q, wide_table(thr), static_cast<hipStream_t>(hip_stream)));
+  return POTTS_OK;
+}
+
+int potts_slab_records(const int64_t *dev_rings, int32_t nslabs, int64_t ring_slots, int32_t q, int64_t t0,
+                       int64_t n, int64_t *dev_out, void *hip_stream) {
+  if (!dev_rings || (!dev_out && n > 0)) return fail(POTTS_EINVAL, "dev_rings or dev_out is NULL");
+  if (nslabs < 1 || q < 2 || q > POTTS_QMAX) return fail(POTTS_EINVAL, "need nslabs >= 1 and 2 <= q <= 256");
+  if (ring_slots < 2 || (ring_slots & (ring_slots - 1)))
+    return fail(POTTS_EINVAL, "ring_slots must be a power of two >= 2");
+  if (t0 < 0 || n < 0 || n > ring_slots) return fail(POTTS_EINVAL, "need t0 >= 0 and 0 <= n <= ring_slots");
+  HIP_TRY(potts::launch_slab_fold(reinterpret_cast<const unsigned long long *>(dev_rings), (uint32_t)nslabs,
+                                  (uint64_t)ring_slots, (uint32_t)q + 1, (uint64_t)t0, (uint64_t)n,
+                                  reinterpret_cast<unsigned long long *>(dev_out),
+                                  static_cast<hipStream_t>(hip_stream)));
   return POTTS_OK;
 }
 
@@ -830,10 +856,14 @@ int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t) {
 
 void *potts_device_spins(potts_state *s) {
   if (!s || sync_spins(s)) return nullptr;
+  // the caller may write through the pointer: the next sweep packs again
+  s->planes_valid = false;
   return (void *)s->spins;
 }
 
 int64_t potts_time(const potts_state *s) { return s ? s->t : -1; }
+
+void *potts_stream(const potts_state *s) { return s ? (void *)s->stream : nullptr; }
 
 int potts_save(potts_state *s, const char *path) {
   if (!s || !path) return fail(POTTS_EINVAL, "NULL argument");

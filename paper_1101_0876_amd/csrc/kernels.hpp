@@ -171,6 +171,10 @@ hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max
 hipError_t launch_measure(const MeasureParams &p, hipStream_t stream);
 hipError_t launch_stats(const StatsParams &p, hipStream_t stream);
 hipError_t launch_reweight(const ReweightParams &p, unsigned npoints, hipStream_t stream);
+// out[r][w] = sum over g < nslabs of slot (t0 + r) % slots, word w, of ring g
+// (rings stored one after another, slots x width words each), r < n
+hipError_t launch_slab_fold(const unsigned long long *rings, uint32_t nslabs, uint64_t slots, uint32_t width,
+                            uint64_t t0, uint64_t n, unsigned long long *out, hipStream_t stream);
 // one workgroup per window, params in device memory
 hipError_t launch_stats_many(const StatsParams *dev_params, unsigned n, hipStream_t stream);
 

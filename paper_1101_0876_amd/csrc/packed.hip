@@ -13,8 +13,9 @@
 // for active index i, chunk y*(L/4) + i/2 and pair i & 1, are the contract's).
 //
 // A single lattice is packed into the state's second buffer before its first
-// colour-split sweep and unpacked only when the row-major lattice is read
-// (capi.hip); batches pack their jobs before a run and unpack them after it.
+// colour-split sweep and unpacked when the row-major lattice is read, or at the
+// end of every call when the caller owns the buffers (capi.hip); batches pack
+// their jobs before a run and unpack them after it.
 // Both copies are plain streaming kernels.
 //
 // Work item: 16 packed bytes (16 active sites) of R consecutive rows of the
@@ -113,7 +114,10 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   fill_accept_table<WIDE>(table, p.thr);
   const uint32_t nh = PRIV ? 64 * q : q;
   for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-  if (threadIdx.x == 0) partial[q] = 0;
+  // a workgroup's bond count reaches 2N / grid, beyond 32 bits on the largest
+  // lattices with few workgroups: counted in 64 bits
+  __shared__ unsigned long long esum;
+  if (threadIdx.x == 0) esum = 0;
   if (p.stripes) {
     __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
     if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<kBlock>(p, t - 1, fold_acc);
@@ -163,10 +167,10 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   }
 
   unsigned long long *rec = p.ring + (t & (p.cap - 1)) * (uint64_t)(q + 1);
-  uint32_t *esum = partial + q;
   if (COLOUR == 1) {
+    // at most 4 x 2^29 bonds per wave (L < 2^16): 32 bits suffice up to here
     const uint32_t e = wave_sum(4u * sums.sites - sums.nz);
-    if (lane == 0 && e) atomicAdd(esum, e);
+    if (lane == 0 && e) atomicAdd(&esum, (unsigned long long)e);
   }
   __syncthreads();
   if (PRIV) {
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
     const uint32_t s = PRIV ? partial[v] : hist[v];
     if (s) atomicAdd(&dst[1 + v], (unsigned long long)s);
   }
-  if (COLOUR == 1 && threadIdx.x == 0 && *esum) atomicAdd(&dst[0], (unsigned long long)*esum);
+  if (COLOUR == 1 && threadIdx.x == 0 && esum) atomicAdd(&dst[0], esum);
 }
 
 // Row-major lattice <-> two colour planes; one thread per 32 bytes of a row

@@ -200,7 +200,30 @@ __global__ __launch_bounds__(kStatsBlock) void reweight_kernel(ReweightParams p)
   out[4] = beta * (U2 - U1 * U1) / (N * q1 * q1);
 }
 
+// Sum of the records of n sweeps over G slab rings stored one after another
+// (ring g at rings + g * slots * width): one thread per output word.
+__global__ __launch_bounds__(256) void slab_fold_kernel(const unsigned long long *rings, uint32_t nslabs,
+                                                        uint64_t slots, uint32_t width, uint64_t t0, uint64_t n,
+                                                        unsigned long long *out) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * width) return;
+  const uint64_t r = i / width, w = i - r * width;
+  const uint64_t at = ((t0 + r) & (slots - 1)) * width + w;
+  unsigned long long sum = 0;
+  for (uint32_t g = 0; g < nslabs; ++g) sum += rings[g * slots * width + at];
+  out[i] = sum;
+}
+
 }  // namespace
+
+hipError_t launch_slab_fold(const unsigned long long *rings, uint32_t nslabs, uint64_t slots, uint32_t width,
+                            uint64_t t0, uint64_t n, unsigned long long *out, hipStream_t stream) {
+  const uint64_t total = n * width;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(slab_fold_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, rings, nslabs,
+                     slots, width, t0, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_reweight(const ReweightParams &p, unsigned npoints, hipStream_t stream) {
   if (npoints == 0) return hipSuccess;

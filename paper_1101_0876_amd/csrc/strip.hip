@@ -108,7 +108,10 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   fill_accept_table<WIDE>(table, p.thr);
   const uint32_t nh = PRIV ? 64 * q : q;
   for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
-  if (threadIdx.x == 0) partial[q] = 0;
+  // a workgroup's bond count reaches 2N / grid, beyond 32 bits on the largest
+  // lattices with few workgroups: counted in 64 bits
+  __shared__ unsigned long long esum;
+  if (threadIdx.x == 0) esum = 0;
   if (p.stripes) {
     // the previous launched sweep's partial records, complete now
     __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
@@ -163,10 +166,10 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   }
 
   unsigned long long *rec = p.ring + (t & (p.cap - 1)) * (uint64_t)(q + 1);
-  uint32_t *esum = partial + q;
   if (COLOUR == 1) {
+    // at most 4 x 2^29 bonds per wave (L < 2^16): 32 bits suffice up to here
     const uint32_t e = wave_sum(4u * sums.sites - sums.nz);
-    if (lane == 0 && e) atomicAdd(esum, e);
+    if (lane == 0 && e) atomicAdd(&esum, (unsigned long long)e);
   }
   __syncthreads();
   if (PRIV) {
@@ -182,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
     const uint32_t s = PRIV ? partial[v] : hist[v];
     if (s) atomicAdd(&dst[1 + v], (unsigned long long)s);
   }
-  if (COLOUR == 1 && threadIdx.x == 0 && *esum) atomicAdd(&dst[0], (unsigned long long)*esum);
+  if (COLOUR == 1 && threadIdx.x == 0 && esum) atomicAdd(&dst[0], esum);
 }
 
 __global__ __launch_bounds__(kBlock) void fold_kernel(StripParams p, uint64_t t) {

@@ -205,25 +205,24 @@ __device__ __forceinline__ Row8 update8(uint32_t s_lo, uint32_t s_hi, uint32_t p
     const uint32_t t0 = POTTS_T(0, idx_lo), t1 = POTTS_T(1, idx_lo), t2 = POTTS_T(2, idx_lo), t3 = POTTS_T(3, idx_lo);
     const uint32_t t4 = POTTS_T(0, idx_hi), t5 = POTTS_T(1, idx_hi), t6 = POTTS_T(2, idx_hi), t7 = POTTS_T(3, idx_hi);
 #undef POTTS_T
-    ns_lo = s_lo;
-    ns_hi = s_hi;
+    // byte 0 by a whole-dword select (its other bytes are overwritten next),
+    // which saves copying s into the destination first
+    const bool a0 = b0.w1 <= t0, a4 = b2.w1 <= t4;
+    ns_lo = a0 ? k_lo : s_lo;
+    ns_hi = a4 ? k_hi : s_hi;
     if (COLOUR == 0) {
-      accept_byte<0>(ns_lo, b0.w1, t0, s_lo, k_lo);
       accept_byte<1>(ns_lo, b0.w3, t1, s_lo, k_lo);
       accept_byte<2>(ns_lo, b1.w1, t2, s_lo, k_lo);
       accept_byte<3>(ns_lo, b1.w3, t3, s_lo, k_lo);
-      accept_byte<0>(ns_hi, b2.w1, t4, s_hi, k_hi);
       accept_byte<1>(ns_hi, b2.w3, t5, s_hi, k_hi);
       accept_byte<2>(ns_hi, b3.w1, t6, s_hi, k_hi);
       accept_byte<3>(ns_hi, b3.w3, t7, s_hi, k_hi);
     } else {
-      nz_lo = ps_lo;
-      nz_hi = ps_hi;
-      accept_byte2<0>(ns_lo, nz_lo, b0.w1, t0, s_lo, k_lo, ps_lo, pk_lo);
+      nz_lo = a0 ? pk_lo : ps_lo;
+      nz_hi = a4 ? pk_hi : ps_hi;
       accept_byte2<1>(ns_lo, nz_lo, b0.w3, t1, s_lo, k_lo, ps_lo, pk_lo);
       accept_byte2<2>(ns_lo, nz_lo, b1.w1, t2, s_lo, k_lo, ps_lo, pk_lo);
       accept_byte2<3>(ns_lo, nz_lo, b1.w3, t3, s_lo, k_lo, ps_lo, pk_lo);
-      accept_byte2<0>(ns_hi, nz_hi, b2.w1, t4, s_hi, k_hi, ps_hi, pk_hi);
       accept_byte2<1>(ns_hi, nz_hi, b2.w3, t5, s_hi, k_hi, ps_hi, pk_hi);
       accept_byte2<2>(ns_hi, nz_hi, b3.w1, t6, s_hi, k_hi, ps_hi, pk_hi);
       accept_byte2<3>(ns_hi, nz_hi, b3.w3, t7, s_hi, k_hi, ps_hi, pk_hi);
@@ -287,14 +286,15 @@ __device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint
 #define POTTS_T(J) *reinterpret_cast<const uint32_t *>(table + table_offset<J, 2>(idx))
     const uint32_t t0 = POTTS_T(0), t1 = POTTS_T(1), t2 = POTTS_T(2), t3 = POTTS_T(3);
 #undef POTTS_T
+    // byte 0 by a whole-dword select, bytes 1..3 overwritten next
+    const bool a0 = b0.w1 <= t0;
+    ns = a0 ? k : s;
     if (COLOUR == 0) {
-      accept_byte<0>(ns, b0.w1, t0, s, k);
       accept_byte<1>(ns, b0.w3, t1, s, k);
       accept_byte<2>(ns, b1.w1, t2, s, k);
       accept_byte<3>(ns, b1.w3, t3, s, k);
     } else {
-      nz = ps;
-      accept_byte2<0>(ns, nz, b0.w1, t0, s, k, ps, pk);
+      nz = a0 ? pk : ps;
       accept_byte2<1>(ns, nz, b0.w3, t1, s, k, ps, pk);
       accept_byte2<2>(ns, nz, b1.w1, t2, s, k, ps, pk);
       accept_byte2<3>(ns, nz, b1.w3, t3, s, k, ps, pk);

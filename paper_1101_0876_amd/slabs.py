@@ -56,7 +56,9 @@ class Slabs:
                 s[1:h + 1].copy_(grid[g * h:(g + 1) * h])
                 self.buf.append(s)
             torch.cuda.current_stream(a.device).synchronize()
-        self.rings = [torch.zeros((self.slots, q + 1), dtype=torch.int64, device=device) for _ in range(self.G)]
+        # the G rings one after another, as potts_slab_records reads them
+        self.ring_store = torch.zeros((self.G, self.slots, q + 1), dtype=torch.int64, device=device)
+        self.rings = [self.ring_store[g] for g in range(self.G)]
 
     def _exchange(self) -> None:
         G, h = self.G, self.h
@@ -80,13 +82,17 @@ class Slabs:
             self.t += 1
 
     def records(self, t0: int, n: int) -> np.ndarray:
-        """Records of sweeps t0 .. t0+n-1, summed over the slabs (the last
-        ring_slots - 1 sweeps are kept)."""
+        """Records of sweeps t0 .. t0+n-1, summed over the slabs by
+        potts_slab_records (the last ring_slots - 1 sweeps are kept)."""
+        import torch
+
         if t0 < max(0, self.t - self.slots + 1) or t0 + n > self.t:
             raise ValueError("records not in the rings")
-        idx = [(t0 + i) % self.slots for i in range(n)]
-        tot = sum(r[idx] for r in self.rings)
-        return tot.cpu().numpy()
+        out = torch.empty((n, self.q + 1), dtype=torch.int64, device=self.ring_store.device)
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+        check(load().potts_slab_records(ctypes.c_void_p(self.ring_store.data_ptr()), self.G, self.slots, self.q,
+                                        int(t0), int(n), ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)))
+        return out.cpu().numpy()
 
     def spins(self) -> np.ndarray:
         import torch

@@ -172,3 +172,24 @@ def test_product_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "potts_oracle" not in text and "liboracle" not in text, f
+
+
+def test_slab_records_validates_without_device(lib):
+    buf = ctypes.c_void_p(8)  # never dereferenced: every call below fails validation first
+    assert lib.potts_slab_records(None, 2, 8, 3, 0, 1, buf, None) == -1
+    assert lib.potts_slab_records(buf, 2, 8, 3, 0, 1, None, None) == -1
+    assert lib.potts_slab_records(buf, 0, 8, 3, 0, 1, buf, None) == -1
+    assert lib.potts_slab_records(buf, 2, 6, 3, 0, 1, buf, None) == -1
+    assert lib.potts_slab_records(buf, 2, 8, 1, 0, 1, buf, None) == -1
+    assert lib.potts_slab_records(buf, 2, 8, 3, -1, 1, buf, None) == -1
+    assert lib.potts_slab_records(buf, 2, 8, 3, 0, 9, buf, None) == -1
+
+
+def test_init_ex_needs_both_buffers_or_neither(lib):
+    h = ctypes.c_void_p()
+    assert lib.potts_init_ex(64, 3, 1, 1, ctypes.c_void_p(8), None, 4096, None, 0, ctypes.byref(h)) == -1
+    assert lib.potts_init_ex(64, 3, 1, 1, None, ctypes.c_void_p(8), 4096, None, 0, ctypes.byref(h)) == -1
+    assert lib.potts_init_ex(64, 3, 1, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), 100, None, 0,
+                             ctypes.byref(h)) == -1
+    assert not h.value
+    assert lib.potts_stream(None) is None

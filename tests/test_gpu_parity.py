@@ -206,6 +206,59 @@ def test_colour_split_copy_stays_in_step(potts, oracle_lib):
         assert np.array_equal(lat.spins(), s)
 
 
+def test_caller_buffer_holds_the_lattice_between_calls(potts, oracle_lib):
+    """Caller-owned buffers on the colour-split path: after every sweep call the
+    caller's dev_spins tensor holds the row-major lattice (read directly, with
+    no library call), and a configuration the caller writes into it between
+    calls is where the next sweep starts."""
+    import torch
+
+    L, q, seed, beta = 512, 6, 9, beta_c(6)
+    thr = oracle_lib.threshold_table(beta)
+    s = oracle_lib.init(L, q, seed, 1)
+    stream = torch.cuda.Stream()
+    with potts.Lattice.from_torch(L, q, seed, 1, stream=stream) as lat:
+        a, _, _ = lat._keep
+        for n, t in ((3, 0), (1, 3)):
+            lat.sweep(beta, n)
+            stream.synchronize()
+            oracle_lib.sweeps(s, q, seed, t, n, thr, record=False)
+            assert np.array_equal(a[:L * L].cpu().numpy().reshape(L, L), s), t
+        w = np.random.default_rng(5).integers(0, q, (L, L), dtype=np.uint8)
+        with torch.cuda.stream(stream):
+            a[:L * L].copy_(torch.from_numpy(w.ravel()).to(a.device, non_blocking=False))
+        lat.sweep(beta, 2)
+        stream.synchronize()
+        rec = oracle_lib.sweeps(w, q, seed, 4, 2, thr)
+        assert np.array_equal(a[:L * L].cpu().numpy().reshape(L, L), w)
+        assert np.array_equal(lat.records(4, 2), rec)
+        assert np.array_equal(lat.spins(), w)
+
+
+def test_device_pointer_writes_reach_the_next_sweep(potts, oracle_lib):
+    """A library-owned state keeps its colour-split copy between calls; a
+    configuration written through potts_device_spins between calls is where
+    the next sweep starts."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+    L, q, seed, beta = 512, 5, 13, beta_c(5)
+    thr = oracle_lib.threshold_table(beta)
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(beta, 2)
+        ptr = lat.device_ptr()
+        assert hip.hipStreamSynchronize(ctypes.c_void_p(lat.stream_ptr())) == 0
+        w = np.random.default_rng(6).integers(0, q, (L, L), dtype=np.uint8)
+        assert hip.hipMemcpy(ctypes.c_void_p(ptr), w.ctypes.data_as(ctypes.c_void_p), L * L, 1) == 0
+        assert hip.hipDeviceSynchronize() == 0
+        lat.sweep(beta, 3)
+        rec = oracle_lib.sweeps(w, q, seed, 2, 3, thr)
+        assert np.array_equal(lat.records(2, 3), rec)
+        assert np.array_equal(lat.spins(), w)
+
+
 @pytest.mark.parametrize("window", [(0, 200), (150, 400), (7, 8)])
 def test_derived_stats_match_oracle(potts, oracle_lib, window):
     from oracle.stats import derived

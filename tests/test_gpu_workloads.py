@@ -1,12 +1,7 @@
-"""Workloads at their full configurations, in the launch configurations the
-benchmark times.  Batched replicas (1024 jobs of L = 128 .. 4096, 500 sweeps,
-one batch with hipGraph and in-run tuning): sampled jobs against the oracle
-(the smallest lattices, every record and the final spins), the largest jobs
-against the same job run alone, and properties of every job.  Serving: the
-1000-job burst against the single-lattice path.  Heat-bath and second
-neighbours: the benchmark lattices' first sweeps against the oracle.  Simple
-cubic: sampled windows of the benchmark cube against the oracle.  Ramps: the
-first points of the benchmark's heating and cooling runs against the
+"""The variants' benchmark configurations, in the launch configurations the
+benchmark times (the main path's workloads are in test_gpu_fullsize.py).
+Heat-bath and second neighbours: the benchmark lattices' first sweeps against
+the oracle.  Simple cubic: sampled windows of the benchmark cube against the
 oracle."""
 import numpy as np
 import pytest
@@ -24,71 +19,6 @@ def potts():
 
     p.load()
     return p
-
-
-def test_batch_full_configuration(potts, oracle_lib):
-    from paper_1101_0876_amd.workloads import batch_jobs
-
-    jobs = batch_jobs()
-    assert len(jobs) == 1024 and all(j["nsweeps"] == 500 for j in jobs)
-    print("batch full configuration: 1024 jobs", flush=True)
-    by_size = sorted(range(len(jobs)), key=lambda i: (jobs[i]["L"], i))
-    small, large = by_size[:3], by_size[-2:]
-    with potts.Batch(jobs, graph=True, tune=True) as b:
-        b.run()
-        res = b.results()
-        for i, (r, j) in enumerate(zip(res, jobs)):
-            assert r["t"] == 500
-            last = b.records(i, 499, 1)
-            assert int(last[0, 1:].sum()) == j["L"] ** 2, i
-            assert r["e_sat"] == last[0, 0] and 0 <= r["e_sat"] <= 2 * j["L"] ** 2
-        for i in small:
-            j = jobs[i]
-            print(f"oracle job {i}: L={j['L']} q={j['q']}", flush=True)
-            s = oracle_lib.init(j["L"], j["q"], j["seed"], j["start"])
-            rec = oracle_lib.sweeps(s, j["q"], j["seed"], 0, 500, oracle_lib.threshold_table(j["beta"]))
-            assert np.array_equal(b.records(i, 0, 500), rec), i
-            assert np.array_equal(b.spins(i), s), i
-        for i in large:
-            j = jobs[i]
-            print(f"alone job {i}: L={j['L']} q={j['q']}", flush=True)
-            with potts.Lattice(j["L"], j["q"], j["seed"], j["start"]) as lat:
-                lat.sweep(j["beta"], 500)
-                assert np.array_equal(lat.records(0, 500), b.records(i, 0, 500)), i
-                assert np.array_equal(lat.spins(), b.spins(i)), i
-
-
-def test_serve_full_configuration(potts):
-    """The serving workload's 1000-job burst (sweeps x 0.01) in the benchmark's
-    server configuration, submitted at once (results do not depend on the
-    schedule): every job completes with the sweeps it asked for and a
-    consistent final record, and sampled jobs' per-point summaries equal
-    those of the same ramp run alone on the single-lattice path."""
-    from paper_1101_0876_amd.workloads import serve_jobs
-
-    jobs = serve_jobs(sweep_scale=0.01)
-    print("serve full configuration: 1000 jobs", flush=True)
-    with potts.Server(quantum=32, max_slots=256) as srv:
-        tickets = [srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"]) for j in jobs]
-        srv.drain(300000)
-        got = [srv.collect(t) for t in tickets]
-    for g, j in zip(got, jobs):
-        assert g["status"] == 0 and g["sweeps"] == sum(j["sweeps"])
-        assert 0 <= g["e_sat"] <= 2 * j["L"] ** 2 and 0 < g["nmax"] <= j["L"] ** 2
-        assert len(g["points"]) == len(j["betas"])
-    work = [j["L"] ** 2 * sum(j["sweeps"]) for j in jobs]
-    order = sorted(range(len(jobs)), key=lambda i: work[i])
-    sample = order[:3] + [max(range(len(jobs)), key=lambda i: jobs[i]["L"])]
-    for i in sample:
-        j = jobs[i]
-        print(f"alone job {i}: L={j['L']} q={j['q']} points={len(j['betas'])}", flush=True)
-        with potts.Lattice(j["L"], j["q"], j["seed"], j["start"]) as lat:
-            for k, (beta, n) in enumerate(zip(j["betas"], j["sweeps"])):
-                lat.sweep(beta, n)
-                w = max(1, (n + 1) // 2)
-                want = lat.stats(lat.t - w, w, beta)
-                for key in ("e", "C", "V_L", "m", "chi"):
-                    assert got[i]["points"][k][key] == pytest.approx(want[key], rel=1e-14, abs=1e-300), (i, k, key)
 
 
 def test_heatbath_benchmark_configuration(potts, oracle_lib):
@@ -143,34 +73,3 @@ def test_cube_benchmark_configuration(potts, oracle_lib):
         win = oracle_lib.window3d(L, q, seed, 1, n, thr, x0, y0, z0, d)
         idx = [(c0 + np.arange(r, d - r)) % L for c0 in (z0, y0, x0)]
         assert np.array_equal(win[r:d - r, r:d - r, r:d - r], spins[np.ix_(*idx)]), (x0, y0, z0)
-
-
-@pytest.mark.parametrize("q,start", [(15, 0), (6, 1)])
-def test_ramp_benchmark_configuration(potts, oracle_lib, q, start):
-    """The ramp workload's lattice (L = 8192, the benchmark's 64-point beta grid
-    within +-2 % of beta_c(q), heating from the ordered start with beta
-    descending or cooling from the random start with beta ascending): its
-    first two points with 1 + 2 sweeps each, the spins and every point's
-    derived statistics against the oracle."""
-    from oracle.stats import derived
-    from paper_1101_0876_amd.workloads import beta_c
-
-    L, seed, t_equil, t_meas = 8192, 1, 1, 2
-    grid = beta_c(q) * (0.98 + 0.04 * np.arange(64) / 63)
-    betas = (grid[::-1] if start == 0 else grid)[:2]
-    print(f"ramp benchmark configuration: L={L} q={q} start={start}", flush=True)
-    s = oracle_lib.init(L, q, seed, start)
-    t, want = 0, []
-    for b in betas:
-        rec = oracle_lib.sweeps(s, q, seed, t, t_equil + t_meas, oracle_lib.threshold_table(b))
-        t += t_equil + t_meas
-        w = rec[t_equil:]
-        want.append(derived(w[:, 0].tolist(), w[:, 1:].max(axis=1).tolist(), L * L, q, float(b)))
-    with potts.Lattice(L, q, seed, start) as lat:
-        got = lat.ramp(betas, t_equil, t_meas)
-        assert lat.t == t
-        assert np.array_equal(lat.spins(), s)
-    for g, w in zip(got, want):
-        assert g["n"] == t_meas
-        for key in ("e", "C", "V_L", "m", "chi"):
-            assert g[key] == pytest.approx(w[key], rel=1e-12, abs=1e-300), key
