@@ -354,7 +354,13 @@ typedef struct {
 
 /* A job: a beta schedule (Sec. 3 protocol), point k run for sweeps[k] sweeps
  * at betas[k] with the configuration carried over.  Point k's summary covers
- * its last ceil(sweeps[k]/2) sweeps (the first half equilibrates). */
+ * its last ceil(sweeps[k]/2) sweeps (the first half equilibrates).
+ * Checkpoints: with `checkpoint` set, the server writes the job's state after
+ * every completed point but the last (lattice, sweep counter, next point and
+ * the summaries so far; the file is replaced atomically).  A request with
+ * `resume_from` naming such a file (same L, q, seed, start and schedule)
+ * continues the job from that point: since the random numbers are keyed by
+ * (seed, site, sweep), it ends with exactly the bits of an uninterrupted run. */
 typedef struct {
     int32_t L, q;            /* L % 16 == 0, 16 <= L <= 65520; 2 <= q <= 256  */
     uint64_t seed;
@@ -364,6 +370,8 @@ typedef struct {
     const int64_t *sweeps;   /* npoints, each 1 .. 2^30, copied at submit     */
     int32_t keep_spins;      /* 1: keep the final lattice for collect         */
     int32_t _pad;
+    const char *checkpoint;  /* NULL, or the job's checkpoint file (copied)   */
+    const char *resume_from; /* NULL, or a checkpoint of this job to continue */
 } potts_request;
 
 typedef struct {
@@ -380,7 +388,8 @@ typedef struct potts_server potts_server;
 int potts_server_start(const potts_server_cfg *cfg, potts_server **out);
 
 /* Queues a job (thread-safe); *ticket identifies it.  Errors: EINVAL (bad
- * fields), ENOMEM (larger than the budget), or the code that stopped a failed
+ * fields, or a resume file of another job), EIO (resume file unreadable),
+ * ENOMEM (larger than the budget), or the code that stopped a failed
  * server. */
 int potts_server_submit(potts_server *srv, const potts_request *req, int64_t *ticket);
 
@@ -393,6 +402,14 @@ int potts_server_wait(potts_server *srv, int64_t *tickets, int32_t max, int32_t 
  * the job's status.  Errors: ERANGE (unknown or unfinished ticket). */
 int potts_server_collect(potts_server *srv, int64_t ticket, potts_served *info, potts_summary *points,
                          uint8_t *spins);
+
+/* Failure injection for recovery tests, on the host only (nothing on the GPU
+ * faults): the job with this ticket, queued or running, ends with status
+ * EDEVICE at the first iteration boundary from which its next iteration would
+ * run sweep at_sweep (a 0-based sweep index of the job); its device memory is
+ * released and the other jobs go on.  Errors: EINVAL (NULL, at_sweep < 0),
+ * ERANGE (no such unfinished job). */
+int potts_server_inject_fault(potts_server *srv, int64_t ticket, int64_t at_sweep);
 
 /* Waits until every submitted job has finished (timeout_ms < 0: no limit).
  * Errors: ERANGE on time-out, or the code that stopped a failed server. */

@@ -434,14 +434,20 @@ class Server:
         self._npoints = {}
         self._L = {}
 
-    def submit(self, L: int, q: int, seed: int, start: int, betas, sweeps, keep_spins: bool = False) -> int:
+    def submit(self, L: int, q: int, seed: int, start: int, betas, sweeps, keep_spins: bool = False,
+               checkpoint: Optional[str] = None, resume_from: Optional[str] = None) -> int:
+        """Queues a job; `checkpoint`: a file the server rewrites after each
+        completed point; `resume_from`: such a file of the same job, to
+        continue from."""
         b = np.ascontiguousarray(betas, dtype=np.float64)
         n = np.ascontiguousarray(sweeps, dtype=np.int64)
         if b.size != n.size:
             raise ValueError("one sweep count per beta")
         req = PottsRequest(int(L), int(q), int(seed), int(start), int(b.size),
                            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(keep_spins), 0)
+                           n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(keep_spins), 0,
+                           os.fsencode(checkpoint) if checkpoint else None,
+                           os.fsencode(resume_from) if resume_from else None)
         t = ctypes.c_int64()
         check(self._lib.potts_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
         self._npoints[t.value] = int(b.size)
@@ -454,7 +460,14 @@ class Server:
         check(self._lib.potts_server_wait(self._h, buf, int(max_n), int(timeout_ms), ctypes.byref(n)))
         return [int(buf[i]) for i in range(n.value)]
 
+    def inject_fault(self, ticket: int, at_sweep: int) -> None:
+        """Makes the job fail (status EDEVICE) before it runs sweep at_sweep
+        (host-side failure injection for recovery tests)."""
+        check(self._lib.potts_server_inject_fault(self._h, int(ticket), int(at_sweep)))
+
     def collect(self, ticket: int, spins: bool = False) -> dict:
+        """A finished job's results; a job that failed is returned with its
+        negative status (an unknown ticket raises)."""
         info = PottsServed()
         npts = self._npoints.pop(ticket)
         L = self._L.pop(ticket)
@@ -462,7 +475,8 @@ class Server:
         sp = np.zeros(L * L, dtype=np.uint8) if spins else None
         rc = self._lib.potts_server_collect(self._h, int(ticket), ctypes.byref(info), pts,
                                             sp.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if spins else None)
-        check(rc)
+        if rc != 0 and info.ticket != ticket:
+            check(rc)
         return {"ticket": info.ticket, "L": info.L, "q": info.q, "status": info.status, "sweeps": info.sweeps,
                 "t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done,
                 "e_sat": info.e_sat, "nmax": info.nmax,

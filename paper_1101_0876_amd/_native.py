@@ -90,6 +90,8 @@ class PottsRequest(ctypes.Structure):
         ("sweeps", ctypes.POINTER(ctypes.c_int64)),
         ("keep_spins", ctypes.c_int32),
         ("_pad", ctypes.c_int32),
+        ("checkpoint", ctypes.c_char_p),
+        ("resume_from", ctypes.c_char_p),
     ]
 
 
@@ -175,6 +177,7 @@ SIGNATURES = [
     ("potts_server_wait", ctypes.c_int, [_VP, _I64P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     ("potts_server_collect", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.POINTER(PottsServed),
                                             ctypes.POINTER(PottsSummary), _U8P]),
+    ("potts_server_inject_fault", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64]),
     ("potts_server_drain", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("potts_server_now", ctypes.c_double, [_VP]),
     ("potts_server_iterations", ctypes.c_int64, [_VP]),

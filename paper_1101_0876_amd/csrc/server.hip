@@ -16,9 +16,16 @@
 //
 // Results are bit-identical to the same job run alone: random numbers are
 // keyed by (seed, site, sweep), and each job's sweep counter is its own.
+//
+// Recovery: a job may name a checkpoint file, rewritten after each completed
+// point; a later request may resume from it and ends with the bits of an
+// uninterrupted run.  A failure of one job (an injected one, for tests, is
+// raised on the host before the iteration that would run the chosen sweep)
+// ends that job alone.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -29,6 +36,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -62,6 +70,14 @@ struct Job {
   std::vector<int64_t> sweeps;
   std::vector<uint32_t> thr;  // 4 per point
   bool keep_spins = false;
+  std::string ckpt_path;           // checkpoint file after each completed point ("" = none)
+  int64_t fault_at = -1;           // injected failure before sweep fault_at runs (-1 = none)
+  // resumed jobs: the state read from the checkpoint at submit
+  bool resume = false;
+  std::vector<uint8_t> resume_spins;
+  int64_t resume_t = 0;
+  int resume_point = 0;
+  bool ckpt_due = false;           // a point completed in the last iteration
   // device state
   uint8_t *lat = nullptr;
   unsigned long long *ring = nullptr;
@@ -103,6 +119,8 @@ struct potts_server {
   std::string fail_msg;
   int64_t next_ticket = 1;
   int64_t submitted = 0, finished = 0;
+  std::map<int64_t, int64_t> faults;  // ticket -> sweep, for injected failures
+  std::set<int64_t> running;          // tickets of admitted, unfinished jobs
   // owned by the server thread
   std::vector<std::unique_ptr<Job>> active;
   size_t used_bytes = 0;
@@ -165,6 +183,71 @@ void release_job_memory(Job &j) {
   j.ring = nullptr;
 }
 
+// Job checkpoint: magic, (L, q, npoints, point, start, pad) int32, seed u64,
+// t int64, `point` summaries, then the L*L lattice.
+const uint32_t kJobMagic[2] = {0x54544f50u, 0x31424a53u};  // "POTTSJB1"
+
+bool write_job_checkpoint(const Job &j, const std::vector<uint8_t> &lat, std::string &err) {
+  const std::string tmp = j.ckpt_path + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "wb");
+  if (!f) {
+    err = "cannot open " + tmp;
+    return false;
+  }
+  const int32_t hdr[6] = {j.req.L, j.req.q, j.req.npoints, j.point, j.req.start, 0};
+  const uint64_t seed = j.req.seed;
+  const int64_t t = j.t;
+  bool ok = fwrite(kJobMagic, sizeof(kJobMagic), 1, f) == 1 && fwrite(hdr, sizeof(hdr), 1, f) == 1 &&
+            fwrite(&seed, sizeof(seed), 1, f) == 1 && fwrite(&t, sizeof(t), 1, f) == 1 &&
+            (j.point == 0 || fwrite(j.points.data(), sizeof(potts_summary), (size_t)j.point, f) == (size_t)j.point) &&
+            fwrite(lat.data(), 1, lat.size(), f) == lat.size();
+  ok = fclose(f) == 0 && ok;
+  if (!ok || rename(tmp.c_str(), j.ckpt_path.c_str()) != 0) {
+    err = "cannot write checkpoint " + j.ckpt_path;
+    return false;
+  }
+  return true;
+}
+
+// Reads a checkpoint into j's resume fields; 0 or a negative code.
+int read_job_checkpoint(Job &j, const char *path) {
+  FILE *f = fopen(path, "rb");
+  if (!f) return record_error(POTTS_EIO, std::string("cannot open ") + path);
+  uint32_t magic[2];
+  int32_t hdr[6];
+  uint64_t seed;
+  int64_t t;
+  bool ok = fread(magic, sizeof(magic), 1, f) == 1 && fread(hdr, sizeof(hdr), 1, f) == 1 &&
+            fread(&seed, sizeof(seed), 1, f) == 1 && fread(&t, sizeof(t), 1, f) == 1;
+  if (!ok || magic[0] != kJobMagic[0] || magic[1] != kJobMagic[1]) {
+    fclose(f);
+    return record_error(POTTS_EIO, std::string("not a job checkpoint: ") + path);
+  }
+  if (hdr[0] != j.req.L || hdr[1] != j.req.q || hdr[2] != j.req.npoints || hdr[4] != j.req.start ||
+      seed != j.req.seed || hdr[3] < 1 || hdr[3] >= j.req.npoints || t < 0) {
+    fclose(f);
+    return record_error(POTTS_EINVAL, std::string("the checkpoint belongs to another job: ") + path);
+  }
+  int64_t expect = 0;  // the sweeps of the points before the resume point
+  for (int k = 0; k < hdr[3]; ++k) expect += j.sweeps[(size_t)k];
+  if (t != expect) {
+    fclose(f);
+    return record_error(POTTS_EINVAL, std::string("the checkpoint's sweep count does not fit the schedule: ") + path);
+  }
+  j.points.assign((size_t)j.req.npoints, potts_summary{});
+  j.resume_spins.resize((size_t)j.req.L * j.req.L);
+  ok = fread(j.points.data(), sizeof(potts_summary), (size_t)hdr[3], f) == (size_t)hdr[3] &&
+       fread(j.resume_spins.data(), 1, j.resume_spins.size(), f) == j.resume_spins.size();
+  fclose(f);
+  if (!ok) return record_error(POTTS_EIO, std::string("truncated job checkpoint: ") + path);
+  for (uint8_t v : j.resume_spins)
+    if (v >= j.req.q) return record_error(POTTS_EIO, std::string("spin value >= q in ") + path);
+  j.resume = true;
+  j.resume_t = t;
+  j.resume_point = hdr[3];
+  return POTTS_OK;
+}
+
 // Allocates and initializes an admitted job on the server stream.
 bool admit(potts_server *s, Job &j, std::string &err) {
   hipError_t e = hipMallocAsync((void **)&j.lat, ((size_t)j.req.L * j.req.L + 255) / 256 * 256, s->stream);
@@ -184,7 +267,12 @@ bool admit(potts_server *s, Job &j, std::string &err) {
   p.k0 = (uint32_t)j.req.seed;
   p.k1 = (uint32_t)(j.req.seed >> 32);
   p.random = j.req.start == POTTS_RANDOM;
-  e = potts::launch_init(p, s->stream);
+  if (j.resume) {
+    e = hipMemcpyAsync(j.lat, j.resume_spins.data(), j.resume_spins.size(), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the host copy goes away next
+  } else {
+    e = potts::launch_init(p, s->stream);
+  }
   if (e == hipSuccess) e = potts::launch_fill_u64(j.ring, (uint64_t)j.cap * (j.req.q + 1), 0ull, s->stream);
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s->stream);
@@ -194,9 +282,11 @@ bool admit(potts_server *s, Job &j, std::string &err) {
   }
   j.resident = potts::resident_fits((uint32_t)j.req.L, (uint32_t)j.req.q);
   j.rows = j.resident ? 0 : potts::auto_strip_rows((uint32_t)j.req.L, (uint32_t)j.req.L, 64 * 256);
-  j.point = 0;
-  j.left = j.sweeps[0];
-  j.t = 0;
+  j.point = j.resume ? j.resume_point : 0;
+  j.left = j.sweeps[(size_t)j.point];
+  j.t = j.resume ? j.resume_t : 0;
+  j.resume_spins.clear();
+  j.resume_spins.shrink_to_fit();
   j.info.t_admit = seconds_since(s);
   return true;
 }
@@ -375,8 +465,71 @@ int iterate(potts_server *s, std::string &err) {
     while (j.left == 0 && j.point + 1 < j.req.npoints) {
       ++j.point;
       j.left = j.sweeps[(size_t)j.point];
-      // a zero-sweep point still gets a summary of nothing
+      j.ckpt_due = true;
     }
+  }
+  return POTTS_OK;
+}
+
+// Ends one active job with an error code: its memory is released and it is
+// reported finished; the server and the other jobs go on.
+void fail_job(potts_server *s, std::unique_ptr<Job> jp, int code) {
+  Job &j = *jp;
+  (void)hipStreamSynchronize(s->stream);
+  release_job_memory(j);
+  s->used_bytes -= j.bytes;
+  j.info.status = code;
+  j.info.sweeps = j.t;
+  j.info.t_done = seconds_since(s);
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->running.erase(j.ticket);
+  s->done_order.push_back(j.ticket);
+  s->done[j.ticket] = std::move(jp);
+  ++s->finished;
+  s->cv_done.notify_all();
+}
+
+// Injected failures: a job whose next iteration would run its marked sweep
+// fails now, before any of that iteration's work is queued.
+void apply_faults(potts_server *s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto &jp : s->active) {
+      auto it = s->faults.find(jp->ticket);
+      if (it != s->faults.end()) {
+        jp->fault_at = it->second;
+        s->faults.erase(it);
+      }
+    }
+  }
+  std::vector<std::unique_ptr<Job>> keep;
+  for (auto &jp : s->active) {
+    Job &j = *jp;
+    const int64_t step = std::min<int64_t>(s->cfg.quantum, j.left);
+    if (j.fault_at >= 0 && j.fault_at < j.t + step)
+      fail_job(s, std::move(jp), POTTS_EDEVICE);
+    else
+      keep.push_back(std::move(jp));
+  }
+  s->active.swap(keep);
+}
+
+// Writes the checkpoints of jobs that completed a point (not their last) in
+// the last iteration.
+int write_checkpoints(potts_server *s, std::string &err) {
+  for (auto &jp : s->active) {
+    Job &j = *jp;
+    if (!j.ckpt_due) continue;
+    j.ckpt_due = false;
+    if (j.ckpt_path.empty() || j.left == 0) continue;
+    std::vector<uint8_t> lat((size_t)j.req.L * j.req.L);
+    hipError_t e = hipMemcpyAsync(lat.data(), j.lat, lat.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+      err = std::string("checkpoint copy failed: ") + herr(e);
+      return POTTS_EDEVICE;
+    }
+    if (!write_job_checkpoint(j, lat, err)) return POTTS_EIO;
   }
   return POTTS_OK;
 }
@@ -418,6 +571,7 @@ int retire(potts_server *s, std::string &err) {
     j.info.t_done = seconds_since(s);
     j.info.status = POTTS_OK;
     std::lock_guard<std::mutex> lk(s->mu);
+    s->running.erase(j.ticket);
     s->done_order.push_back(j.ticket);
     s->done[j.ticket] = std::move(jp);
     ++s->finished;
@@ -442,6 +596,7 @@ void fail_all(potts_server *s, int code, const std::string &msg) {
   };
   for (auto &jp : s->active) finish(std::move(jp));
   s->active.clear();
+  s->running.clear();
   while (!s->queue.empty()) {
     finish(std::move(s->queue.front()));
     s->queue.pop_front();
@@ -473,13 +628,17 @@ void server_loop(potts_server *s) {
           return;
         }
         s->used_bytes += jp->bytes;
+        const int64_t ticket = jp->ticket;
         s->active.push_back(std::move(jp));
         lk.lock();
+        s->running.insert(ticket);
       }
     }
+    apply_faults(s);
     if (s->active.empty()) continue;
     std::string err;
     int rc = iterate(s, err);
+    if (rc == POTTS_OK) rc = write_checkpoints(s, err);
     if (rc == POTTS_OK) rc = retire(s, err);
     if (rc != POTTS_OK) {
       fail_all(s, rc, err);
@@ -549,6 +708,13 @@ int potts_server_submit(potts_server *s, const potts_request *req, int64_t *tick
     most = std::max<int64_t>(most, j->sweeps[k]);
   }
   j->points.assign(req->npoints, potts_summary{});
+  if (req->checkpoint) j->ckpt_path = req->checkpoint;
+  j->req.checkpoint = nullptr;
+  j->req.resume_from = nullptr;
+  if (req->resume_from) {
+    int rc = read_job_checkpoint(*j, req->resume_from);
+    if (rc) return rc;
+  }
   j->cap = pow2_at_least(most + 1);
   j->bytes = job_bytes(*j);
   j->info.L = req->L;
@@ -602,6 +768,19 @@ int potts_server_collect(potts_server *s, int64_t ticket, potts_served *info, po
   if (points) memcpy(points, j->points.data(), j->points.size() * sizeof(potts_summary));
   if (spins && !j->spins.empty()) memcpy(spins, j->spins.data(), j->spins.size());
   return j->info.status;
+}
+
+int potts_server_inject_fault(potts_server *s, int64_t ticket, int64_t at_sweep) {
+  if (!s || at_sweep < 0) return record_error(POTTS_EINVAL, "need a server and at_sweep >= 0");
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (auto &jp : s->queue)
+    if (jp->ticket == ticket) {
+      jp->fault_at = at_sweep;
+      return POTTS_OK;
+    }
+  if (!s->running.count(ticket)) return record_error(POTTS_ERANGE, "no unfinished job with this ticket");
+  s->faults[ticket] = at_sweep;  // an active job: picked up by the server thread
+  return POTTS_OK;
 }
 
 int potts_server_drain(potts_server *s, int32_t timeout_ms) {

@@ -121,3 +121,38 @@ def test_bad_requests(potts):
     with potts.Server(hbm_budget=1 << 12) as srv:
         with pytest.raises(potts.PottsError):
             srv.submit(1024, 3, 1, 1, [1.0], [5])
+
+
+@pytest.mark.parametrize("L,q,fault_at", [(512, 7, 30 + 25 + 13), (128, 5, 30 + 25 + 40 + 3)])
+def test_served_job_resumes_after_a_failure(potts, oracle_lib, tmp_path, L, q, fault_at):
+    """Recovery: a served job that writes a checkpoint after each point fails
+    at sweep fault_at (an injected host-side failure, mid-point) while other
+    jobs run; they finish unaffected, and the job resubmitted from its last
+    checkpoint ends with the bits of the oracle's uninterrupted run.  L = 512
+    runs in the strip kernel, L = 128 in the LDS-resident one."""
+    job = dict(L=L, q=q, seed=41, start=1, betas=_ramp(q, 5, 1), sweeps=[30, 25, 40, 20, 35])
+    ck = str(tmp_path / "job.ckpt")
+    others = JOBS[:3]
+
+    def submit(srv, j, **kw):
+        return srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"], keep_spins=True, **kw)
+
+    with potts.Server(quantum=8, max_slots=16) as srv:
+        bad = submit(srv, job, checkpoint=ck)
+        srv.inject_fault(bad, fault_at)
+        t_others = [submit(srv, j) for j in others]
+        srv.drain(120000)
+        failed = srv.collect(bad, spins=True)
+        assert failed["status"] == -3  # POTTS_EDEVICE
+        assert fault_at - 8 < failed["sweeps"] <= fault_at
+        for t, j in zip(t_others, others):
+            _check(srv.collect(t, spins=True), *_oracle(oracle_lib, j))
+        with pytest.raises(potts.PottsError):
+            srv.inject_fault(bad, 1)  # finished jobs cannot fail again
+        resumed = submit(srv, job, resume_from=ck)
+        srv.drain(120000)
+        got = srv.collect(resumed, spins=True)
+        with pytest.raises(potts.PottsError):  # a checkpoint of another job
+            srv.submit(L, q, 42, 1, job["betas"], job["sweeps"], resume_from=ck)
+    assert got["sweeps"] == sum(job["sweeps"])
+    _check(got, *_oracle(oracle_lib, job))
