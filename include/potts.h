@@ -302,10 +302,14 @@ typedef struct {
 
 typedef struct {
     int32_t graph;       /* 1: capture the run in a hipGraph and launch it      */
-    int32_t tune;        /* 1: time strip heights on the first sweeps, keep the best */
+    int32_t tune;        /* 1: time launch shapes on the first sweeps, keep the best */
     int32_t window;      /* summary window in sweeps, 0 = every sweep of the job */
     int32_t strip_rows;  /* fixed strip height (even divisor of L), 0 = automatic */
     void *hip_stream;    /* hipStream_t, NULL = the batch's own stream          */
+    const char *tune_cache; /* NULL, or a JSON file of launch shapes (read at
+                               create, used with or without `tune`, updated by
+                               the tuner; entries measured on other kernel
+                               sources are ignored) */
 } potts_batch_opts;
 
 typedef struct potts_batch potts_batch;
@@ -329,9 +333,20 @@ int potts_batch_records(potts_batch *b, int32_t job, int64_t t0, int64_t n, int6
 int potts_batch_spins(potts_batch *b, int32_t job, uint8_t *host_out);
 
 /* Device time of the last run in ms (HIP events on the batch's stream), and
- * the strip heights the tuner chose ("L=<L>:rows=<r> ..."). */
+ * the launch shapes the tuner chose or read from the cache ("L=<L>:rows=<r>
+ * ... <kernel>/q<class>:block=<lanes>,waves/SIMD=<w|auto> ..."). */
 double potts_batch_elapsed_ms(const potts_batch *b);
 const char *potts_batch_tuning(const potts_batch *b);
+
+/* The digest of the tuned kernels' sources this library was built from: the
+ * key under which tuning caches (potts_batch_opts.tune_cache,
+ * potts_server_cfg.tune_cache) keep launch shapes.  A cache file is JSON:
+ *   {"kernel_hash": "<digest>",
+ *    "rows":   {"<strip|packed>/<q class>/<L>": <strip height>, ...},
+ *    "shapes": {"<strip|packed>/<q class>": [<lanes 256|128>, <waves/SIMD 0|8>], ...}}
+ * q class 0..3 = q <= 16, <= 64, <= 128, <= 256; shapes other than [256, 0]
+ * exist for class 0. */
+const char *potts_kernel_digest(void);
 
 /* Releases the batch (synchronizes first).  NULL is a no-op. */
 void potts_batch_free(potts_batch *b);
@@ -350,6 +365,12 @@ typedef struct {
     int32_t max_slots;   /* jobs on the device at once (<= 0: 256)              */
     int32_t quantum;     /* sweeps per job per iteration (<= 0: 32)             */
     void *hip_stream;    /* hipStream_t, NULL = the server's own stream         */
+    int32_t tune;        /* 1: the first job of a lattice size and q class that
+                            the cache does not know has its launch shape timed
+                            first, on a throwaway lattice of that size        */
+    int32_t _pad;
+    const char *tune_cache; /* NULL, or a JSON file of launch shapes (as
+                               potts_batch_opts.tune_cache; updated by `tune`) */
 } potts_server_cfg;
 
 /* A job: a beta schedule (Sec. 3 protocol), point k run for sweeps[k] sweeps
@@ -418,6 +439,11 @@ int potts_server_drain(potts_server *srv, int32_t timeout_ms);
 /* The server's clock (seconds since start) and the number of iterations run. */
 double potts_server_now(const potts_server *srv);
 int64_t potts_server_iterations(const potts_server *srv);
+
+/* The launch shapes in use: those timed by this server and those read from
+ * its cache, as text (as potts_batch_tuning), into out[0..cap) with a
+ * terminating NUL (truncated to fit).  Errors: EINVAL. */
+int potts_server_tuning(potts_server *srv, char *out, int32_t cap);
 
 /* Finishes every queued and running job, stops the thread and releases the
  * server; returns 0 or the code that failed it.  NULL is a no-op. */

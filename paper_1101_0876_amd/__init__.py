@@ -363,15 +363,16 @@ class Batch:
     gives alone."""
 
     def __init__(self, jobs, graph: bool = True, tune: bool = True, window: int = 0, strip_rows: int = 0,
-                 stream=None):
+                 stream=None, tune_cache: Optional[str] = None):
         self._lib = load()
         arr = (PottsJob * len(jobs))()
         for a, j in zip(arr, jobs):
             a.L, a.q, a.seed, a.start = int(j["L"]), int(j["q"]), int(j["seed"]), int(j["start"])
             a.beta, a.nsweeps = float(j["beta"]), int(j["nsweeps"])
         self.jobs = [dict(j) for j in jobs]
+        self._cache = os.fsencode(tune_cache) if tune_cache else None  # kept alive for the library
         opts = PottsBatchOpts(int(graph), int(tune), int(window), int(strip_rows),
-                              ctypes.c_void_p(stream.cuda_stream) if stream is not None else None)
+                              ctypes.c_void_p(stream.cuda_stream) if stream is not None else None, self._cache)
         self._h = ctypes.c_void_p()
         check(self._lib.potts_batch_create(arr, len(jobs), ctypes.byref(opts), ctypes.byref(self._h)))
 
@@ -425,10 +426,13 @@ class Server:
     beta schedule each) while earlier ones run; results are bit-identical to
     the same job run alone."""
 
-    def __init__(self, hbm_budget: int = 0, max_slots: int = 0, quantum: int = 0, stream=None):
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 0, quantum: int = 0, stream=None,
+                 tune: bool = False, tune_cache: Optional[str] = None):
         self._lib = load()
+        self._cache = os.fsencode(tune_cache) if tune_cache else None  # kept alive for the library
         cfg = PottsServerCfg(int(hbm_budget), int(max_slots), int(quantum),
-                             ctypes.c_void_p(stream.cuda_stream) if stream is not None else None)
+                             ctypes.c_void_p(stream.cuda_stream) if stream is not None else None,
+                             int(tune), 0, self._cache)
         self._h = ctypes.c_void_p()
         check(self._lib.potts_server_start(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._npoints = {}
@@ -491,6 +495,12 @@ class Server:
 
     def iterations(self) -> int:
         return int(self._lib.potts_server_iterations(self._h))
+
+    def tuning(self) -> str:
+        """The launch shapes in use (timed by this server or read from its cache)."""
+        buf = ctypes.create_string_buffer(4096)
+        check(self._lib.potts_server_tuning(self._h, buf, len(buf)))
+        return buf.value.decode()
 
     def stop(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

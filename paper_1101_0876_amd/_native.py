@@ -67,6 +67,7 @@ class PottsBatchOpts(ctypes.Structure):
         ("window", ctypes.c_int32),
         ("strip_rows", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
+        ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -76,6 +77,9 @@ class PottsServerCfg(ctypes.Structure):
         ("max_slots", ctypes.c_int32),
         ("quantum", ctypes.c_int32),
         ("hip_stream", ctypes.c_void_p),
+        ("tune", ctypes.c_int32),
+        ("_pad", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -172,6 +176,7 @@ SIGNATURES = [
     ("potts_batch_elapsed_ms", ctypes.c_double, [_VP]),
     ("potts_batch_tuning", ctypes.c_char_p, [_VP]),
     ("potts_batch_free", None, [_VP]),
+    ("potts_kernel_digest", ctypes.c_char_p, []),
     ("potts_server_start", ctypes.c_int, [ctypes.POINTER(PottsServerCfg), ctypes.POINTER(_VP)]),
     ("potts_server_submit", ctypes.c_int, [_VP, ctypes.POINTER(PottsRequest), ctypes.POINTER(ctypes.c_int64)]),
     ("potts_server_wait", ctypes.c_int, [_VP, _I64P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
@@ -181,6 +186,7 @@ SIGNATURES = [
     ("potts_server_drain", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("potts_server_now", ctypes.c_double, [_VP]),
     ("potts_server_iterations", ctypes.c_int64, [_VP]),
+    ("potts_server_tuning", ctypes.c_int, [_VP, ctypes.c_char_p, ctypes.c_int32]),
     ("potts_server_stop", ctypes.c_int, [_VP]),
     ("potts_free", None, [_VP]),
     ("potts_nnn_init", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int,

@@ -10,9 +10,12 @@
 // random numbers are keyed by (seed, site, sweep), every job gives exactly the
 // bits it gives alone.
 //
-// Launch shape: an in-run autotuner times the candidate strip heights per
-// lattice size on the first sweeps of the run (these are real sweeps: the
-// shape does not change the results) and keeps the fastest.  The remaining
+// Launch shape: an in-run autotuner times, on the first sweeps of the run
+// (real sweeps: the shape does not change the results), first the strip
+// heights of each lattice size, then the workgroup shape of each kernel group
+// (lanes per workgroup, and the occupancy asked of the compiler), and keeps
+// the fastest; the choices persist in a JSON cache keyed by the kernels'
+// source digest, so later runs of the same sizes skip the timing.  The remaining
 // sweeps are captured once into a hipGraph: the resident launches and the
 // strip chain as two branches that the GPU overlaps, then replayed.  No
 // memset is recorded in the graph; record slots are cleared by the kernels.
@@ -29,6 +32,7 @@
 
 #include "../../include/potts.h"
 #include "kernels.hpp"
+#include "tune_cache.hpp"
 
 namespace potts {
 int record_error(int code, const std::string &msg);  // capi.hip
@@ -95,7 +99,9 @@ struct potts_batch {
   std::vector<uint32_t> thr;                // 4 per job
   std::vector<uint32_t> rows;               // strip rows per job (0: resident)
   std::vector<StripGroup> strip_groups;
+  std::vector<potts::TileShape> shape;      // per strip group
   std::vector<ResidentGroup> res_groups;
+  potts::TuneCache cache;
   // device tables
   potts::StripParams *d_strip = nullptr;    // per strip group: jobs' descriptors, contiguous
   potts::StripTile *d_tiles = nullptr;
@@ -142,8 +148,9 @@ std::vector<uint32_t> row_candidates(uint32_t L) {
 
 // Descriptors and tiles of one strip group for the jobs' current rows; the
 // sweep index of launch s is done[j] + s for every job (t0 = done[j]).
-void build_strip_tables(const potts_batch *b, const StripGroup &g, std::vector<potts::StripParams> &desc,
-                        std::vector<potts::StripTile> &tiles, const std::vector<int> *only = nullptr) {
+void build_strip_tables(const potts_batch *b, const StripGroup &g, const potts::TileShape &shape,
+                        std::vector<potts::StripParams> &desc, std::vector<potts::StripTile> &tiles,
+                        const std::vector<int> *only = nullptr) {
   desc.clear();
   tiles.clear();
   for (size_t k = 0; k < g.jobs.size(); ++k) {
@@ -164,8 +171,8 @@ void build_strip_tables(const potts_batch *b, const StripGroup &g, std::vector<p
     p.cap = (uint64_t)b->ring[j];
     desc.push_back(p);
     if (only && std::find(only->begin(), only->end(), j) == only->end()) continue;
-    for (uint32_t first = 0; first < p.nitems; first += 256) {
-      potts::StripTile t{(uint32_t)k, first, std::min<uint32_t>(256, p.nitems - first), first == 0 ? 1u : 0u};
+    for (uint32_t first = 0; first < p.nitems; first += shape.block) {
+      potts::StripTile t{(uint32_t)k, first, std::min<uint32_t>(shape.block, p.nitems - first), first == 0 ? 1u : 0u};
       tiles.push_back(t);
     }
   }
@@ -179,36 +186,37 @@ int upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
 }
 
 // One launch pair (colour 0, colour 1) of a strip group for sweep s.
-int launch_strip_sweep(const StripGroup &g, const potts::StripParams *d_desc, const potts::StripTile *d_tiles,
-                       size_t ntiles, uint32_t s, hipStream_t st) {
+int launch_strip_sweep(const StripGroup &g, const potts::TileShape &shape, const potts::StripParams *d_desc,
+                       const potts::StripTile *d_tiles, size_t ntiles, uint32_t s, hipStream_t st) {
   potts::StripLaunch l{};
   l.jobs = d_desc;
   l.tiles = d_tiles;
   l.sweep = s;
+  const uint32_t mq = class_max_q(g.qc);
   if (g.packed) {
-    HIP_TRY(potts::launch_packed(l, 0, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
-    HIP_TRY(potts::launch_packed(l, 1, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+    HIP_TRY(potts::launch_packed_tiled(l, 0, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_packed_tiled(l, 1, (unsigned)ntiles, shape, mq, g.wide, st));
   } else {
-    HIP_TRY(potts::launch_strip(l, 0, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
-    HIP_TRY(potts::launch_strip(l, 1, (unsigned)ntiles, class_max_q(g.qc), g.wide, st));
+    HIP_TRY(potts::launch_strip_tiled(l, 0, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_strip_tiled(l, 1, (unsigned)ntiles, shape, mq, g.wide, st));
   }
   return POTTS_OK;
 }
 
 // Times `reps` sweeps of the given jobs of a strip group with their current
-// rows (real sweeps), advancing done[] for them.
-int timed_strip_sweeps(potts_batch *b, const StripGroup &g, const std::vector<int> &jobs, int reps,
-                       float *ms) {
+// rows and the given shape (real sweeps), advancing done[] for them.
+int timed_strip_sweeps(potts_batch *b, const StripGroup &g, const potts::TileShape &shape,
+                       const std::vector<int> &jobs, int reps, float *ms) {
   std::vector<potts::StripParams> desc;
   std::vector<potts::StripTile> tiles;
-  build_strip_tables(b, g, desc, tiles, &jobs);
+  build_strip_tables(b, g, shape, desc, tiles, &jobs);
   int rc = upload(b->d_strip, desc.data(), desc.size() * sizeof(desc[0]), b->stream);
   if (rc) return rc;
   rc = upload(b->d_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]), b->stream);
   if (rc) return rc;
   HIP_TRY(hipEventRecord(b->ev_t0, b->stream));
   for (int s = 0; s < reps; ++s) {
-    rc = launch_strip_sweep(g, b->d_strip, b->d_tiles, tiles.size(), (uint32_t)s, b->stream);
+    rc = launch_strip_sweep(g, shape, b->d_strip, b->d_tiles, tiles.size(), (uint32_t)s, b->stream);
     if (rc) return rc;
   }
   HIP_TRY(hipEventRecord(b->ev_t1, b->stream));
@@ -218,25 +226,50 @@ int timed_strip_sweeps(potts_batch *b, const StripGroup &g, const std::vector<in
   return POTTS_OK;
 }
 
-// In-run tuning of the strip heights, per (group, L): each candidate runs one
-// real sweep of the jobs of that size; the fastest is kept.
-int autotune(potts_batch *b) {
-  for (StripGroup &g : b->strip_groups) {
+int64_t sweeps_left(const potts_batch *b, const std::vector<int> &jobs) {
+  int64_t left = INT64_MAX;
+  for (int j : jobs) left = std::min<int64_t>(left, b->target[j] - b->done[j]);
+  return left;
+}
+
+std::string shape_text(const potts::TileShape &t) {
+  return "block=" + std::to_string(t.block) + ",waves/SIMD=" + (t.wpe ? std::to_string(t.wpe) : std::string("auto"));
+}
+
+// In-run tuning, on real sweeps of the run (kReps timed sweeps per candidate,
+// after one untimed warm-up sweep of each lattice size):
+//   1. per (group, L): the strip height, with the default shape;
+//   2. per group of q <= 16: the workgroup shape (lanes 256 or 128; the
+//      compiler's occupancy or at least 8 waves per SIMD) at the chosen heights.
+// Choices found in the cache are taken without timing; new ones are added.
+constexpr int kReps = 2;
+
+int autotune(potts_batch *b, bool time_new) {
+  for (size_t gi = 0; gi < b->strip_groups.size(); ++gi) {
+    StripGroup &g = b->strip_groups[gi];
     std::map<int, std::vector<int>> by_L;
     for (int j : g.jobs) by_L[b->jobs[j].L].push_back(j);
+    const potts::TileShape base;
     for (auto &kv : by_L) {
       const uint32_t L = (uint32_t)kv.first;
       std::vector<int> &js = kv.second;
-      int64_t left = INT64_MAX;
-      for (int j : js) left = std::min<int64_t>(left, b->target[j] - b->done[j]);
+      const std::string key = potts::TuneCache::rows_key(g.packed, g.qc, L);
+      auto hit = b->cache.rows.find(key);
+      if (hit != b->cache.rows.end() && L % hit->second == 0) {
+        for (int j : js) b->rows[j] = hit->second;
+        b->tuned += "L=" + std::to_string(L) + ":rows=" + std::to_string(hit->second) + "(cached) ";
+        continue;
+      }
       const std::vector<uint32_t> cands = row_candidates(L);
-      if (left < (int64_t)cands.size() + 1) continue;  // too short to be worth it
-      float best_ms = 0.0f;
+      if (!time_new || sweeps_left(b, js) < 1 + kReps * (int64_t)cands.size() + 1) continue;  // too short
+      float ms = 0.0f, best_ms = 0.0f;
       uint32_t best = cands[0];
+      for (int j : js) b->rows[j] = best;
+      int rc = timed_strip_sweeps(b, g, base, js, 1, &ms);  // warm-up
+      if (rc) return rc;
       for (uint32_t r : cands) {
         for (int j : js) b->rows[j] = r;
-        float ms = 0.0f;
-        int rc = timed_strip_sweeps(b, g, js, 1, &ms);
+        rc = timed_strip_sweeps(b, g, base, js, kReps, &ms);
         if (rc) return rc;
         if (r == cands[0] || ms < best_ms) {
           best_ms = ms;
@@ -244,9 +277,39 @@ int autotune(potts_batch *b) {
         }
       }
       for (int j : js) b->rows[j] = best;
+      b->cache.rows[key] = best;
+      b->cache.dirty = true;
       b->tuned += "L=" + std::to_string(L) + ":rows=" + std::to_string(best) + " ";
     }
+    // the workgroup shape of the whole group
+    const std::string skey = potts::TuneCache::shape_key(g.packed, g.qc);
+    auto hit = b->cache.shapes.find(skey);
+    if (hit != b->cache.shapes.end() && potts::shape_ok(hit->second, class_max_q(g.qc))) {
+      b->shape[gi] = hit->second;
+      b->tuned += std::string(g.packed ? "packed" : "strip") + "/q" + std::to_string(class_max_q(g.qc)) + ":" +
+                  shape_text(hit->second) + "(cached) ";
+      continue;
+    }
+    if (!time_new || g.qc != 0) continue;  // one shape for q > 16
+    const potts::TileShape cands[4] = {{256, 0}, {128, 0}, {256, 8}, {128, 8}};
+    if (sweeps_left(b, g.jobs) < kReps * 4 + 1) continue;
+    float best_ms = 0.0f;
+    potts::TileShape best = cands[0];
+    for (int c = 0; c < 4; ++c) {
+      float ms = 0.0f;
+      int rc = timed_strip_sweeps(b, g, cands[c], g.jobs, kReps, &ms);
+      if (rc) return rc;
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = cands[c];
+      }
+    }
+    b->shape[gi] = best;
+    b->cache.shapes[skey] = best;
+    b->cache.dirty = true;
+    b->tuned += std::string(g.packed ? "packed" : "strip") + "/q16:" + shape_text(best) + " ";
   }
+  if (!b->cache.save()) return record_error(POTTS_EIO, "cannot write the tuning cache " + b->cache.path);
   return POTTS_OK;
 }
 
@@ -263,7 +326,7 @@ int queue_rest(potts_batch *b) {
   for (const StripGroup &g : b->strip_groups) {
     std::vector<potts::StripParams> desc;
     std::vector<potts::StripTile> tiles;
-    build_strip_tables(b, g, desc, tiles);
+    build_strip_tables(b, g, b->shape[b->strip_desc_off.size()], desc, tiles);
     b->strip_desc_off.push_back(all_desc.size());
     b->tile_off.push_back(all_tiles.size());
     b->tile_count.push_back(tiles.size());
@@ -333,7 +396,7 @@ int queue_rest(potts_batch *b) {
   for (int64_t s = 0; s < strip_sweeps && !err; ++s) {
     for (size_t gi = 0; gi < b->strip_groups.size() && !err; ++gi) {
       if (!b->tile_count[gi]) continue;
-      err = launch_strip_sweep(b->strip_groups[gi], b->d_strip + b->strip_desc_off[gi],
+      err = launch_strip_sweep(b->strip_groups[gi], b->shape[gi], b->d_strip + b->strip_desc_off[gi],
                                b->d_tiles + b->tile_off[gi], b->tile_count[gi], (uint32_t)s, st);
     }
   }
@@ -481,9 +544,11 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
                        ? (uint32_t)b->opts.strip_rows
                        : potts::auto_strip_rows((uint32_t)j.L, (uint32_t)j.L, 64 * 256);
       ++nstrip_desc;
-      ntiles_max += ((size_t)j.L / 2) * ((size_t)j.L / 16) / 256 + 1;  // rows = 2 is the most tiles
+      ntiles_max += ((size_t)j.L / 2) * ((size_t)j.L / 16) / 128 + 1;  // rows = 2, 128 lanes: the most tiles
     }
   }
+  b->shape.assign(b->strip_groups.size(), potts::TileShape{});
+  b->cache.load(b->opts.tune_cache);
   // resident descriptors: one per job per chunk of the longest run
   size_t nres = 0;
   for (const ResidentGroup &g : b->res_groups) {
@@ -529,7 +594,7 @@ int potts_batch_run(potts_batch *b) {
   HIP_TRY(hipEventCreate(&mark));
   HIP_TRY(hipEventRecord(mark, b->stream));
   int rc = convert_packed(b, true);
-  if (!rc && b->opts.tune) rc = autotune(b);
+  if (!rc) rc = autotune(b, b->opts.tune != 0);
   if (!rc) rc = queue_rest(b);
   if (!rc) rc = convert_packed(b, false);
   if (!rc) {

@@ -64,9 +64,23 @@ __host__ __device__ inline uint32_t stripe_words(uint32_t q) { return (q + 1 + 1
 struct StripTile {
   uint32_t job;
   uint32_t first;  // first item of the range
-  uint32_t count;  // items in the range (<= 256: one per lane)
+  uint32_t count;  // items in the range (at most one per lane of the workgroup)
   uint32_t lead;   // 1 for one tile per job: it clears the next record slot
 };
+
+// Launch shape of a tiled launch (batches, the serving loop): lanes, and so
+// items, per workgroup tile (256 or 128), and the occupancy asked of the
+// compiler (wpe 0: its own choice; 8: at least 8 waves per SIMD, at most 64
+// VGPRs).  Shapes other than (256, 0) exist for q <= 16.
+struct TileShape {
+  uint32_t block = 256;
+  uint32_t wpe = 0;
+};
+
+inline bool shape_ok(const TileShape &s, uint32_t max_q) {
+  if (s.block == 256 && s.wpe == 0) return true;
+  return max_q <= 16 && (s.block == 128 || s.block == 256) && (s.wpe == 0 || s.wpe == 8);
+}
 
 struct StripLaunch {
   const StripParams *jobs;  // null: run `single` over a grid-stride loop
@@ -160,6 +174,12 @@ hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_
 hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
                          hipStream_t stream);
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream);
+// tiled launches (l.tiles set, tiles of shape.block items) in a tuner shape;
+// hipErrorInvalidValue for a shape that does not exist for max_q
+hipError_t launch_strip_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,
+                              uint32_t max_q, bool wide, hipStream_t stream);
+hipError_t launch_packed_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,
+                               uint32_t max_q, bool wide, hipStream_t stream);
 hipError_t launch_unpack(const uint8_t *packed, uint8_t *row_major, uint32_t L, hipStream_t stream);
 // folds stripe set t & 1 of p into ring slot t and clears it
 hipError_t launch_fold_stripes(const StripParams &p, uint64_t t, hipStream_t stream);

@@ -32,7 +32,6 @@ namespace potts {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
 
 using namespace row;
 
@@ -89,8 +88,9 @@ __device__ __forceinline__ void packed_row(const StripParams &p, const PhiloxHea
 // TILED: workgroup -> (job, item range) from the tile table (batched
 // lattices, as in the strip kernel); otherwise the single descriptor with a
 // grid-stride loop.
-template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
-__global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__device__ __forceinline__ void packed_body(const StripLaunch &launch) {
+  constexpr int kWaves = BLOCK / 64;
   __shared__ __align__(16) uint32_t table_words[512];
   constexpr uint32_t kHistWords = PRIV ? 64u * (CMP == 0 ? 16u : kPrivateHistMaxQ) : 256u;
   __shared__ __align__(16) uint32_t hist[kHistWords];
@@ -99,9 +99,9 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   const uint32_t bid = COLOUR == 1 ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
   const StripTile tile = TILED ? launch.tiles[bid] : StripTile{0, 0, 0, 0};
   const StripParams &p = TILED ? launch.jobs[tile.job] : launch.single;
-  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * kBlock + threadIdx.x;
+  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * BLOCK + threadIdx.x;
   const uint32_t end = TILED ? tile.first + tile.count : p.nitems;
-  const uint32_t stride = TILED ? (uint32_t)kBlock : gridDim.x * kBlock;
+  const uint32_t stride = TILED ? (uint32_t)BLOCK : gridDim.x * BLOCK;
   const bool lead = TILED ? tile.lead != 0 : bid == 0;
   if (launch.sweep >= p.nsweeps) return;
   const uint64_t t = p.t0 + launch.sweep;
@@ -113,17 +113,17 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
 
   fill_accept_table<WIDE>(table, p.thr);
   const uint32_t nh = PRIV ? 64 * q : q;
-  for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < nh; i += BLOCK) hist[i] = 0;
   // a workgroup's bond count reaches 2N / grid, beyond 32 bits on the largest
   // lattices with few workgroups: counted in 64 bits
   __shared__ unsigned long long esum;
   if (threadIdx.x == 0) esum = 0;
   if (p.stripes) {
     __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
-    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<kBlock>(p, t - 1, fold_acc);
+    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<BLOCK>(p, t - 1, fold_acc);
   } else if (COLOUR == 1 && lead) {
     unsigned long long *rec_next = p.ring + ((t + 1) & (p.cap - 1)) * (uint64_t)(q + 1);
-    for (uint32_t i = threadIdx.x; i < q + 1; i += kBlock) rec_next[i] = 0;
+    for (uint32_t i = threadIdx.x; i < q + 1; i += BLOCK) rec_next[i] = 0;
   }
   __syncthreads();
 
@@ -182,11 +182,25 @@ __global__ __launch_bounds__(kBlock) void packed_kernel(StripLaunch launch) {
   }
   unsigned long long *dst =
       p.stripes ? p.stripes + ((t & 1) * p.nstripes + (bid & (p.nstripes - 1))) * (uint64_t)stripe_words(q) : rec;
-  for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
+  for (uint32_t v = threadIdx.x; v < q; v += BLOCK) {
     const uint32_t s = PRIV ? partial[v] : hist[v];
     if (s) atomicAdd(&dst[1 + v], (unsigned long long)s);
   }
   if (COLOUR == 1 && threadIdx.x == 0 && esum) atomicAdd(&dst[0], esum);
+}
+
+// BLOCK lanes per workgroup (tiled launches: BLOCK items per tile); the _w8
+// form asks the compiler for at least 8 waves per SIMD (at most 64 VGPRs), the
+// occupancy the tuner may pick.
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void packed_kernel(StripLaunch launch) {
+  packed_body<COLOUR, CMP, PRIV, WIDE, TILED, BLOCK>(launch);
+}
+
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void packed_kernel_w8(
+    StripLaunch launch) {
+  packed_body<COLOUR, CMP, PRIV, WIDE, TILED, BLOCK>(launch);
 }
 
 // Row-major lattice <-> two colour planes; one thread per 32 bytes of a row
@@ -240,13 +254,13 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(const uint8_t *src, uint
 template <int COLOUR, bool WIDE, bool TILED>
 hipError_t launch_w(const StripLaunch &l, unsigned grid, uint32_t q, hipStream_t stream) {
   if (q <= 16)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 0, true, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 0, true, WIDE, TILED, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
   else if (q <= kPrivateHistMaxQ)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, true, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, true, WIDE, TILED, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
   else if (q <= 128)
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, false, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 1, false, WIDE, TILED, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
   else
-    hipLaunchKernelGGL((packed_kernel<COLOUR, 2, false, WIDE, TILED>), dim3(grid), dim3(kBlock), 0, stream, l);
+    hipLaunchKernelGGL((packed_kernel<COLOUR, 2, false, WIDE, TILED, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
   return hipGetLastError();
 }
 
@@ -257,6 +271,20 @@ hipError_t launch_c(const StripLaunch &l, int colour, unsigned grid, uint32_t qm
   return wide ? launch_w<1, true, TILED>(l, grid, qmax, stream) : launch_w<1, false, TILED>(l, grid, qmax, stream);
 }
 
+// Tiled launches of q <= 16 in the tuner's other shapes.
+template <int COLOUR, bool WIDE>
+hipError_t launch_shape(const StripLaunch &l, unsigned ntiles, const TileShape &shape, hipStream_t stream) {
+  if (shape.block == 128) {
+    if (shape.wpe)
+      hipLaunchKernelGGL((packed_kernel_w8<COLOUR, 0, true, WIDE, true, 128>), dim3(ntiles), dim3(128), 0, stream, l);
+    else
+      hipLaunchKernelGGL((packed_kernel<COLOUR, 0, true, WIDE, true, 128>), dim3(ntiles), dim3(128), 0, stream, l);
+  } else {
+    hipLaunchKernelGGL((packed_kernel_w8<COLOUR, 0, true, WIDE, true, 256>), dim3(ntiles), dim3(256), 0, stream, l);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
@@ -264,6 +292,15 @@ hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32
   if (grid == 0) return hipSuccess;
   return l.tiles ? launch_c<true>(l, colour, grid, qmax, wide, stream)
                  : launch_c<false>(l, colour, grid, qmax, wide, stream);
+}
+
+hipError_t launch_packed_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,
+                               uint32_t qmax, bool wide, hipStream_t stream) {
+  if (!shape_ok(shape, qmax) || !l.tiles) return hipErrorInvalidValue;
+  if (ntiles == 0) return hipSuccess;
+  if (shape.block == 256 && shape.wpe == 0) return launch_c<true>(l, colour, ntiles, qmax, wide, stream);
+  if (colour == 0) return wide ? launch_shape<0, true>(l, ntiles, shape, stream) : launch_shape<0, false>(l, ntiles, shape, stream);
+  return wide ? launch_shape<1, true>(l, ntiles, shape, stream) : launch_shape<1, false>(l, ntiles, shape, stream);
 }
 
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream) {

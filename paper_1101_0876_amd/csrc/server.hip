@@ -43,6 +43,7 @@
 
 #include "../../include/potts.h"
 #include "kernels.hpp"
+#include "tune_cache.hpp"
 
 namespace potts {
 int record_error(int code, const std::string &msg);  // capi.hip
@@ -132,6 +133,8 @@ struct potts_server {
   void *h_stage = nullptr;  // pinned staging for descriptor uploads
   size_t cap_stage = 0;
   int64_t iterations = 0;
+  potts::TuneCache cache;   // launch shapes: strip heights per (q class, L), shape per q class
+  std::string tuned;        // what the tuner chose, for the record (guarded by mu)
 };
 
 namespace {
@@ -248,6 +251,140 @@ int read_job_checkpoint(Job &j, const char *path) {
   return POTTS_OK;
 }
 
+std::string shape_text(const potts::TileShape &t) {
+  return "block=" + std::to_string(t.block) + ",waves/SIMD=" + (t.wpe ? std::to_string(t.wpe) : std::string("auto"));
+}
+
+// Times `reps` sweeps of one throwaway lattice in the strip kernel with the
+// given height and shape; ms is the device time.
+bool time_shape(potts_server *s, potts::StripParams p, uint32_t rows, const potts::TileShape &shape, int reps,
+                uint64_t *t, float *ms, hipEvent_t e0, hipEvent_t e1, std::string &err) {
+  p.rows = rows;
+  potts::set_items(p, p.L / 16, p.L, rows);
+  p.t0 = *t;
+  p.nsweeps = (uint64_t)reps;
+  std::vector<potts::StripTile> tiles;
+  for (uint32_t first = 0; first < p.nitems; first += shape.block)
+    tiles.push_back(potts::StripTile{0, first, std::min<uint32_t>(shape.block, p.nitems - first), first == 0 ? 1u : 0u});
+  if (!reserve_dev((void **)&s->d_strip, &s->cap_strip, 1, sizeof(potts::StripParams)) ||
+      !reserve_dev((void **)&s->d_tiles, &s->cap_tiles, tiles.size(), sizeof(potts::StripTile))) {
+    err = "descriptor table allocation failed";
+    return false;
+  }
+  hipError_t e = hipMemcpyAsync(s->d_strip, &p, sizeof(p), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the host tables go away next
+  if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+  potts::StripLaunch l{};
+  l.jobs = s->d_strip;
+  l.tiles = s->d_tiles;
+  const uint32_t mq = (p.q <= 16) ? 16 : p.q <= potts::kPrivateHistMaxQ ? potts::kPrivateHistMaxQ : p.q <= 128 ? 128 : 256;
+  const bool wide = !p.thr.v[0] || !p.thr.v[1] || !p.thr.v[2] || !p.thr.v[3];
+  for (int k = 0; k < reps && e == hipSuccess; ++k) {
+    l.sweep = (uint32_t)k;
+    e = potts::launch_strip_tiled(l, 0, (unsigned)tiles.size(), shape, mq, wide, s->stream);
+    if (e == hipSuccess) e = potts::launch_strip_tiled(l, 1, (unsigned)tiles.size(), shape, mq, wide, s->stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e != hipSuccess) {
+    err = std::string("tuning failed: ") + herr(e);
+    return false;
+  }
+  *t += (uint64_t)reps;
+  return true;
+}
+
+// The strip height of lattice size L in q class qc (and, on first sight of
+// the class, the workgroup shape), timed on a throwaway random lattice at
+// beta_c(q) unless the cache knows them; the cache is updated.
+bool tune_size(potts_server *s, uint32_t L, uint32_t q, int qc, std::string &err) {
+  const std::string rkey = potts::TuneCache::rows_key(false, qc, L);
+  const std::string skey = potts::TuneCache::shape_key(false, qc);
+  const bool need_rows = !s->cache.rows.count(rkey);
+  const bool need_shape = qc == 0 && !s->cache.shapes.count(skey);
+  if (!need_rows && !need_shape) return true;
+  uint8_t *lat = nullptr;
+  unsigned long long *ring = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const uint64_t cap = 2;
+  hipError_t e = hipMallocAsync((void **)&lat, (size_t)L * L, s->stream);
+  if (e == hipSuccess) e = hipMallocAsync((void **)&ring, cap * (q + 1) * 8, s->stream);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  potts::InitParams ip{};
+  ip.spins = lat;
+  ip.L = L;
+  ip.q = q;
+  ip.nchunks = (uint64_t)L * L / 4;
+  ip.k0 = 1;
+  ip.random = 1;
+  if (e == hipSuccess) e = potts::launch_init(ip, s->stream);
+  if (e == hipSuccess) e = potts::launch_fill_u64(ring, cap * (q + 1), 0ull, s->stream);
+  bool ok = e == hipSuccess;
+  if (!ok) err = std::string("tuning setup failed: ") + herr(e);
+  uint32_t thr[4] = {0, 0, 0, 0};
+  if (ok) ok = potts::build_threshold_table(log1p(sqrt((double)q)), thr) == POTTS_OK;
+  potts::StripParams p{};
+  if (ok) {
+    potts::fill_strip_params(p, lat, L, q, 1, thr, 2);
+    p.ring = ring;
+    p.cap = cap;
+  }
+  uint64_t t = 0;
+  const potts::TileShape base;
+  uint32_t rows = need_rows ? 0 : s->cache.rows[rkey];
+  float ms = 0.0f;
+  if (ok && need_rows) {
+    ok = time_shape(s, p, 2, base, 1, &t, &ms, e0, e1, err);  // warm-up
+    float best_ms = 0.0f;
+    for (uint32_t r = 2; r <= 32 && ok; r *= 2) {
+      if (L % r) continue;
+      ok = time_shape(s, p, r, base, 2, &t, &ms, e0, e1, err);
+      if (ok && (rows == 0 || ms < best_ms)) {
+        best_ms = ms;
+        rows = r;
+      }
+    }
+    if (ok) {
+      s->cache.rows[rkey] = rows;
+      s->cache.dirty = true;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->tuned += "L=" + std::to_string(L) + ":rows=" + std::to_string(rows) + " ";
+    }
+  }
+  if (ok && need_shape) {
+    const potts::TileShape cands[4] = {{256, 0}, {128, 0}, {256, 8}, {128, 8}};
+    float best_ms = 0.0f;
+    potts::TileShape best = cands[0];
+    for (int c = 0; c < 4 && ok; ++c) {
+      ok = time_shape(s, p, rows, cands[c], 2, &t, &ms, e0, e1, err);
+      if (ok && (c == 0 || ms < best_ms)) {
+        best_ms = ms;
+        best = cands[c];
+      }
+    }
+    if (ok) {
+      s->cache.shapes[skey] = best;
+      s->cache.dirty = true;
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->tuned += "strip/q16:" + shape_text(best) + " ";
+    }
+  }
+  (void)hipStreamSynchronize(s->stream);
+  if (lat) (void)hipFreeAsync(lat, s->stream);
+  if (ring) (void)hipFreeAsync(ring, s->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (ok && !s->cache.save()) {
+    err = "cannot write the tuning cache " + s->cache.path;
+    ok = false;
+  }
+  return ok;
+}
+
 // Allocates and initializes an admitted job on the server stream.
 bool admit(potts_server *s, Job &j, std::string &err) {
   hipError_t e = hipMallocAsync((void **)&j.lat, ((size_t)j.req.L * j.req.L + 255) / 256 * 256, s->stream);
@@ -281,7 +418,19 @@ bool admit(potts_server *s, Job &j, std::string &err) {
     return false;
   }
   j.resident = potts::resident_fits((uint32_t)j.req.L, (uint32_t)j.req.q);
-  j.rows = j.resident ? 0 : potts::auto_strip_rows((uint32_t)j.req.L, (uint32_t)j.req.L, 64 * 256);
+  j.rows = 0;
+  if (!j.resident) {
+    const int qc = q_class((uint32_t)j.req.q);
+    if (s->cfg.tune && !tune_size(s, (uint32_t)j.req.L, (uint32_t)j.req.q, qc, err)) {
+      (void)hipStreamSynchronize(s->stream);
+      release_job_memory(j);
+      return false;
+    }
+    auto hit = s->cache.rows.find(potts::TuneCache::rows_key(false, qc, (uint32_t)j.req.L));
+    j.rows = hit != s->cache.rows.end() && j.req.L % hit->second == 0
+                 ? hit->second
+                 : potts::auto_strip_rows((uint32_t)j.req.L, (uint32_t)j.req.L, 64 * 256);
+  }
   j.point = j.resume ? j.resume_point : 0;
   j.left = j.sweeps[(size_t)j.point];
   j.t = j.resume ? j.resume_t : 0;
@@ -298,12 +447,16 @@ int iterate(potts_server *s, std::string &err) {
     int qc;
     bool wide;
     std::vector<Job *> jobs;
+    potts::TileShape shape;
   };
   std::vector<SG> strip_groups, res_groups;
-  auto group_of = [](std::vector<SG> &gs, int qc, bool wide) -> SG & {
+  auto group_of = [s](std::vector<SG> &gs, int qc, bool wide) -> SG & {
     for (SG &g : gs)
       if (g.qc == qc && g.wide == wide) return g;
-    gs.push_back(SG{qc, wide, {}});
+    potts::TileShape shape;
+    auto hit = s->cache.shapes.find(potts::TuneCache::shape_key(false, qc));
+    if (hit != s->cache.shapes.end() && potts::shape_ok(hit->second, class_max_q(qc))) shape = hit->second;
+    gs.push_back(SG{qc, wide, {}, shape});
     return gs.back();
   };
   std::vector<int64_t> step(s->active.size());
@@ -335,8 +488,8 @@ int iterate(potts_server *s, std::string &err) {
       p.ring = j.ring;
       p.cap = (uint64_t)j.cap;
       strip_sweeps = std::max<int64_t>(strip_sweeps, nstep[&j]);
-      for (uint32_t first = 0; first < p.nitems; first += 256)
-        tiles.push_back(potts::StripTile{(uint32_t)k, first, std::min<uint32_t>(256, p.nitems - first),
+      for (uint32_t first = 0; first < p.nitems; first += g.shape.block)
+        tiles.push_back(potts::StripTile{(uint32_t)k, first, std::min<uint32_t>(g.shape.block, p.nitems - first),
                                          first == 0 ? 1u : 0u});
       desc.push_back(p);
     }
@@ -432,8 +585,10 @@ int iterate(potts_server *s, std::string &err) {
       l.tiles = s->d_tiles + tile_off[gi];
       l.sweep = (uint32_t)sw;
       const uint32_t mq = class_max_q(strip_groups[gi].qc);
-      e = potts::launch_strip(l, 0, (unsigned)tile_cnt[gi], mq, strip_groups[gi].wide, s->stream);
-      if (e == hipSuccess) e = potts::launch_strip(l, 1, (unsigned)tile_cnt[gi], mq, strip_groups[gi].wide, s->stream);
+      const potts::TileShape &shape = strip_groups[gi].shape;
+      e = potts::launch_strip_tiled(l, 0, (unsigned)tile_cnt[gi], shape, mq, strip_groups[gi].wide, s->stream);
+      if (e == hipSuccess)
+        e = potts::launch_strip_tiled(l, 1, (unsigned)tile_cnt[gi], shape, mq, strip_groups[gi].wide, s->stream);
     }
   }
   std::vector<double> out(stats.size() * 8);
@@ -660,6 +815,8 @@ int potts_server_start(const potts_server_cfg *cfg, potts_server **out) {
   if (s->cfg.hbm_budget <= 0) s->cfg.hbm_budget = 200ll << 30;
   if (s->cfg.max_slots <= 0) s->cfg.max_slots = 256;
   if (s->cfg.quantum <= 0) s->cfg.quantum = 32;
+  s->cache.load(s->cfg.tune_cache);
+  s->cfg.tune_cache = nullptr;  // the path lives on in the cache
   if (s->cfg.hip_stream) {
     s->stream = (hipStream_t)s->cfg.hip_stream;
   } else {
@@ -797,6 +954,20 @@ int potts_server_drain(potts_server *s, int32_t timeout_ms) {
 double potts_server_now(const potts_server *s) { return s ? seconds_since(s) : -1.0; }
 
 int64_t potts_server_iterations(const potts_server *s) { return s ? s->iterations : -1; }
+
+int potts_server_tuning(potts_server *s, char *out, int32_t cap) {
+  if (!s || !out || cap < 1) return record_error(POTTS_EINVAL, "NULL argument or cap < 1");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::string text = s->tuned;
+  for (const auto &kv : s->cache.rows)
+    if (text.find(kv.first) == std::string::npos) text += kv.first + ":rows=" + std::to_string(kv.second) + "(cached) ";
+  for (const auto &kv : s->cache.shapes)
+    if (text.find(kv.first) == std::string::npos) text += kv.first + ":" + shape_text(kv.second) + "(cached) ";
+  const size_t n = std::min<size_t>(text.size(), (size_t)cap - 1);
+  memcpy(out, text.data(), n);
+  out[n] = 0;
+  return POTTS_OK;
+}
 
 int potts_server_stop(potts_server *s) {
   if (!s) return POTTS_OK;

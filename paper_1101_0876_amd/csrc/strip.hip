@@ -25,7 +25,6 @@ namespace potts {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
 
 using namespace row;
 
@@ -76,8 +75,9 @@ __device__ __forceinline__ void do_row(const StripParams &p, const PhiloxHead &h
 // lattices); otherwise the single descriptor in the kernel arguments with a
 // grid-stride loop.  Two instantiations keep the descriptor in scalar
 // registers in both cases.
-template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED>
-__global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__device__ __forceinline__ void strip_body(const StripLaunch &launch) {
+  constexpr int kWaves = BLOCK / 64;
   // acceptance table in static LDS, so its address folds into the ds_read offset
   __shared__ __align__(16) uint32_t table_words[512];
   // colour 1 walks the lattice bottom-up, so it starts on the rows colour 0
@@ -86,9 +86,9 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   const uint32_t bid = COLOUR == 1 ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
   const StripTile tile = TILED ? launch.tiles[bid] : StripTile{0, 0, 0, 0};
   const StripParams &p = TILED ? launch.jobs[tile.job] : launch.single;
-  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * kBlock + threadIdx.x;
+  const uint32_t first = TILED ? tile.first + threadIdx.x : bid * BLOCK + threadIdx.x;
   const uint32_t end = TILED ? tile.first + tile.count : p.nitems;
-  const uint32_t stride = TILED ? (uint32_t)kBlock : gridDim.x * kBlock;
+  const uint32_t stride = TILED ? (uint32_t)BLOCK : gridDim.x * BLOCK;
   const bool lead = TILED ? tile.lead != 0 : bid == 0;
   if (launch.sweep >= p.nsweeps) return;  // the whole workgroup: this job is done
   const uint64_t t = p.t0 + launch.sweep;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
 
   fill_accept_table<WIDE>(table, p.thr);
   const uint32_t nh = PRIV ? 64 * q : q;
-  for (uint32_t i = threadIdx.x; i < nh; i += kBlock) hist[i] = 0;
+  for (uint32_t i = threadIdx.x; i < nh; i += BLOCK) hist[i] = 0;
   // a workgroup's bond count reaches 2N / grid, beyond 32 bits on the largest
   // lattices with few workgroups: counted in 64 bits
   __shared__ unsigned long long esum;
@@ -115,11 +115,11 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   if (p.stripes) {
     // the previous launched sweep's partial records, complete now
     __shared__ unsigned long long fold_acc[COLOUR == 0 ? 257 : 1];
-    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<kBlock>(p, t - 1, fold_acc);
+    if (COLOUR == 0 && lead && launch.sweep > 0) fold_stripes<BLOCK>(p, t - 1, fold_acc);
   } else if (COLOUR == 1 && lead) {
     // the slot of sweep t+1, zeroed before the next colour-0 launch starts
     unsigned long long *rec_next = p.ring + ((t + 1) & (p.cap - 1)) * (uint64_t)(q + 1);
-    for (uint32_t i = threadIdx.x; i < q + 1; i += kBlock) rec_next[i] = 0;
+    for (uint32_t i = threadIdx.x; i < q + 1; i += BLOCK) rec_next[i] = 0;
   }
   __syncthreads();
 
@@ -181,11 +181,25 @@ __global__ __launch_bounds__(kBlock) void strip_kernel(StripLaunch launch) {
   }
   unsigned long long *dst =
       p.stripes ? p.stripes + ((t & 1) * p.nstripes + (bid & (p.nstripes - 1))) * (uint64_t)stripe_words(q) : rec;
-  for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
+  for (uint32_t v = threadIdx.x; v < q; v += BLOCK) {
     const uint32_t s = PRIV ? partial[v] : hist[v];
     if (s) atomicAdd(&dst[1 + v], (unsigned long long)s);
   }
   if (COLOUR == 1 && threadIdx.x == 0 && esum) atomicAdd(&dst[0], esum);
+}
+
+// BLOCK lanes per workgroup (tiled launches: BLOCK items per tile); the _w8
+// form asks the compiler for at least 8 waves per SIMD (at most 64 VGPRs), the
+// occupancy the tuner may pick.
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void strip_kernel(StripLaunch launch) {
+  strip_body<COLOUR, CMP, PRIV, WIDE, TILED, BLOCK>(launch);
+}
+
+template <int COLOUR, int CMP, bool PRIV, bool WIDE, bool TILED, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void strip_kernel_w8(
+    StripLaunch launch) {
+  strip_body<COLOUR, CMP, PRIV, WIDE, TILED, BLOCK>(launch);
 }
 
 __global__ __launch_bounds__(kBlock) void fold_kernel(StripParams p, uint64_t t) {
@@ -196,9 +210,23 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(StripParams p, uint64_t t)
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 hipError_t launch_t(const StripLaunch &l, unsigned grid, size_t lds, hipStream_t stream) {
   if (l.tiles)
-    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, true>), dim3(grid), dim3(kBlock), lds, stream, l);
+    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, true, kBlock>), dim3(grid), dim3(kBlock), lds, stream, l);
   else
-    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, false>), dim3(grid), dim3(kBlock), lds, stream, l);
+    hipLaunchKernelGGL((strip_kernel<COLOUR, CMP, PRIV, WIDE, false, kBlock>), dim3(grid), dim3(kBlock), lds, stream, l);
+  return hipGetLastError();
+}
+
+// Tiled launches of q <= 16 in the tuner's other shapes.
+template <int COLOUR, bool WIDE>
+hipError_t launch_shape(const StripLaunch &l, unsigned ntiles, const TileShape &shape, hipStream_t stream) {
+  if (shape.block == 128) {
+    if (shape.wpe)
+      hipLaunchKernelGGL((strip_kernel_w8<COLOUR, 0, true, WIDE, true, 128>), dim3(ntiles), dim3(128), 0, stream, l);
+    else
+      hipLaunchKernelGGL((strip_kernel<COLOUR, 0, true, WIDE, true, 128>), dim3(ntiles), dim3(128), 0, stream, l);
+  } else {
+    hipLaunchKernelGGL((strip_kernel_w8<COLOUR, 0, true, WIDE, true, 256>), dim3(ntiles), dim3(256), 0, stream, l);
+  }
   return hipGetLastError();
 }
 
@@ -228,6 +256,15 @@ hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_
   if (grid == 0) return hipSuccess;
   return colour == 0 ? launch_c<0>(l, grid, max_q, wide, 0, stream)
                      : launch_c<1>(l, grid, max_q, wide, 0, stream);
+}
+
+hipError_t launch_strip_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,
+                              uint32_t max_q, bool wide, hipStream_t stream) {
+  if (!shape_ok(shape, max_q) || !l.tiles) return hipErrorInvalidValue;
+  if (ntiles == 0) return hipSuccess;
+  if (shape.block == 256 && shape.wpe == 0) return launch_strip(l, colour, ntiles, max_q, wide, stream);
+  if (colour == 0) return wide ? launch_shape<0, true>(l, ntiles, shape, stream) : launch_shape<0, false>(l, ntiles, shape, stream);
+  return wide ? launch_shape<1, true>(l, ntiles, shape, stream) : launch_shape<1, false>(l, ntiles, shape, stream);
 }
 
 }  // namespace potts

@@ -122,3 +122,52 @@ def test_batch_rejects_bad_jobs(potts, bad):
     j.update(bad)
     with pytest.raises(potts.PottsError):
         potts.Batch([MIX[1], j])
+
+
+def test_tuner_shapes_cache_and_every_shape(potts, oracle_lib, tmp_path):
+    """The tuner times strip heights per lattice size, then the workgroup shape
+    (lanes per workgroup, occupancy) per kernel group, on real sweeps of the
+    run; its choices persist in a JSON cache keyed by the kernels' digest,
+    which a second batch reads without timing.  Every shape, forced through
+    the cache, gives the oracle's bits."""
+    import json
+
+    cache = str(tmp_path / "tune.json")
+    jobs = [dict(j, nsweeps=40) for j in (MIX[6], MIX[7], MIX[8], MIX[14])]
+    want = [_oracle(oracle_lib, j) for j in jobs]
+    digest = potts.load().potts_kernel_digest().decode()
+
+    def check(b):
+        for i, (s, rec) in enumerate(want):
+            assert np.array_equal(b.records(i, 0, 40), rec), i
+            assert np.array_equal(b.spins(i), s), i
+
+    with potts.Batch(jobs, graph=True, tune=True, tune_cache=cache) as b:
+        b.run()
+        tuned = b.tuning()
+        _say(f"tuned: {tuned}")
+        check(b)
+    assert "rows=" in tuned and "block=" in tuned and "waves/SIMD=" in tuned
+    data = json.load(open(cache))
+    assert data["kernel_hash"] == digest
+    assert set(data["rows"]) == {"packed/0/512", "packed/0/1024", "strip/0/560"}
+    assert set(data["shapes"]) == {"packed/0", "strip/0"}
+    with potts.Batch(jobs, graph=True, tune=False, tune_cache=cache) as b:
+        b.run()
+        assert "(cached)" in b.tuning() and "block=" in b.tuning()
+        check(b)
+    for shape in ([128, 0], [256, 8], [128, 8], [256, 0]):
+        with open(cache, "w") as f:
+            json.dump({"kernel_hash": digest, "rows": {"packed/0/512": 2, "packed/0/1024": 32, "strip/0/560": 8},
+                       "shapes": {"packed/0": shape, "strip/0": shape}}, f)
+        _say(f"forced shape {shape}")
+        with potts.Batch(jobs, graph=False, tune=False, tune_cache=cache) as b:
+            b.run()
+            check(b)
+    # a cache of other kernel sources is ignored
+    with open(cache, "w") as f:
+        json.dump({"kernel_hash": "other", "rows": {"packed/0/512": 4}, "shapes": {"packed/0": [128, 8]}}, f)
+    with potts.Batch(jobs, graph=False, tune=False, tune_cache=cache) as b:
+        b.run()
+        assert "cached" not in b.tuning()
+        check(b)

@@ -156,3 +156,30 @@ def test_served_job_resumes_after_a_failure(potts, oracle_lib, tmp_path, L, q, f
             srv.submit(L, q, 42, 1, job["betas"], job["sweeps"], resume_from=ck)
     assert got["sweeps"] == sum(job["sweeps"])
     _check(got, *_oracle(oracle_lib, job))
+
+
+def test_server_tunes_and_persists_shapes(potts, oracle_lib, tmp_path):
+    """A tuning server times the strip height of each new lattice size and the
+    workgroup shape of q <= 16 on a throwaway lattice before its first job of
+    that size; the choices persist, a second server reads them, and every job
+    still gives the oracle's bits."""
+    import json
+
+    cache = str(tmp_path / "serve_tune.json")
+    for tune in (True, False):
+        with potts.Server(quantum=8, tune=tune, tune_cache=cache) as srv:
+            tickets = [srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"], keep_spins=True)
+                       for j in JOBS]
+            srv.drain(120000)
+            got = [srv.collect(t, spins=True) for t in tickets]
+            tuned = srv.tuning()
+        print(f"tune={tune}: {tuned}", flush=True)
+        for g, j in zip(got, JOBS):
+            _check(g, *_oracle(oracle_lib, j))
+        assert "rows=" in tuned and "block=" in tuned
+        if not tune:
+            assert "(cached)" in tuned
+    data = json.load(open(cache))
+    assert data["kernel_hash"] == potts.load().potts_kernel_digest().decode()
+    assert {"strip/0/512", "strip/0/528", "strip/1/1024"} <= set(data["rows"])
+    assert "strip/0" in data["shapes"]
