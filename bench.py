@@ -113,6 +113,7 @@ def run_large(args):
                 for start in (potts.ORDERED, potts.RANDOM)]
         for lat in lats:
             lat.tune(kernel=args.kernel)
+            lat.tune_occupancy(args.occupancy)
         return lats
 
     if args.warmup > 0:
@@ -793,6 +794,8 @@ def main():
     ap.add_argument("--serve-scale", type=float, default=0.01)
     ap.add_argument("--serve-quantum", type=int, default=32)
     ap.add_argument("--serve-slots", type=int, default=256)
+    ap.add_argument("--occupancy", type=int, default=0, choices=[0, 8],
+                    help="large: colour-split kernel waves per SIMD (0: the compiler's choice)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()

@@ -159,6 +159,12 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * Errors: EINVAL. */
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups);
 
+/* Occupancy of the colour-split kernel: 0 = the compiler's register budget
+ * (the default), 8 = at most 64 VGPRs so that 8 waves fit on each SIMD (the
+ * variant exists for q <= 16; other q keep the default).  Results never
+ * depend on it.  Errors: EINVAL (s NULL, waves_per_simd not 0 or 8). */
+int potts_tune_occupancy(potts_state *s, int32_t waves_per_simd);
+
 /* The table potts_sweep uses for beta: thr[d-1] = min(floor(exp(-beta d)
  * 2^32), 2^32-1), computed on the host in FP64.  Errors: EINVAL. */
 int potts_threshold_table(double beta, uint32_t thr[4]);

@@ -107,6 +107,10 @@ class Lattice:
         """Launch shape (0 = automatic); results are identical for every choice."""
         check(self._lib.potts_tune(self._h, int(kernel), int(strip_rows), int(max_groups)))
 
+    def tune_occupancy(self, waves_per_simd: int) -> None:
+        """Colour-split kernel occupancy: 0 (compiler's choice) or 8 waves per SIMD."""
+        check(self._lib.potts_tune_occupancy(self._h, int(waves_per_simd)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts_time(self._h))

@@ -34,6 +34,7 @@ struct potts_state {
   int kernel = 0;          // 0 automatic, 1 strip, 2 chunk, 3 LDS-resident
   uint32_t rows = 0;       // strip rows per work item, 0 = automatic
   unsigned max_groups = 0; // persistent grid size, 0 = automatic
+  uint32_t wpe = 0;        // colour-split kernel: waves per SIMD asked of the compiler (0 = its choice)
   // The colour-split kernel works on a copy of the lattice in spins2 split
   // into its two colour planes; the row-major lattice in spins is rebuilt
   // only when something reads it, and the copy only when it is stale.
@@ -375,8 +376,8 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     p.nsweeps = (uint64_t)count;
     for (int64_t j = 0; j < count; ++j) {
       l.sweep = (uint32_t)j;
-      HIP_TRY(potts::launch_packed(l, 0, grid, l.single.q, wide, s->stream));
-      HIP_TRY(potts::launch_packed(l, 1, grid, l.single.q, wide, s->stream));
+      HIP_TRY(potts::launch_packed_single(l, 0, grid, l.single.q, wide, s->wpe, s->stream));
+      HIP_TRY(potts::launch_packed_single(l, 1, grid, l.single.q, wide, s->wpe, s->stream));
     }
     HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
   }
@@ -613,6 +614,13 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
   const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
   const unsigned grid = (unsigned)(need < 8192 ? need : 8192);
   HIP_TRY(potts::launch_strip(l, colour, grid, p.q, wide_table(thr), static_cast<hipStream_t>(hip_stream)));
+  return POTTS_OK;
+}
+
+int potts_tune_occupancy(potts_state *s, int32_t waves_per_simd) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (waves_per_simd != 0 && waves_per_simd != 8) return fail(POTTS_EINVAL, "waves_per_simd must be 0 or 8");
+  s->wpe = (uint32_t)waves_per_simd;
   return POTTS_OK;
 }
 

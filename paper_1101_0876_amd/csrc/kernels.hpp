@@ -174,6 +174,10 @@ hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_
 hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
                          hipStream_t stream);
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream);
+// a single lattice's colour-split launch (grid-stride) asking for at least
+// wpe waves per SIMD (0: the compiler's choice; 8 exists for q <= 16)
+hipError_t launch_packed_single(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
+                                uint32_t wpe, hipStream_t stream);
 // tiled launches (l.tiles set, tiles of shape.block items) in a tuner shape;
 // hipErrorInvalidValue for a shape that does not exist for max_q
 hipError_t launch_strip_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,

@@ -294,6 +294,24 @@ hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32
                  : launch_c<false>(l, colour, grid, qmax, wide, stream);
 }
 
+hipError_t launch_packed_single(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
+                                uint32_t wpe, hipStream_t stream) {
+  if (wpe == 0 || qmax > 16 || l.tiles) return launch_packed(l, colour, grid, qmax, wide, stream);
+  if (grid == 0) return hipSuccess;
+  if (colour == 0) {
+    if (wide)
+      hipLaunchKernelGGL((packed_kernel_w8<0, 0, true, true, false, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
+    else
+      hipLaunchKernelGGL((packed_kernel_w8<0, 0, true, false, false, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL((packed_kernel_w8<1, 0, true, true, false, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
+    else
+      hipLaunchKernelGGL((packed_kernel_w8<1, 0, true, false, false, kBlock>), dim3(grid), dim3(kBlock), 0, stream, l);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_packed_tiled(const StripLaunch &l, int colour, unsigned ntiles, const TileShape &shape,
                                uint32_t qmax, bool wide, hipStream_t stream) {
   if (!shape_ok(shape, qmax) || !l.tiles) return hipErrorInvalidValue;

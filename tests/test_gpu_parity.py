@@ -434,6 +434,26 @@ def test_launch_shape_does_not_change_results(potts, oracle_lib, L):
             assert np.array_equal(lat.spins(), want_spins), (kernel, rows, groups)
 
 
+@pytest.mark.parametrize("L,q,start", [(512, 6, 1), (1056, 16, 0), (96, 9, 1), (512, 40, 1)])
+def test_occupancy_does_not_change_results(potts, oracle_lib, L, q, start):
+    """The colour-split kernel asked for 8 waves per SIMD (q <= 16; other q
+    keep the default variant) gives the same bits, alone and switched
+    mid-chain."""
+    seed, beta, n = 31, beta_c(q), 5
+    want_spins, want_rec = oracle_lib.run(L, q, seed, start, beta, n)
+    with potts.Lattice(L, q, seed, start) as lat:
+        lat.tune_occupancy(8)
+        lat.sweep(beta, 3)
+        lat.tune_occupancy(0)
+        lat.sweep(beta, 1)
+        lat.tune_occupancy(8)
+        lat.sweep(beta, 1)
+        assert np.array_equal(lat.records(0, n), want_rec)
+        assert np.array_equal(lat.spins(), want_spins)
+        with pytest.raises(potts.PottsError):
+            lat.tune_occupancy(4)
+
+
 def test_tune_rejects_bad_shapes(potts):
     with potts.Lattice(20, 3, 1, 1) as lat:
         with pytest.raises(potts.PottsError):
