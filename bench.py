@@ -495,7 +495,8 @@ def run_heatbath(args):
     beta = 1.02 * math.log(4.0)
     steps = args.steps if args.steps != 2000 else 200
     st = torch.cuda.Stream()
-    with potts.Lattice.from_torch(L, q, seed, potts.RANDOM, stream=st) as lat:
+    with potts.Lattice.on_stream(L, q, seed, potts.RANDOM, stream=st) as lat:
+        lat.tune(kernel=args.kernel)
         lat.sweep_heatbath(beta, max(1, args.warmup))
         st.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -539,7 +540,8 @@ def run_heatbath(args):
                 "unit": "Tops/s",
                 "frac": achieved_ops / VALU_PEAK_OPS,
                 "traffic": None,
-                "kernel": "heatbath4_kernel (chunk half sweep)",
+                "kernel": "heatbath4_kernel (chunk half sweep)" if args.kernel == 2
+                          else "hb_packed_kernel (colour-split heat-bath half sweep)",
                 "avg_launch_us": per_launch_s * 1e6,
                 "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
             },

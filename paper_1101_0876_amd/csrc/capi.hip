@@ -40,6 +40,12 @@ struct potts_state {
   // only when something reads it, and the copy only when it is stale.
   bool spins_valid = true;    // spins holds the current configuration
   bool planes_valid = false;  // spins2 holds it, colour-split
+  // heat-bath draw table of the colour-split kernel (device copy, and the host
+  // copy it was uploaded from, valid for hb_thr and q)
+  potts::HbTable *hb_dev = nullptr;
+  potts::HbTable *hb_host = nullptr;
+  uint32_t hb_thr[4] = {0, 0, 0, 0};
+  bool hb_valid = false, hb_wide = false;
 };
 
 namespace {
@@ -106,6 +112,8 @@ void release(potts_state *s) {
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->stripes) (void)hipFree(s->stripes);
   if (s->stats_out) (void)hipFree(s->stats_out);
+  if (s->hb_dev) (void)hipFree(s->hb_dev);
+  if (s->hb_host) (void)hipHostFree(s->hb_host);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
 }
@@ -458,13 +466,78 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   return POTTS_OK;
 }
 
-// Heat-bath sweeps (kernels.hip): one thread per 4-byte chunk, records as the
-// chunk path; the sweep counter is shared with the Metropolis sweeps.
+// Heat-bath sweeps on the colour-split copy (heatbath_packed.hip): the draw
+// table is rebuilt and uploaded when the thresholds change; records through
+// the striped partial records, as the Metropolis colour-split path.
+int run_heatbath_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  const uint32_t L = (uint32_t)s->L;
+  if (!s->hb_dev) {
+    if (hipMalloc(&s->hb_dev, sizeof(potts::HbTable)) != hipSuccess ||
+        hipHostMalloc(&s->hb_host, sizeof(potts::HbTable), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the heat-bath table failed");
+    }
+  }
+  if (!s->hb_valid || memcmp(s->hb_thr, thr, sizeof(s->hb_thr)) != 0) {
+    // the previous upload from the host copy may still be queued
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->hb_wide = potts::build_heatbath_table(thr, (uint32_t)s->q, s->hb_host);
+    HIP_TRY(hipMemcpyAsync(s->hb_dev, s->hb_host, sizeof(potts::HbTable), hipMemcpyHostToDevice, s->stream));
+    memcpy(s->hb_thr, thr, sizeof(s->hb_thr));
+    s->hb_valid = true;
+  }
+  if (!s->planes_valid) {
+    HIP_TRY(potts::launch_pack(s->spins, s->spins2, L, s->stream));
+    s->planes_valid = true;
+  }
+  s->spins_valid = false;
+  potts::HbLaunch l{};
+  potts::StripParams &p = l.p;
+  const uint32_t rows = packed_rows(s);
+  fill_strip_params(p, s->spins2, L, (uint32_t)s->q, s->seed, thr, rows);
+  potts::set_items(p, L / 32, L, rows);
+  p.ring = s->records;
+  p.cap = (uint64_t)s->rec_cap;
+  p.stripes = s->stripes;
+  p.nstripes = kStripes;
+  l.table = s->hb_dev;
+  const unsigned groups = s->max_groups ? s->max_groups : 8192u;
+  const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
+  const unsigned grid = (unsigned)(need < groups ? need : groups);
+  const int64_t seg = 1ll << 30;
+  for (int64_t base = 0; base < nsweeps; base += seg) {
+    const int64_t count = std::min<int64_t>(seg, nsweeps - base);
+    p.t0 = (uint64_t)(s->t + base);
+    p.nsweeps = (uint64_t)count;
+    for (int64_t j = 0; j < count; ++j) {
+      l.sweep = (uint32_t)j;
+      HIP_TRY(potts::launch_heatbath_packed(l, 0, grid, s->hb_wide, s->stream));
+      HIP_TRY(potts::launch_heatbath_packed(l, 1, grid, s->hb_wide, s->stream));
+    }
+    HIP_TRY(potts::launch_fold_stripes(p, p.t0 + (uint64_t)count - 1, s->stream));
+  }
+  s->t += nsweeps;
+  if (!s->owns_spins) {
+    HIP_TRY(potts::launch_unpack(s->spins2, s->spins, L, s->stream));
+    s->spins_valid = true;
+    s->planes_valid = false;
+  }
+  return POTTS_OK;
+}
+
+// Heat-bath sweeps: on the colour-split copy where the lattice has one (L % 32
+// == 0, kernel 0 or 4), else one thread per 4-byte chunk (kernels.hip); the
+// sweep counter and records are shared with the Metropolis sweeps.
 int run_heatbath(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
+  if (packed_ok(s) && (s->kernel == 0 || s->kernel == 4)) {
+    const int64_t rl = s->q + 1;
+    HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
+    return run_heatbath_packed(s, thr, nsweeps);
+  }
   {
     const int rc = sync_spins(s);
     if (rc) return rc;

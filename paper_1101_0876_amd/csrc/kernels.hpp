@@ -89,6 +89,31 @@ struct StripLaunch {
   uint32_t sweep;           // this launch updates sweep t = t0 + sweep of every job
 };
 
+// Heat-bath draw table of the colour-split kernel, per pattern of equal
+// neighbours (64 patterns of the six flags ab, ac, ad, bc, bd, cd "differ",
+// a..d = up, down, left, right; pattern bit 5 = ab .. bit 0 = cd), built on
+// the host from the thresholds and q: the cuts on the site's word that pick
+// the ranked neighbour values, Z and S of the draw, w0 and its reciprocal.
+struct HbTable {
+  static constexpr uint32_t kCut = 0;       // 64 x 4 uint32: ceil(c_i 2^32 / Z) - 1 (all thresholds >= 1)
+  static constexpr uint32_t kZs = 1024;     // 64 x {Z lo, Z hi, S lo, S hi}
+  static constexpr uint32_t kWi = 2048;     // 64 x {w0, 1/w0 as FP32 bits, 0, 0}
+  static constexpr uint32_t kCut64 = 3072;  // 64 x 4 uint64: ceil(c_i 2^32 / Z) (some threshold 0)
+  static constexpr uint32_t kBytes = 5120;
+  uint8_t bytes[kBytes];
+};
+
+struct HbLaunch {
+  StripParams p;         // the colour-split copy, as for the Metropolis kernel
+  const HbTable *table;  // device
+  uint32_t sweep;        // sweep t = p.t0 + sweep
+};
+
+// fills the table for thresholds thr and q; returns true when some threshold
+// is 0 (the wide form is then the one to use)
+bool build_heatbath_table(const uint32_t thr[4], uint32_t q, HbTable *t);
+hipError_t launch_heatbath_packed(const HbLaunch &l, int colour, unsigned grid, bool wide, hipStream_t stream);
+
 // populations are counted in lane-private LDS columns up to this many states
 constexpr uint32_t kPrivateHistMaxQ = 64;
 

@@ -54,12 +54,47 @@ def test_heatbath_matches_oracle(potts, oracle_lib, L, q, seed, start, beta, n):
         assert np.array_equal(lat.records(0, n), rec)
 
 
+# lattices with L % 32 == 0 take the colour-split kernel: every comparison
+# class (q <= 16, <= 64 lane-private populations, <= 128, any), zero
+# thresholds (the wide cuts), beta = 0, ragged item counts
+SPLIT_CASES = [
+    (32, 2, 31, 1, 0.9, 6),
+    (96, 16, 32, 1, 1.3, 5),
+    (96, 17, 33, 0, 1.2, 5),
+    (160, 64, 34, 1, 1.4, 4),
+    (160, 65, 35, 1, 1.4, 4),
+    (224, 128, 36, 1, 1.5, 3),
+    (224, 129, 37, 0, 1.5, 3),
+    (64, 256, 38, 1, 2.0, 3),
+    (96, 200, 39, 1, 9.0, 4),
+    (128, 6, 40, 1, 0.0, 3),
+    (544, 15, 41, 1, beta_c(15), 4),
+    (1056, 9, 42, 0, beta_c(9), 3),
+]
+
+
+@pytest.mark.parametrize("L,q,seed,start,beta,n", SPLIT_CASES)
+@pytest.mark.parametrize("kernel", [0, 2])
+def test_heatbath_colour_split_matches_oracle(potts, oracle_lib, L, q, seed, start, beta, n, kernel):
+    """The colour-split heat-bath kernel (kernel 0: automatic) and the chunk
+    kernel (kernel 2) on the same lattices give the oracle's chain."""
+    print(f"heatbath split L={L} q={q} beta={beta:.4f} kernel={kernel}", flush=True)
+    s = oracle_lib.init(L, q, seed, start)
+    rec = oracle_lib.heatbath_sweeps(s, q, seed, 0, n, oracle_lib.threshold_table(beta))
+    with potts.Lattice(L, q, seed, start) as lat:
+        lat.tune(kernel=kernel)
+        lat.sweep_heatbath(beta, n)
+        assert np.array_equal(lat.records(0, n), rec)
+        assert np.array_equal(lat.spins(), s)
+
+
+@pytest.mark.parametrize("L", [48, 64])  # chunk kernel, colour-split kernel
 @pytest.mark.parametrize("q", [3, 16, 129])
-def test_heatbath_caller_tables(potts, oracle_lib, q):
+def test_heatbath_caller_tables(potts, oracle_lib, q, L):
     """Caller tables that no temperature gives: zeros, 1, 2^32 - 1 and values
     out of order, so that w0 (the weight of a value no neighbour holds) is 0
     for some counts and tiny for others."""
-    L, seed = 48, 21
+    seed = 21
     tables = [np.array(t, dtype=np.uint32) for t in
               ([1, 0, 7, 0xFFFFFFFF], [0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF], [0, 0, 0, 0],
                [3, 0xFFFFFFFE, 1, 2])]
