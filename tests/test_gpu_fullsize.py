@@ -217,3 +217,50 @@ def test_serve_burst_jobs_against_oracle(potts, oracle_lib):
             for k, (gp, wp) in enumerate(zip(g["points"], pts)):
                 for key in ("e", "C", "V_L", "m", "chi"):
                     assert gp[key] == pytest.approx(wp[key], rel=1e-12, abs=1e-300), (i, k, key)
+
+
+def test_end_to_end_run_equals_each_sample_alone(potts, oracle_lib):
+    """The paper's end-to-end run as the benchmark runs it (q = 9, L = 1024,
+    three samples concurrently on their own streams, T = 0.71 .. 0.73 in steps
+    of 0.002, 2000 + 8000 sweeps per point, heating from the ordered start):
+    every sample's per-point statistics equal those of the same ramp run alone;
+    the same protocol, shortened to 20 + 30 sweeps on the first three points,
+    equals the oracle's."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle.stats import derived
+
+    L, q, samples = 1024, 9, 3
+    betas = [1.0 / (0.71 + 0.002 * k) for k in range(11)]
+
+    def run(t_tran, t_max, npts):
+        lats = [potts.Lattice(L, q, s + 1, potts.ORDERED) for s in range(samples)]
+        for lat in lats:
+            lat.reserve_records(t_max + 2)
+        with ThreadPoolExecutor(max_workers=samples) as pool:
+            curves = list(pool.map(lambda lat: lat.ramp(betas[:npts], t_tran, t_max), lats))
+        spins = [lat.spins() for lat in lats]
+        for lat in lats:
+            lat.close()
+        return curves, spins
+
+    _say("end-to-end run: 3 samples x 11 points x 10000 sweeps")
+    curves, _ = run(2000, 8000, 11)
+    for s in range(samples):
+        with potts.Lattice(L, q, s + 1, potts.ORDERED) as lat:
+            want = lat.ramp(betas, 2000, 8000)
+        assert curves[s] == want, s
+    # shortened protocol against the oracle
+    t_tran, t_max, npts = 20, 30, 3
+    curves, spins = run(t_tran, t_max, npts)
+    for s in range(samples):
+        o = oracle_lib.init(L, q, s + 1, 0)
+        t = 0
+        for k in range(npts):
+            rec = oracle_lib.sweeps(o, q, s + 1, t, t_tran + t_max, oracle_lib.threshold_table(betas[k]))
+            t += t_tran + t_max
+            w = rec[t_tran:]
+            want = derived(w[:, 0].tolist(), w[:, 1:].max(axis=1).tolist(), L * L, q, betas[k])
+            for key in ("e", "C", "V_L", "m", "chi"):
+                assert curves[s][k][key] == pytest.approx(want[key], rel=1e-12, abs=1e-300), (s, k, key)
+        assert np.array_equal(spins[s], o), s
