@@ -165,6 +165,15 @@ int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_g
  * depend on it.  Errors: EINVAL (s NULL, waves_per_simd not 0 or 8). */
 int potts_tune_occupancy(potts_state *s, int32_t waves_per_simd);
 
+/* Graph replay of colour-split sweeps: with sweeps > 0, a sweep call of at
+ * least that many sweeps captures the launches of `sweeps` sweeps once into
+ * a hipGraph (kept while the launch shape and table form stay the same) and
+ * replays it, the remainder launched directly; 0 (the default) launches every
+ * sweep directly.  Needs a stream that can be captured (not the legacy NULL
+ * stream).  Results never depend on it.  Errors: EINVAL (sweeps outside
+ * 0 .. 4096). */
+int potts_tune_graph(potts_state *s, int32_t sweeps);
+
 /* The table potts_sweep uses for beta: thr[d-1] = min(floor(exp(-beta d)
  * 2^32), 2^32-1), computed on the host in FP64.  Errors: EINVAL. */
 int potts_threshold_table(double beta, uint32_t thr[4]);

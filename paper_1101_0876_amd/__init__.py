@@ -111,6 +111,10 @@ class Lattice:
         """Colour-split kernel occupancy: 0 (compiler's choice) or 8 waves per SIMD."""
         check(self._lib.potts_tune_occupancy(self._h, int(waves_per_simd)))
 
+    def tune_graph(self, sweeps: int) -> None:
+        """Replay colour-split sweeps from a captured graph of `sweeps` sweeps (0: off)."""
+        check(self._lib.potts_tune_graph(self._h, int(sweeps)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts_time(self._h))

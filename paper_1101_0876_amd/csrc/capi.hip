@@ -46,6 +46,17 @@ struct potts_state {
   potts::HbTable *hb_host = nullptr;
   uint32_t hb_thr[4] = {0, 0, 0, 0};
   bool hb_valid = false, hb_wide = false;
+  // graph replay of colour-split sweeps: graph_sweeps sweeps per captured
+  // graph (0 = off); the graph's kernels read g_desc, written once per call
+  int32_t graph_sweeps = 0;
+  potts::StripParams *g_desc = nullptr;  // device, one descriptor
+  potts::StripTile *g_tiles = nullptr;   // device, the lattice's tiles
+  size_t g_ntiles = 0;
+  hipGraph_t g_graph = nullptr;
+  hipGraphExec_t g_exec = nullptr;
+  uint32_t g_rows = 0, g_wpe = 0;        // what the graph was captured for
+  int32_t g_K = 0;
+  bool g_wide = false;
 };
 
 namespace {
@@ -112,6 +123,10 @@ void release(potts_state *s) {
   if (s->scratch) (void)hipFree(s->scratch);
   if (s->stripes) (void)hipFree(s->stripes);
   if (s->stats_out) (void)hipFree(s->stats_out);
+  if (s->g_exec) (void)hipGraphExecDestroy(s->g_exec);
+  if (s->g_graph) (void)hipGraphDestroy(s->g_graph);
+  if (s->g_desc) (void)hipFree(s->g_desc);
+  if (s->g_tiles) (void)hipFree(s->g_tiles);
   if (s->hb_dev) (void)hipFree(s->hb_dev);
   if (s->hb_host) (void)hipHostFree(s->hb_host);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -355,6 +370,69 @@ uint32_t packed_rows(const potts_state *s) {
   return L <= 4096 ? 2 : 4;
 }
 
+void drop_graph(potts_state *s) {
+  if (s->g_exec) (void)hipGraphExecDestroy(s->g_exec);
+  if (s->g_graph) (void)hipGraphDestroy(s->g_graph);
+  s->g_exec = nullptr;
+  s->g_graph = nullptr;
+}
+
+// Captures K colour-split sweeps of the lattice (tiled launches reading the
+// device descriptor g_desc, then the fold-and-advance node) into a graph.
+int capture_graph(potts_state *s, const potts::StripParams &p, int32_t K, bool wide) {
+  drop_graph(s);
+  const size_t ntiles = (p.nitems + 255) / 256;
+  if (!s->g_desc && hipMalloc(&s->g_desc, sizeof(potts::StripParams)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(POTTS_ENOMEM, "allocation of the graph descriptor failed");
+  }
+  if (ntiles > s->g_ntiles) {
+    if (s->g_tiles) (void)hipFree(s->g_tiles);
+    s->g_tiles = nullptr;
+    s->g_ntiles = 0;
+    if (hipMalloc(&s->g_tiles, ntiles * sizeof(potts::StripTile)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the graph tiles failed");
+    }
+    s->g_ntiles = ntiles;
+  }
+  std::vector<potts::StripTile> tiles;
+  for (uint32_t first = 0; first < p.nitems; first += 256)
+    tiles.push_back(potts::StripTile{0, first, std::min<uint32_t>(256, p.nitems - first), first == 0 ? 1u : 0u});
+  HIP_TRY(hipMemcpyAsync(s->g_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));  // the host tiles go away next
+  HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  potts::StripLaunch l{};
+  l.jobs = s->g_desc;
+  l.tiles = s->g_tiles;
+  potts::TileShape shape;
+  shape.wpe = s->wpe;
+  if (!potts::shape_ok(shape, p.q)) shape.wpe = 0;
+  hipError_t e = hipSuccess;
+  for (int32_t j = 0; j < K && e == hipSuccess; ++j) {
+    l.sweep = (uint32_t)j;
+    e = potts::launch_packed_tiled(l, 0, (unsigned)tiles.size(), shape, p.q, wide, s->stream);
+    if (e == hipSuccess) e = potts::launch_packed_tiled(l, 1, (unsigned)tiles.size(), shape, p.q, wide, s->stream);
+  }
+  if (e == hipSuccess) e = potts::launch_fold_advance(s->g_desc, (uint32_t)K, s->stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(s->stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&s->g_exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    s->g_exec = nullptr;
+    return hip_fail(e, "capture of the sweep graph");
+  }
+  s->g_graph = g;
+  s->g_rows = p.rows;
+  s->g_K = K;
+  s->g_wide = wide;
+  s->g_wpe = s->wpe;
+  return POTTS_OK;
+}
+
 // Sweeps on the colour-split copy in the second buffer (packed.hip): pack,
 // sweep, unpack; records as the strip path (striped partial records).
 int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
@@ -377,8 +455,23 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
   const unsigned grid = (unsigned)(need < groups ? need : groups);
   const bool wide = wide_table(thr);
+  // whole graphs of graph_sweeps sweeps first (one workgroup per tile, as the
+  // grid-stride launch when the item count fits the grid), the rest direct
+  int64_t done = 0;
+  const int32_t K = s->graph_sweeps;
+  if (K > 0 && nsweeps >= K && need <= groups) {
+    if (!s->g_exec || s->g_K != K || s->g_rows != rows || s->g_wide != wide || s->g_wpe != s->wpe) {
+      const int rc = capture_graph(s, p, K, wide);
+      if (rc) return rc;
+    }
+    potts::StripParams d = p;
+    d.t0 = (uint64_t)s->t;
+    d.nsweeps = (uint64_t)K;
+    HIP_TRY(potts::launch_set_desc(s->g_desc, d, s->stream));
+    for (; done + K <= nsweeps; done += K) HIP_TRY(hipGraphLaunch(s->g_exec, s->stream));
+  }
   const int64_t seg = 1ll << 30;
-  for (int64_t base = 0; base < nsweeps; base += seg) {
+  for (int64_t base = done; base < nsweeps; base += seg) {
     const int64_t count = std::min<int64_t>(seg, nsweeps - base);
     p.t0 = (uint64_t)(s->t + base);
     p.nsweeps = (uint64_t)count;
@@ -687,6 +780,13 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
   const uint64_t need = ((uint64_t)p.nitems + 255) / 256;
   const unsigned grid = (unsigned)(need < 8192 ? need : 8192);
   HIP_TRY(potts::launch_strip(l, colour, grid, p.q, wide_table(thr), static_cast<hipStream_t>(hip_stream)));
+  return POTTS_OK;
+}
+
+int potts_tune_graph(potts_state *s, int32_t sweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (sweeps < 0 || sweeps > 4096) return fail(POTTS_EINVAL, "sweeps per graph must be 0 .. 4096");
+  s->graph_sweeps = sweeps;
   return POTTS_OK;
 }
 

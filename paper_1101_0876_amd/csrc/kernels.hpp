@@ -199,6 +199,10 @@ hipError_t launch_strip(const StripLaunch &l, int colour, unsigned grid, uint32_
 hipError_t launch_packed(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,
                          hipStream_t stream);
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream);
+// graph replay of a single lattice: write the device descriptor *d = p; fold
+// the stripes of sweep d->t0 + sweeps - 1 and advance d->t0 by sweeps
+hipError_t launch_set_desc(StripParams *d, const StripParams &p, hipStream_t stream);
+hipError_t launch_fold_advance(StripParams *d, uint32_t sweeps, hipStream_t stream);
 // a single lattice's colour-split launch (grid-stride) asking for at least
 // wpe waves per SIMD (0: the compiler's choice; 8 exists for q <= 16)
 hipError_t launch_packed_single(const StripLaunch &l, int colour, unsigned grid, uint32_t qmax, bool wide,

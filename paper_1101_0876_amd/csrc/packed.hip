@@ -203,6 +203,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(8))) void
   packed_body<COLOUR, CMP, PRIV, WIDE, TILED, BLOCK>(launch);
 }
 
+// Graph replay of a single lattice's sweeps (capi.hip): the captured launches
+// read the lattice's descriptor from device memory; set_desc_kernel writes it
+// before the first replay of a call, and fold_advance_kernel, the last node of
+// the graph, folds the partial records of the graph's last sweep into their
+// ring slot and moves the descriptor's first sweep on by the graph's length.
+__global__ void set_desc_kernel(StripParams *d, StripParams p) {
+  if (threadIdx.x == 0) *d = p;
+}
+
+__global__ __launch_bounds__(kBlock) void fold_advance_kernel(StripParams *d, uint32_t sweeps) {
+  __shared__ unsigned long long acc[257];
+  const StripParams p = *d;
+  fold_stripes<kBlock>(p, p.t0 + sweeps - 1, acc);
+  __syncthreads();  // every thread has read the descriptor
+  if (threadIdx.x == 0) d->t0 = p.t0 + sweeps;
+}
+
 // Row-major lattice <-> two colour planes; one thread per 32 bytes of a row
 // (16 sites of each colour).
 __global__ __launch_bounds__(kBlock) void pack_kernel(const uint8_t *src, uint8_t *dst, uint32_t L) {
@@ -319,6 +336,16 @@ hipError_t launch_packed_tiled(const StripLaunch &l, int colour, unsigned ntiles
   if (shape.block == 256 && shape.wpe == 0) return launch_c<true>(l, colour, ntiles, qmax, wide, stream);
   if (colour == 0) return wide ? launch_shape<0, true>(l, ntiles, shape, stream) : launch_shape<0, false>(l, ntiles, shape, stream);
   return wide ? launch_shape<1, true>(l, ntiles, shape, stream) : launch_shape<1, false>(l, ntiles, shape, stream);
+}
+
+hipError_t launch_set_desc(StripParams *d, const StripParams &p, hipStream_t stream) {
+  hipLaunchKernelGGL(set_desc_kernel, dim3(1), dim3(64), 0, stream, d, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_advance(StripParams *d, uint32_t sweeps, hipStream_t stream) {
+  hipLaunchKernelGGL(fold_advance_kernel, dim3(1), dim3(kBlock), 0, stream, d, sweeps);
+  return hipGetLastError();
 }
 
 hipError_t launch_pack(const uint8_t *row_major, uint8_t *packed, uint32_t L, hipStream_t stream) {

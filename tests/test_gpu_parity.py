@@ -454,6 +454,37 @@ def test_occupancy_does_not_change_results(potts, oracle_lib, L, q, start):
             lat.tune_occupancy(4)
 
 
+@pytest.mark.parametrize("L,q,K", [(512, 6, 8), (1056, 40, 4), (96, 9, 3)])
+def test_graph_replay_does_not_change_results(potts, oracle_lib, L, q, K):
+    """Colour-split sweeps replayed from a captured graph of K sweeps (whole
+    graphs first, the remainder launched directly), across calls, a change
+    of beta and of occupancy, with a ring shorter than the run."""
+    seed = 17
+    betas = [beta_c(q), 0.95 * beta_c(q), beta_c(q)]
+    calls = [2 * K + 3, 2 * K, K - 1]
+    s = oracle_lib.init(L, q, seed, 1)
+    t, recs = 0, []
+    for b, n in zip(betas, calls):
+        recs.append(oracle_lib.sweeps(s, q, seed, t, n, oracle_lib.threshold_table(b)))
+        t += n
+    want = np.concatenate(recs)
+    import torch
+
+    stream = torch.cuda.Stream()  # a stream that can be captured
+    with potts.Lattice.from_torch(L, q, seed, 1, stream=stream, records_capacity=64) as lat:
+        lat.tune_graph(K)
+        for i, (b, n) in enumerate(zip(betas, calls)):
+            if i == 2 and q <= 16:
+                lat.tune_occupancy(8)
+            lat.sweep(b, n)
+        assert lat.t == t
+        assert np.array_equal(lat.records(t - 40, 40), want[-40:])
+        assert np.array_equal(lat.spins(), s)
+    with potts.Lattice(20, 3, 1, 1) as lat:
+        with pytest.raises(potts.PottsError):
+            lat.tune_graph(-1)
+
+
 def test_tune_rejects_bad_shapes(potts):
     with potts.Lattice(20, 3, 1, 1) as lat:
         with pytest.raises(potts.PottsError):
