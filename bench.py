@@ -235,31 +235,46 @@ def run_batch(args):
     import paper_1101_0876_amd as potts
     from paper_1101_0876_amd.workloads import batch_jobs
 
-    jobs = batch_jobs(n=args.batch_jobs, sweeps=args.steps)
+    import tempfile
+
+    sweeps = args.steps if args.steps != 2000 else 500
+    jobs = batch_jobs(n=args.batch_jobs, sweeps=sweeps)
     torch.cuda.set_device(0)
     site_updates = sum(j["L"] ** 2 * j["nsweeps"] for j in jobs)
     # warm-up: a small batch touches every kernel variant used below
     with potts.Batch(jobs[:16], graph=True, tune=False) as w:
         w.run()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with potts.Batch(jobs, graph=True, tune=True) as b:
-        t_create = time.perf_counter()
-        dev_ms = b.run()
-        t_run = time.perf_counter()
-        tuning = b.tuning()
-        res = b.results()
-    wall = t_run - t_create
-    assert all(r["t"] == j["nsweeps"] for r, j in zip(res, jobs))
+    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(), "tune.json")
+
+    def one(tune, tune_cache):
+        t0 = time.perf_counter()
+        with potts.Batch(jobs, graph=True, tune=tune, tune_cache=tune_cache) as b:
+            t_create = time.perf_counter()
+            dev_ms = b.run()
+            t_run = time.perf_counter()
+            tuning = b.tuning()
+            res = b.results()
+        assert all(r["t"] == j["nsweeps"] for r, j in zip(res, jobs))
+        return t_run - t_create, dev_ms, t_create - t0, tuning
+
+    # untuned shapes, then the in-run tuner (writing the cache), then the cached shapes
+    wall_plain_shape, _, _, _ = one(False, None)
+    wall_tuning, _, _, _ = one(True, cache)
+    wall, dev_ms, setup_s, tuning = one(False, cache)
+    t0, t_create = 0.0, setup_s
     out = {
         "metric": "jobs/s", "value": len(jobs) / wall, "unit": "jobs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 0, "ms_per_step": wall * 1e3 / args.steps,
+        "steps": sweeps, "warmup": 0, "ms_per_step": wall * 1e3 / sweeps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "batched replicas", "jobs": len(jobs), "L": "2^U{7..12}", "q": "U{3..12}",
-                   "beta": "beta_c(q) U[0.98,1.02]", "sweeps": args.steps, "list_seed": 1101},
+                   "beta": "beta_c(q) U[0.98,1.02]", "sweeps": sweeps, "list_seed": 1101,
+                   "launch_shapes": "tuned (from the cache a tuning run wrote)"},
         "ns_per_spin_flip": wall * 1e9 / site_updates,
         "device_ms": dev_ms, "setup_s": t_create - t0, "tuning": tuning,
+        "untuned_jobs_per_s": len(jobs) / wall_plain_shape,
+        "tuning_run_jobs_per_s": len(jobs) / wall_tuning,
     }
     if not args.no_plain:
         # the plain loop: one lattice at a time, single-lattice path, same stream order
@@ -289,13 +304,19 @@ def run_serve(args):
     torch.cuda.set_device(0)
     jobs = serve_jobs(n=args.serve_jobs, rate=args.serve_rate, sweep_scale=args.serve_scale)
     site_updates = sum(j["L"] ** 2 * sum(j["sweeps"]) for j in jobs)
-    with potts.Server(quantum=args.serve_quantum) as warm:  # loads every kernel variant once
-        t = warm.submit(512, 6, 1, 1, [1.0, 1.2], [4, 4])
-        t2 = warm.submit(256, 15, 1, 0, [1.0], [4])
+    import tempfile
+
+    cache = args.tune_cache or os.path.join(tempfile.mkdtemp(), "serve_tune.json")
+    # warm-up, outside the timed burst: loads every kernel variant once, and a
+    # tuning server times the launch shapes of every lattice size of the
+    # workload (one tiny job each) into the cache the timed server reads
+    with potts.Server(quantum=args.serve_quantum, tune=True, tune_cache=cache) as warm:
+        ts = [warm.submit(L, 6, 1, 1, [1.0, 1.2], [2, 2]) for L in (256, 512, 1024, 2048, 4096, 8192)]
+        ts.append(warm.submit(256, 15, 1, 0, [1.0], [4]))
         warm.drain()
-        warm.collect(t)
-        warm.collect(t2)
-    with potts.Server(quantum=args.serve_quantum, max_slots=args.serve_slots) as srv:
+        for t in ts:
+            warm.collect(t)
+    with potts.Server(quantum=args.serve_quantum, max_slots=args.serve_slots, tune_cache=cache) as srv:
         start = time.perf_counter()
         tickets = []
         for j in jobs:
@@ -306,6 +327,7 @@ def run_serve(args):
         srv.drain()
         got = [srv.collect(t) for t in tickets]
         iterations = srv.iterations()
+        tuning = srv.tuning()
     lat = np.array([g["t_done"] - g["t_submit"] for g in got])
     span = max(g["t_done"] for g in got) - min(g["t_submit"] for g in got)
     assert all(g["status"] == 0 for g in got)
@@ -321,6 +343,7 @@ def run_serve(args):
                       "max": float(lat.max())},
         "ns_per_spin_flip": span * 1e9 / site_updates,
         "span_s": span,
+        "tuning": tuning,
     }
 
 
@@ -798,6 +821,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--occupancy", type=int, default=0, choices=[0, 8],
                     help="large: colour-split kernel waves per SIMD (0: the compiler's choice)")
+    ap.add_argument("--tune-cache", default=None, help="batch/serve: launch-shape cache file (default: a fresh one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
