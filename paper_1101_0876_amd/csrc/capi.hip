@@ -498,8 +498,10 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
-  if (!use_packed(s)) {
-    // every other kernel sweeps the row-major lattice
+  if (use_resident(s) || !use_packed(s)) {
+    // every other kernel sweeps the row-major lattice (the LDS-resident one
+    // too, although the lattice may have a colour-split copy from heat-bath
+    // sweeps)
     const int rc = sync_spins(s);
     if (rc) return rc;
     s->planes_valid = false;

@@ -352,7 +352,7 @@ bool tune_size(potts_server *s, uint32_t L, uint32_t q, int qc, std::string &err
       s->cache.rows[rkey] = rows;
       s->cache.dirty = true;
       std::lock_guard<std::mutex> lk(s->mu);
-      s->tuned += "L=" + std::to_string(L) + ":rows=" + std::to_string(rows) + " ";
+      s->tuned += rkey + ":rows=" + std::to_string(rows) + " ";
     }
   }
   if (ok && need_shape) {
@@ -370,7 +370,7 @@ bool tune_size(potts_server *s, uint32_t L, uint32_t q, int qc, std::string &err
       s->cache.shapes[skey] = best;
       s->cache.dirty = true;
       std::lock_guard<std::mutex> lk(s->mu);
-      s->tuned += "strip/q16:" + shape_text(best) + " ";
+      s->tuned += skey + ":" + shape_text(best) + " ";
     }
   }
   (void)hipStreamSynchronize(s->stream);
@@ -958,11 +958,16 @@ int64_t potts_server_iterations(const potts_server *s) { return s ? s->iteration
 int potts_server_tuning(potts_server *s, char *out, int32_t cap) {
   if (!s || !out || cap < 1) return record_error(POTTS_EINVAL, "NULL argument or cap < 1");
   std::lock_guard<std::mutex> lk(s->mu);
+  // entries are "<cache key>:<choice>"; those this server did not time
+  // itself come from its cache file
   std::string text = s->tuned;
+  const auto timed_here = [&](const std::string &key) {
+    return (" " + s->tuned).find(" " + key + ":") != std::string::npos;
+  };
   for (const auto &kv : s->cache.rows)
-    if (text.find(kv.first) == std::string::npos) text += kv.first + ":rows=" + std::to_string(kv.second) + "(cached) ";
+    if (!timed_here(kv.first)) text += kv.first + ":rows=" + std::to_string(kv.second) + "(cached) ";
   for (const auto &kv : s->cache.shapes)
-    if (text.find(kv.first) == std::string::npos) text += kv.first + ":" + shape_text(kv.second) + "(cached) ";
+    if (!timed_here(kv.first)) text += kv.first + ":" + shape_text(kv.second) + "(cached) ";
   const size_t n = std::min<size_t>(text.size(), (size_t)cap - 1);
   memcpy(out, text.data(), n);
   out[n] = 0;

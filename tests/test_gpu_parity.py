@@ -478,7 +478,8 @@ def test_graph_replay_does_not_change_results(potts, oracle_lib, L, q, K):
                 lat.tune_occupancy(8)
             lat.sweep(b, n)
         assert lat.t == t
-        assert np.array_equal(lat.records(t - 40, 40), want[-40:])
+        n = min(t, 40)  # the last records the 64-slot ring still holds
+        assert np.array_equal(lat.records(t - n, n), want[-n:])
         assert np.array_equal(lat.spins(), s)
     with potts.Lattice(20, 3, 1, 1) as lat:
         with pytest.raises(potts.PottsError):
