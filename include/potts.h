@@ -443,8 +443,10 @@ int potts_server_collect(potts_server *srv, int64_t ticket, potts_served *info, 
  * faults): the job with this ticket, queued or running, ends with status
  * EDEVICE at the first iteration boundary from which its next iteration would
  * run sweep at_sweep (a 0-based sweep index of the job); its device memory is
- * released and the other jobs go on.  Errors: EINVAL (NULL, at_sweep < 0),
- * ERANGE (no such unfinished job). */
+ * released and the other jobs go on.  Ticket 0 names the next job this
+ * server accepts: the failure is attached when the job is submitted, before
+ * it can run (a later call with ticket 0 replaces an unclaimed one).
+ * Errors: EINVAL (NULL, at_sweep < 0), ERANGE (no such unfinished job). */
 int potts_server_inject_fault(potts_server *srv, int64_t ticket, int64_t at_sweep);
 
 /* Waits until every submitted job has finished (timeout_ms < 0: no limit).

@@ -474,7 +474,8 @@ class Server:
 
     def inject_fault(self, ticket: int, at_sweep: int) -> None:
         """Makes the job fail (status EDEVICE) before it runs sweep at_sweep
-        (host-side failure injection for recovery tests)."""
+        (host-side failure injection for recovery tests); ticket 0: the next
+        job submitted, attached at its submission."""
         check(self._lib.potts_server_inject_fault(self._h, int(ticket), int(at_sweep)))
 
     def collect(self, ticket: int, spins: bool = False) -> dict:

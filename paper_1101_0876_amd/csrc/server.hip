@@ -121,6 +121,7 @@ struct potts_server {
   int64_t next_ticket = 1;
   int64_t submitted = 0, finished = 0;
   std::map<int64_t, int64_t> faults;  // ticket -> sweep, for injected failures
+  int64_t fault_next = -1;            // injected failure of the next accepted job (-1 = none)
   std::set<int64_t> running;          // tickets of admitted, unfinished jobs
   // owned by the server thread
   std::vector<std::unique_ptr<Job>> active;
@@ -883,6 +884,10 @@ int potts_server_submit(potts_server *s, const potts_request *req, int64_t *tick
   if (j->bytes > (size_t)s->cfg.hbm_budget) return record_error(POTTS_ENOMEM, "job exceeds the HBM budget");
   j->ticket = s->next_ticket++;
   j->info.ticket = j->ticket;
+  if (s->fault_next >= 0) {
+    j->fault_at = s->fault_next;  // attached before the server thread can see the job
+    s->fault_next = -1;
+  }
   j->info.t_submit = seconds_since(s);
   *ticket = j->ticket;
   s->queue.push_back(std::move(j));
@@ -930,6 +935,10 @@ int potts_server_collect(potts_server *s, int64_t ticket, potts_served *info, po
 int potts_server_inject_fault(potts_server *s, int64_t ticket, int64_t at_sweep) {
   if (!s || at_sweep < 0) return record_error(POTTS_EINVAL, "need a server and at_sweep >= 0");
   std::lock_guard<std::mutex> lk(s->mu);
+  if (ticket == 0) {
+    s->fault_next = at_sweep;
+    return POTTS_OK;
+  }
   for (auto &jp : s->queue)
     if (jp->ticket == ticket) {
       jp->fault_at = at_sweep;

@@ -138,8 +138,8 @@ def test_served_job_resumes_after_a_failure(potts, oracle_lib, tmp_path, L, q, f
         return srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"], keep_spins=True, **kw)
 
     with potts.Server(quantum=8, max_slots=16) as srv:
+        srv.inject_fault(0, fault_at)  # attached at submission: the job cannot finish first
         bad = submit(srv, job, checkpoint=ck)
-        srv.inject_fault(bad, fault_at)
         t_others = [submit(srv, j) for j in others]
         srv.drain(120000)
         failed = srv.collect(bad, spins=True)
