@@ -217,6 +217,32 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
 int potts_slab_records(const int64_t *dev_rings, int32_t nslabs, int64_t ring_slots, int32_t q, int64_t t0,
                        int64_t n, int64_t *dev_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the sweeps of
+ * potts_sweep_thr on the row-major strip kernel, with no state and no
+ * allocation.  Bit for bit the sweeps and records potts_sweep_thr gives a
+ * state of the same (L, q, seed) whose t is t0 and whose lattice is dev_spins.
+ *   dev_spins: device, L*L bytes, row-major, values 0..q-1; sweeps t0 ..
+ *     t0+nsweeps-1 update it in place (caller-owned).
+ *   thr: host, the threshold table (potts_threshold_table), passed by value
+ *     to the kernels.
+ *   dev_records: device, nsweeps * (1+q) int64 (caller-owned): record r =
+ *     {e_sat, hist[0..q)} of sweep t0 + r.
+ *   hip_stream: hipStream_t of the current device (NULL = default stream);
+ *     asynchronous, nothing is synchronized.
+ * The strip kernel's partial records live in a static device array of
+ * 2 x 32 x 272 int64 (139,264 bytes), one per GPU, held until the process
+ * ends; every call on a GPU uses it, so calls that overlap on one GPU (on
+ * different streams or threads) race and must be ordered by the caller.
+ * Each call clears the partial records first.  Calls no hipMalloc, hipFree
+ * or allocating library routine and records no memset.
+ * Needs L % 16 == 0, 16 <= L <= 65520, 2 <= q <= 256, t0 >= 0.  Errors:
+ * EINVAL (NULL, bad shape, negative counts, a stream of another device),
+ * ERANGE (t0 + nsweeps overflows, or partial records beyond the static
+ * array), EDEVICE. */
+int potts_sweep_static(uint8_t *dev_spins, int32_t L, int32_t q, uint64_t seed, int64_t t0,
+                       const uint32_t thr[4], int64_t nsweeps, int64_t *dev_records, void *hip_stream);
+
 /* Observables of the current configuration (synchronizes the stream).  Uses
  * the last sweep's record, or measures the lattice if no sweep has run. */
 int potts_observables(potts_state *s, potts_obs *out);

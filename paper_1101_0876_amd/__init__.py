@@ -19,8 +19,19 @@ from ._native import (PottsBatchOpts, PottsError, PottsJob, PottsJobResult, Pott
 ORDERED = 0
 RANDOM = 1
 
-__all__ = ["Lattice", "Cube", "NnnLattice", "Batch", "Server", "Slabs", "slab_half_sweep", "PottsError", "threshold_table",
+__all__ = ["Lattice", "Cube", "NnnLattice", "Batch", "Server", "Slabs", "slab_half_sweep", "sweep_static", "PottsError", "threshold_table",
            "threshold_table6", "nnn_table", "ORDERED", "RANDOM", "load"]
+
+
+def sweep_static(spins_ptr: int, L: int, q: int, seed: int, t0: int, thr, nsweeps: int, records_ptr: int,
+                 stream_ptr: int = 0) -> None:
+    """potts_sweep_static on device pointers (argument marshalling only): the
+    allocation-free sweeps of a caller-owned row-major lattice, records of
+    sweeps t0 .. t0+nsweeps-1 into the caller's nsweeps x (1+q) int64 buffer."""
+    th = np.ascontiguousarray(thr, dtype=np.uint32)
+    check(load().potts_sweep_static(ctypes.c_void_p(spins_ptr), int(L), int(q), int(seed), int(t0),
+                                    th.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), int(nsweeps),
+                                    ctypes.c_void_p(records_ptr), ctypes.c_void_p(stream_ptr)))
 
 
 def threshold_table(beta: float) -> np.ndarray:

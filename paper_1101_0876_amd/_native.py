@@ -151,6 +151,8 @@ SIGNATURES = [
                                              ctypes.c_int64, _VP]),
     ("potts_slab_records", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
                                           ctypes.c_int64, _VP, _VP]),
+    ("potts_sweep_static", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64,
+                                          _U32P, ctypes.c_int64, _VP, _VP]),
     ("potts_observables", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
     ("potts_measure", ctypes.c_int, [_VP, ctypes.POINTER(PottsObs)]),
     ("potts_records", ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, _I64P]),
