@@ -68,3 +68,16 @@ def test_table2_order_parameter_jump(row):
     # wherever the fifth term is visible at six places
     four = 1.0 - sum(3 ** (k - 1) * float(q) ** -k for k in range(1, 5))
     assert _truncated(four, dm) == (81 * float(q) ** -5 < 1e-6)
+
+
+@pytest.mark.parametrize("row", _rows("table2calc"))
+def test_table2_calculated_columns_transcribed(row):
+    """Table 2's calculated values (as transcribed) lie within two printed
+    errors of the exact columns of the same table: a mistyped digit fails."""
+    q = int(row[0])
+    c_eo, err_eo, c_ed, err_ed, c_dm, err_dm = (float(x) for x in row[1:7])
+    exact = {int(r[0]): (float(r[1]), float(r[2])) for r in _rows("table2")}[q]
+    dm = {int(r[0]): float(r[1]) for r in _rows("table2dm")}[q]
+    assert abs(c_eo - exact[0]) <= 2 * err_eo
+    assert abs(c_ed - exact[1]) <= 2 * err_ed
+    assert abs(c_dm - dm) <= 2 * err_dm
