@@ -324,7 +324,16 @@ def run_serve(args):
             if delay > 0:
                 time.sleep(delay)
             tickets.append(srv.submit(j["L"], j["q"], j["seed"], j["start"], j["betas"], j["sweeps"]))
-        srv.drain()
+        # drain in slices, with a progress line on stderr (long bursts at full sweep counts)
+        while True:
+            try:
+                srv.drain(30000)
+                break
+            except potts.PottsError as exc:
+                if exc.code != -4:  # anything but the slice's time-out
+                    raise
+                print(f"serve: {time.perf_counter() - start:.0f} s, {srv.iterations()} iterations",
+                      file=sys.stderr, flush=True)
         got = [srv.collect(t) for t in tickets]
         iterations = srv.iterations()
         tuning = srv.tuning()
