@@ -153,11 +153,27 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * lattice in LDS and runs all sweeps of a call in one launch), 4 = the
  * colour-split kernel (L % 32 == 0, L <= 65520: a call copies the lattice into
  * two colour planes in the second buffer, sweeps there and copies it back;
- * the automatic choice for such L above 256);
+ * the automatic choice for such L above 2048), 5 = the multi-sweep tile kernel
+ * (L % 16 == 0, L <= 65520; the automatic choice for 256 < L <= 2048: each
+ * launch runs several sweeps, one LDS tile
+ * per workgroup whose halo is recomputed, and moves the row-major lattice
+ * between the state's two buffers; with library-owned buffers they trade
+ * roles, so potts_device_spins may return the other one afterwards; shape
+ * from potts_tune_tiles);
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
  * L); max_groups: persistent grid size in workgroups (0 = automatic).
  * Errors: EINVAL. */
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups);
+
+/* Shape of the multi-sweep tile kernel (kernel 5): tiles of tx bytes (a
+ * multiple of 16 dividing L) by ty rows (even, dividing L), `sweeps` sweeps
+ * per launch (1..8; the tile reads 2 x sweeps halo rows above and below and
+ * 16 halo bytes left and right, and one tile with its halo must fit in
+ * 44 KiB of LDS); 0 for any of them = automatic (tx: the largest of 256 ..
+ * 16 up to L/8 dividing L, ty: 16 rows up to L = 1024 and 32 above, or the
+ * largest even divisor below, 4 sweeps).  Results never depend on it.
+ * Errors: EINVAL (a shape the lattice cannot take; the old one is kept). */
+int potts_tune_tiles(potts_state *s, int32_t tx, int32_t ty, int32_t sweeps);
 
 /* Occupancy of the colour-split kernel: 0 = the compiler's register budget
  * (the default), 8 = at most 64 VGPRs so that 8 waves fit on each SIMD (the

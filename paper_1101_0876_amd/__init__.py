@@ -122,6 +122,11 @@ class Lattice:
         """Colour-split kernel occupancy: 0 (compiler's choice) or 8 waves per SIMD."""
         check(self._lib.potts_tune_occupancy(self._h, int(waves_per_simd)))
 
+    def tune_tiles(self, tx: int = 0, ty: int = 0, sweeps: int = 0) -> None:
+        """Multi-sweep tile kernel (kernel 5) shape: tx x ty tiles, sweeps per
+        launch (0 = automatic); results are identical for every shape."""
+        check(self._lib.potts_tune_tiles(self._h, int(tx), int(ty), int(sweeps)))
+
     def tune_graph(self, sweeps: int) -> None:
         """Replay colour-split sweeps from a captured graph of `sweeps` sweeps (0: off)."""
         check(self._lib.potts_tune_graph(self._h, int(sweeps)))

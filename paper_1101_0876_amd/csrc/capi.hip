@@ -57,6 +57,10 @@ struct potts_state {
   uint32_t g_rows = 0, g_wpe = 0;        // what the graph was captured for
   int32_t g_K = 0;
   bool g_wide = false;
+  // several sweeps per launch on LDS tiles (tiles.hip): the shape asked for
+  // (0 = automatic) and the partial records of a launch's sweeps
+  uint32_t tile_tx = 0, tile_ty = 0, tile_sweeps = 0;
+  unsigned long long *tstripes = nullptr;
 };
 
 namespace {
@@ -128,6 +132,7 @@ void release(potts_state *s) {
   if (s->g_desc) (void)hipFree(s->g_desc);
   if (s->g_tiles) (void)hipFree(s->g_tiles);
   if (s->hb_dev) (void)hipFree(s->hb_dev);
+  if (s->tstripes) (void)hipFree(s->tstripes);
   if (s->hb_host) (void)hipHostFree(s->hb_host);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -248,9 +253,48 @@ bool use_resident(const potts_state *s) {
 // the colour-split copy needs 16-byte groups of packed bytes: L % 32 == 0
 bool packed_ok(const potts_state *s) { return strip_ok(s) && s->L % 32 == 0; }
 
-bool use_packed(const potts_state *s) { return packed_ok(s) && (s->kernel == 4 || s->kernel == 0); }
+bool auto_tiles(const potts_state *s);
+
+bool use_packed(const potts_state *s) {
+  return packed_ok(s) && (s->kernel == 4 || (s->kernel == 0 && !auto_tiles(s)));
+}
 
 bool use_strip(const potts_state *s) { return strip_ok(s) && (s->kernel == 1 || s->kernel == 0); }
+
+// The tile shape (interior tx bytes x ty rows, sweeps per launch) of the
+// multi-sweep tile kernel: the one asked for, else about 256-512 tiles per
+// lattice (tx the largest of 256 .. 16 bytes up to L/8 dividing L, ty 16 rows
+// up to L = 1024 and 32 above, or the largest even divisor below), 4 sweeps
+// per launch.  Measured on MI355X (q = 6, ps per site update): L = 512 64x16
+// 16.9 (128x16 21.6, 256x32 32.6), L = 1024 128x16 6.1 (64x16 6.4, 256x32
+// 8.3), L = 2048 256x32 2.67 (256x64 with 8 sweeps 3.05, 128x16 3.64).
+bool tile_shape(const potts_state *s, uint32_t *tx, uint32_t *ty, uint32_t *sweeps) {
+  const uint32_t L = (uint32_t)s->L;
+  *sweeps = s->tile_sweeps ? s->tile_sweeps : 4u;
+  *tx = s->tile_tx;
+  *ty = s->tile_ty;
+  for (uint32_t c = 256; !*tx && c >= 16; c /= 2)
+    if (L % c == 0 && (c * 8 <= L || c == 16)) *tx = c;
+  for (uint32_t c = L <= 1024 ? 16u : 32u; !*ty && c >= 2; c /= 2)
+    if (L % c == 0) *ty = c;
+  return *tx && *ty && potts::tile_shape_ok(L, *tx, *ty, 2u * *sweeps);
+}
+
+bool tiles_ok(const potts_state *s) {
+  uint32_t tx, ty, n;
+  return s->L % 16 == 0 && s->L <= 65520 && tile_shape(s, &tx, &ty, &n);
+}
+
+// the automatic choice for lattices too large for one workgroup's LDS and too
+// small for a half sweep to hide a kernel boundary: the colour-split kernel
+// runs L = 512 / 1024 / 2048 at 48.7 / 12.2 / 3.47 ps per site update, the
+// tiles at 16.9 / 6.1 / 2.67; from L = 4096 (1.64 against 1.86) the halo work
+// costs more than the launches it saves
+bool auto_tiles(const potts_state *s) { return s->L > 256 && s->L <= 2048 && tiles_ok(s); }
+
+bool use_tiles(const potts_state *s) {
+  return tiles_ok(s) && (s->kernel == 5 || (s->kernel == 0 && !use_resident(s) && auto_tiles(s)));
+}
 
 bool wide_table(const uint32_t thr[4]) { return !thr[0] || !thr[1] || !thr[2] || !thr[3]; }
 
@@ -493,6 +537,56 @@ int run_packed(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   return POTTS_OK;
 }
 
+// Sweeps on LDS tiles, several per launch (tiles.hip), ping-ponging the
+// row-major lattice between the state's two buffers; each launch's records
+// are folded into their ring slots right after it.
+int run_tiles(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  uint32_t tx, ty, per;
+  if (!tile_shape(s, &tx, &ty, &per)) return fail(POTTS_EINVAL, "no tile shape for this lattice");
+  const uint32_t sw = potts::stripe_words((uint32_t)s->q);
+  const uint64_t words = (uint64_t)potts::kTileMaxSweeps * kStripes * sw;
+  if (!s->tstripes) {
+    if (hipMalloc(&s->tstripes, words * sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the tile partial records failed");
+    }
+    HIP_TRY(potts::launch_fill_u64(s->tstripes, words, 0ull, s->stream));
+  }
+  s->planes_valid = false;  // the second buffer now holds row-major lattices
+  potts::TileParams p{};
+  p.L = (uint32_t)s->L;
+  p.q = (uint32_t)s->q;
+  p.k0 = (uint32_t)s->seed;
+  p.k1 = (uint32_t)(s->seed >> 32);
+  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+  p.tx = tx;
+  p.ty = ty;
+  p.halo = 2u * per;
+  p.tiles_x = p.L / tx;
+  p.stripes = s->tstripes;
+  p.nstripes = kStripes;
+  uint8_t *cur = s->spins, *other = s->spins2;
+  for (int64_t done = 0; done < nsweeps; done += per) {
+    p.nsweeps = (uint32_t)std::min<int64_t>(per, nsweeps - done);
+    p.t0 = (uint64_t)(s->t + done);
+    p.src = cur;
+    p.dst = other;
+    HIP_TRY(potts::launch_tiles(p, s->stream));
+    HIP_TRY(potts::launch_fold_sets(p, s->records, (uint64_t)s->rec_cap, s->stream));
+    std::swap(cur, other);
+  }
+  if (cur != s->spins) {
+    if (s->owns_spins) {
+      std::swap(s->spins, s->spins2);  // library-owned: the buffers trade roles
+    } else {
+      // the caller's buffer holds the lattice after every call
+      HIP_TRY(hipMemcpyAsync(s->spins, cur, (size_t)n_sites(s), hipMemcpyDeviceToDevice, s->stream));
+    }
+  }
+  s->t += nsweeps;
+  return POTTS_OK;
+}
+
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
@@ -507,6 +601,7 @@ int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
     s->planes_valid = false;
   }
   if (use_resident(s)) return run_resident(s, thr, nsweeps);
+  if (use_tiles(s)) return run_tiles(s, thr, nsweeps);
   const int64_t rl = s->q + 1;
   HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
   if (use_packed(s)) return run_packed(s, thr, nsweeps);
@@ -785,6 +880,24 @@ int potts_slab_half_sweep(uint8_t *dev_slab, int32_t L, int32_t h, int64_t y0, i
   return POTTS_OK;
 }
 
+int potts_tune_tiles(potts_state *s, int32_t tx, int32_t ty, int32_t sweeps) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (tx < 0 || ty < 0 || sweeps < 0 || sweeps > (int32_t)potts::kTileMaxSweeps)
+    return fail(POTTS_EINVAL, "tx, ty >= 0 and sweeps in 0 .. 8");
+  const uint32_t old_tx = s->tile_tx, old_ty = s->tile_ty, old_n = s->tile_sweeps;
+  s->tile_tx = (uint32_t)tx;
+  s->tile_ty = (uint32_t)ty;
+  s->tile_sweeps = (uint32_t)sweeps;
+  uint32_t a, b, c;
+  if ((tx || ty || sweeps) && !tile_shape(s, &a, &b, &c)) {
+    s->tile_tx = old_tx;
+    s->tile_ty = old_ty;
+    s->tile_sweeps = old_n;
+    return fail(POTTS_EINVAL, "tile shape: tx % 16 == 0 and ty even dividing L, LDS of one tile within 44 KiB");
+  }
+  return POTTS_OK;
+}
+
 int potts_tune_graph(potts_state *s, int32_t sweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (sweeps < 0 || sweeps > 4096) return fail(POTTS_EINVAL, "sweeps per graph must be 0 .. 4096");
@@ -815,7 +928,8 @@ int potts_slab_records(const int64_t *dev_rings, int32_t nslabs, int64_t ring_sl
 
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
-  if (kernel < 0 || kernel > 4) return fail(POTTS_EINVAL, "kernel must be 0 .. 4");
+  if (kernel < 0 || kernel > 5) return fail(POTTS_EINVAL, "kernel must be 0 .. 5");
+  if (kernel == 5 && !tiles_ok(s)) return fail(POTTS_EINVAL, "tile kernel needs L % 16 == 0 and a tile shape");
   if (kernel == 4 && !packed_ok(s))
     return fail(POTTS_EINVAL, "colour-split kernel needs L % 32 == 0 and L <= 65520");
   if (kernel == 1 && !strip_ok(s)) return fail(POTTS_EINVAL, "strip kernel needs L % 16 == 0 and L <= 65520");

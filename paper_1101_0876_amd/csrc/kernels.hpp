@@ -117,6 +117,37 @@ hipError_t launch_heatbath_packed(const HbLaunch &l, int colour, unsigned grid, 
 // populations are counted in lane-private LDS columns up to this many states
 constexpr uint32_t kPrivateHistMaxQ = 64;
 
+// Several sweeps per launch on LDS tiles with recomputed halos (tiles.hip):
+// one workgroup per tile of ty rows x tx bytes of a row-major L x L lattice,
+// read from src with halo rows above and below and 16 bytes left and right,
+// swept nsweeps <= halo / 2 times in LDS, interior written to dst (another
+// buffer).  The record of sweep t0 + s is added into partial-record set s
+// (nstripes stripes of stripe_words(q) words, set s at stripes + s x nstripes
+// x stripe_words(q)), which launch_fold_sets sums into ring slot t0 + s.
+constexpr uint32_t kTileMaxSweeps = 8;
+constexpr uint32_t kTileMaxHalo = 16;          // = the 16-byte column halo: 2 x 8 sweeps
+constexpr size_t kTileMaxLds = 44u * 1024u;    // dynamic LDS of one tile (static LDS up to 19 KB)
+
+struct TileParams {
+  const uint8_t *src;
+  uint8_t *dst;
+  uint32_t L, q;
+  uint32_t k0, k1;      // Philox key = seed
+  Thresholds thr;
+  uint64_t t0;          // sweep index of the launch's first sweep
+  uint32_t nsweeps;     // sweeps of this launch
+  uint32_t tx, ty;      // tile interior: tx bytes (multiple of 16) x ty rows (even)
+  uint32_t halo;        // rows above and below (even, >= 2 nsweeps)
+  uint32_t tiles_x;     // L / tx
+  unsigned long long *stripes;
+  uint32_t nstripes;    // a power of two
+};
+
+size_t tile_lds_bytes(uint32_t tx, uint32_t ty, uint32_t halo);
+bool tile_shape_ok(uint32_t L, uint32_t tx, uint32_t ty, uint32_t halo);
+hipError_t launch_tiles(const TileParams &p, hipStream_t stream);
+hipError_t launch_fold_sets(const TileParams &p, unsigned long long *ring, uint64_t cap, hipStream_t stream);
+
 // One lattice run entirely in LDS by one workgroup (resident.hip).
 struct ResidentJob {
   uint8_t *spins;                 // L*L bytes, updated in place

@@ -174,6 +174,7 @@ def test_colour_split_copy_stays_in_step(potts, oracle_lib):
         t += n
 
     with potts.Lattice.from_torch(L, q, seed, 1) as lat:
+        lat.tune(kernel=4)
         for n in (1, 1, 2):
             lat.sweep(beta, n)
             oracle_sweeps(n)
@@ -218,6 +219,7 @@ def test_caller_buffer_holds_the_lattice_between_calls(potts, oracle_lib):
     s = oracle_lib.init(L, q, seed, 1)
     stream = torch.cuda.Stream()
     with potts.Lattice.from_torch(L, q, seed, 1, stream=stream) as lat:
+        lat.tune(kernel=4)
         a, _, _ = lat._keep
         for n, t in ((3, 0), (1, 3)):
             lat.sweep(beta, n)
@@ -442,6 +444,8 @@ def test_occupancy_does_not_change_results(potts, oracle_lib, L, q, start):
     seed, beta, n = 31, beta_c(q), 5
     want_spins, want_rec = oracle_lib.run(L, q, seed, start, beta, n)
     with potts.Lattice(L, q, seed, start) as lat:
+        if L % 32 == 0:
+            lat.tune(kernel=4)
         lat.tune_occupancy(8)
         lat.sweep(beta, 3)
         lat.tune_occupancy(0)
@@ -472,6 +476,8 @@ def test_graph_replay_does_not_change_results(potts, oracle_lib, L, q, K):
 
     stream = torch.cuda.Stream()  # a stream that can be captured
     with potts.Lattice.from_torch(L, q, seed, 1, stream=stream, records_capacity=64) as lat:
+        if L % 32 == 0:
+            lat.tune(kernel=4)
         lat.tune_graph(K)
         for i, (b, n) in enumerate(zip(betas, calls)):
             if i == 2 and q <= 16:
