@@ -19,8 +19,9 @@
 //     values;
 //   * past them (r >= S, the neighbour values' total), the run of other
 //     values, each of weight w0 = D[n_max], is indexed by j = floor((r - S) /
-//     w0) (an FP32 estimate and one integer check each way), and the j-th
-//     value held by no neighbour comes from the sorted neighbour values.
+//     w0) (an FP32 estimate from above and one integer check), and the j-th
+//     value held by no neighbour comes from a bit mask of the neighbour values
+//     (q <= 16) or from the sorted neighbour values.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -58,19 +59,76 @@ __device__ __forceinline__ uint32_t pair_pattern(uint32_t a, uint32_t b, uint32_
   return bfi(0xF0F0F0F0u, hi, lo >> 4) & 0xFCFCFCFCu;
 }
 
-// dst.byte_J = (w <= t) ? src.byte_K : dst.byte_J (one v_cmp, one SDWA v_cndmask)
-#define POTTS_HB_SEL(J, K)                                                                         \
-  asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:BYTE_" #J          \
-      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #K                        \
+// dst.byte_J = (w <= t) ? src.byte_J : dst.byte_J: one v_cmp and one SDWA
+// v_cndmask.  gfx950 needs two wait states between a VALU write of VCC and a
+// VALU read of it, and one between an SDWA byte write and the next read of
+// that register (TAIL: the last select of a byte, whose result compiled code
+// reads next).
+#define POTTS_HB_SEL(J, TAIL)                                                                      \
+  asm("v_cmp_le_u32 vcc, %1, %2\n\ts_nop 1\n\tv_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:BYTE_" #J \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J TAIL                    \
       : "+v"(dst) : "v"(w), "v"(t), "v"(src) : "vcc")
-template <int J>
+template <int J, bool LAST = false>
 __device__ __forceinline__ void select_byte(uint32_t &dst, uint32_t w, uint32_t t, uint32_t src) {
-  if (J == 0) POTTS_HB_SEL(0, 0);
-  else if (J == 1) POTTS_HB_SEL(1, 1);
-  else if (J == 2) POTTS_HB_SEL(2, 2);
-  else POTTS_HB_SEL(3, 3);
+  if (LAST) {
+    if (J == 0) POTTS_HB_SEL(0, "\n\ts_nop 0");
+    else if (J == 1) POTTS_HB_SEL(1, "\n\ts_nop 0");
+    else if (J == 2) POTTS_HB_SEL(2, "\n\ts_nop 0");
+    else POTTS_HB_SEL(3, "\n\ts_nop 0");
+  } else {
+    if (J == 0) POTTS_HB_SEL(0, "");
+    else if (J == 1) POTTS_HB_SEL(1, "");
+    else if (J == 2) POTTS_HB_SEL(2, "");
+    else POTTS_HB_SEL(3, "");
+  }
 }
 #undef POTTS_HB_SEL
+
+// dst.byte_J = (w <= t) ? src.byte_J : k.byte_0 (the first select of a byte
+// also places the value no neighbour holds).
+#define POTTS_HB_PLACE(J)                                                                          \
+  asm("v_cmp_le_u32 vcc, %1, %2\n\ts_nop 1\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_" #J \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_0 src1_sel:BYTE_" #J                              \
+      : "+v"(dst) : "v"(w), "v"(t), "v"(k), "v"(src) : "vcc")
+template <int J>
+__device__ __forceinline__ void place_select(uint32_t &dst, uint32_t w, uint32_t t, uint32_t k, uint32_t src) {
+  if (J == 0) POTTS_HB_PLACE(0);
+  else if (J == 1) POTTS_HB_PLACE(1);
+  else if (J == 2) POTTS_HB_PLACE(2);
+  else POTTS_HB_PLACE(3);
+}
+#undef POTTS_HB_PLACE
+
+// float -> u32, truncating and saturating (v_cvt_u32_f32): the estimate below
+// is huge when the draw lands on a neighbour value, and is not used then.
+__device__ __forceinline__ uint32_t cvt_u32_sat(float f) {
+  uint32_t r;
+  asm("v_cvt_u32_f32 %0, %1" : "=v"(r) : "v"(f));
+  return r;
+}
+
+// u32 -> float, rounded to nearest (one v_cvt_f32_u32; written out so that
+// the pair below is not re-read as a 64-bit conversion)
+__device__ __forceinline__ float cvt_f32(uint32_t x) {
+  float r;
+  asm("v_cvt_f32_u32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// The j-th value (from 0, ascending) that none of the byte-J values of up,
+// dn, lf, rt holds, for values below 16: with m the set of neighbour values as
+// a bit mask, k = j + |{v in m : v <= k}|, reached from k = j in four steps
+// (each step before the last adds at least one of the at most four values).
+// kk = k + 1 is carried, so |{v <= k}| = popcount of the low kk bits of m.
+template <int J>
+__device__ __forceinline__ uint32_t free_value16(uint32_t j, uint32_t up, uint32_t dn, uint32_t lf, uint32_t rt) {
+  const uint32_t m = (1u << byte_of(up, J)) | (1u << byte_of(dn, J)) | (1u << byte_of(lf, J)) | (1u << byte_of(rt, J));
+  const uint32_t j1 = j + 1u;
+  uint32_t kk = j1 + __popc(__builtin_amdgcn_ubfe(m, 0u, j1));
+  kk = j1 + __popc(__builtin_amdgcn_ubfe(m, 0u, kk));
+  kk = j1 + __popc(__builtin_amdgcn_ubfe(m, 0u, kk));
+  return j + __popc(__builtin_amdgcn_ubfe(m, 0u, kk));
+}
 
 // The j-th value (from 0, ascending) that none of a, b, c, d holds.
 __device__ __forceinline__ uint32_t free_value(uint32_t j, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -94,40 +152,46 @@ __device__ __forceinline__ uint32_t free_value(uint32_t j, uint32_t a, uint32_t 
 
 // The new value of byte J of a 4-site group: up/dn/lf/rt the neighbour dwords,
 // pf their pattern bytes, w the site's word.  Written into byte J of out.
-template <int J, bool WIDE>
+template <int J, int CMP, bool WIDE>
 __device__ __forceinline__ void draw(uint32_t &out, uint32_t up, uint32_t dn, uint32_t lf, uint32_t rt, uint32_t pf,
                                      uint32_t w, const uint8_t *tab) {
   const uint32_t off = table_offset<J, 2>(pf);
   const u32x4 zs = *reinterpret_cast<const u32x4 *>(tab + HbTable::kZs + off);   // Z lo/hi, S lo/hi
-  const u32x4 wi = *reinterpret_cast<const u32x4 *>(tab + HbTable::kWi + off);   // w0, 1/w0 (FP32)
+  const uint2 wi = *reinterpret_cast<const uint2 *>(tab + HbTable::kWi + off);   // w0, 1/w0 rounded up (FP32)
   const uint64_t S = ((uint64_t)zs.w << 32) | zs.z;
-  // r = floor(w Z / 2^32) for Z = zs.y 2^32 + zs.x < 2^41
-  const uint64_t r = (uint64_t)w * zs.y + __umulhi(w, zs.x);
-  // the run of values no neighbour holds: j = floor((r - S) / w0), exact
-  const uint64_t X = r >= S ? r - S : 0;
-  const float xf = __builtin_fmaf((float)(uint32_t)(X >> 32), 4294967296.0f, (float)(uint32_t)X);
-  uint32_t j = (uint32_t)(xf * __uint_as_float(wi.y));
-  const uint64_t jw = (uint64_t)j * wi.x;
-  j = j - (uint32_t)(jw > X) + (uint32_t)(jw + wi.x <= X);
-  const uint32_t a = byte_of(up, J), b = byte_of(dn, J), c = byte_of(lf, J), d = byte_of(rt, J);
-  const uint32_t k = free_value(j, a, b, c, d);
-  out = (out & ~(0xFFu << (8 * J))) | ((k & 0xFFu) << (8 * J));
+  // X = floor(w Z / 2^32) - S (Z = zs.y 2^32 + zs.x < 2^41), modulo 2^64: when
+  // the draw lands in the run of values no neighbour holds (r >= S) it is the
+  // offset into that run, X < 2^40; otherwise a cut below picks a neighbour
+  // value and what follows from X is overwritten.
+  const uint64_t X = (uint64_t)w * zs.y + __umulhi(w, zs.x) - S;
+  // j = floor(X / w0): the FP32 estimate lies in [X / w0, X / w0 + 2^-10) (the
+  // reciprocal carries a 2^-19 upward bias against four roundings of 2^-24 and
+  // X / w0 < 256), so it is exact or one too high
+  const float xf = __builtin_fmaf(cvt_f32((uint32_t)(X >> 32)), 4294967296.0f, cvt_f32((uint32_t)X));
+  const uint32_t je = cvt_u32_sat(xf * __uint_as_float(wi.y));
+  const uint32_t j = je - (uint32_t)((uint64_t)je * wi.x > X);
+  uint32_t k;
+  if (CMP == 0) {
+    k = free_value16<J>(j, up, dn, lf, rt);
+  } else {
+    k = free_value(j, byte_of(up, J), byte_of(dn, J), byte_of(lf, J), byte_of(rt, J));
+  }
   if (!WIDE) {
     // narrow cuts: rank i wins when w <= cut_i (= ceil(c_i 2^32 / Z) - 1)
     const u32x4 cut = *reinterpret_cast<const u32x4 *>(tab + HbTable::kCut + off);
-    select_byte<J>(out, w, cut.w, rt);
+    place_select<J>(out, w, cut.w, k, rt);
     select_byte<J>(out, w, cut.z, lf);
     select_byte<J>(out, w, cut.y, dn);
-    select_byte<J>(out, w, cut.x, up);
+    select_byte<J, true>(out, w, cut.x, up);
   } else {
     // wide cuts (some weights are 0): rank i wins when w < cut_i, cut_i <= 2^32
     const uint64_t *c64 = reinterpret_cast<const uint64_t *>(tab + HbTable::kCut64 + 2 * off);
     uint32_t v = k;
-    if ((uint64_t)w < c64[3]) v = d;
-    if ((uint64_t)w < c64[2]) v = c;
-    if ((uint64_t)w < c64[1]) v = b;
-    if ((uint64_t)w < c64[0]) v = a;
-    out = (out & ~(0xFFu << (8 * J))) | (v << (8 * J));
+    if ((uint64_t)w < c64[3]) v = byte_of(rt, J);
+    if ((uint64_t)w < c64[2]) v = byte_of(lf, J);
+    if ((uint64_t)w < c64[1]) v = byte_of(dn, J);
+    if ((uint64_t)w < c64[0]) v = byte_of(up, J);
+    out = (out & ~(0xFFu << (8 * J))) | ((v & 0xFFu) << (8 * J));
   }
 }
 
@@ -137,10 +201,10 @@ __device__ __forceinline__ uint32_t draw4(uint32_t up, uint32_t dn, uint32_t lf,
                                           uint32_t w1_, uint32_t w2_, uint32_t w3_, const uint8_t *tab) {
   const uint32_t pf = pair_pattern<CMP>(up, dn, lf, rt);
   uint32_t out = 0;
-  draw<0, WIDE>(out, up, dn, lf, rt, pf, w0_, tab);
-  draw<1, WIDE>(out, up, dn, lf, rt, pf, w1_, tab);
-  draw<2, WIDE>(out, up, dn, lf, rt, pf, w2_, tab);
-  draw<3, WIDE>(out, up, dn, lf, rt, pf, w3_, tab);
+  draw<0, CMP, WIDE>(out, up, dn, lf, rt, pf, w0_, tab);
+  draw<1, CMP, WIDE>(out, up, dn, lf, rt, pf, w1_, tab);
+  draw<2, CMP, WIDE>(out, up, dn, lf, rt, pf, w2_, tab);
+  draw<3, CMP, WIDE>(out, up, dn, lf, rt, pf, w3_, tab);
   return out;
 }
 
@@ -194,6 +258,9 @@ __device__ __forceinline__ void hb_row(const PhiloxHead &h, __amdgpu_buffer_rsrc
   cy.p = dn;
 }
 
+// The compiler's register choice (about 92 VGPRs, 5 waves per SIMD) measured
+// faster than 6 or 8 waves per SIMD forced (1.81 against 1.91 and 1.94 ps per
+// site update at L = 8192, q = 9: the forced forms spill inside the loop).
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 __global__ __launch_bounds__(kBlock) void hb_packed_kernel(HbLaunch launch) {
   __shared__ __align__(16) uint8_t tab[HbTable::kBytes];
@@ -345,7 +412,9 @@ bool build_heatbath_table(const uint32_t thr[4], uint32_t q, HbTable *t) {
     zs[pat * 4 + 1] = (uint32_t)(Z >> 32);
     zs[pat * 4 + 2] = (uint32_t)S;
     zs[pat * 4 + 3] = (uint32_t)(S >> 32);
-    const float inv = w0 ? (float)(1.0 / (double)w0) : 0.0f;
+    // 1/w0 rounded up by 2^-19 relative, so the kernel's FP32 estimate of
+    // floor(X / w0) is never below it
+    const float inv = w0 ? (float)((1.0 + 0x1p-19) / (double)w0) : 0.0f;
     uint32_t inv_bits;
     memcpy(&inv_bits, &inv, 4);
     wi[pat * 4 + 0] = (uint32_t)w0;

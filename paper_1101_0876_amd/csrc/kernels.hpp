@@ -97,7 +97,7 @@ struct StripLaunch {
 struct HbTable {
   static constexpr uint32_t kCut = 0;       // 64 x 4 uint32: ceil(c_i 2^32 / Z) - 1 (all thresholds >= 1)
   static constexpr uint32_t kZs = 1024;     // 64 x {Z lo, Z hi, S lo, S hi}
-  static constexpr uint32_t kWi = 2048;     // 64 x {w0, 1/w0 as FP32 bits, 0, 0}
+  static constexpr uint32_t kWi = 2048;     // 64 x {w0, (1 + 2^-19)/w0 as FP32 bits, 0, 0}
   static constexpr uint32_t kCut64 = 3072;  // 64 x 4 uint64: ceil(c_i 2^32 / Z) (some threshold 0)
   static constexpr uint32_t kBytes = 5120;
   uint8_t bytes[kBytes];

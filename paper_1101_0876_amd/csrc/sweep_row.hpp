@@ -66,41 +66,42 @@ __device__ __forceinline__ uint32_t table_offset(uint32_t idx) {
 }
 
 // dst.byte_J = (w <= t) ? if_acc.byte_J : if_rej.byte_J, other bytes of dst
-// kept: one v_cmp and one SDWA v_cndmask.
+// kept: one v_cmp and one SDWA v_cndmask.  gfx950 needs two wait states
+// between a VALU write of VCC and a VALU read of it, and one between an SDWA
+// byte write and the next read of that register: byte 3 is a byte's last
+// select, whose result compiled code may read next.
+#define POTTS_ACCEPT1(J, TAIL)                                                                  \
+  asm("v_cmp_le_u32 vcc, %1, %2\n\ts_nop 1\n\t"                                              \
+      "v_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_" #J                                     \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J TAIL                 \
+      : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc")
 template <int J>
 __device__ __forceinline__ void accept_byte(uint32_t &dst, uint32_t w, uint32_t t, uint32_t if_rej,
                                             uint32_t if_acc) {
-  if (J == 0)
-    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_0 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_0 src1_sel:BYTE_0"
-        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
-  else if (J == 1)
-    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_1 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_1 src1_sel:BYTE_1"
-        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
-  else if (J == 2)
-    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_2 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_2 src1_sel:BYTE_2"
-        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
-  else
-    asm("v_cmp_le_u32 vcc, %1, %2\n\tv_cndmask_b32_sdwa %0, %3, %4, vcc dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:BYTE_3 src1_sel:BYTE_3"
-        : "+v"(dst) : "v"(w), "v"(t), "v"(if_rej), "v"(if_acc) : "vcc");
+  if (J == 0) POTTS_ACCEPT1(0, "");
+  else if (J == 1) POTTS_ACCEPT1(1, "");
+  else if (J == 2) POTTS_ACCEPT1(2, "");
+  else POTTS_ACCEPT1(3, "\n\ts_nop 0");
 }
+#undef POTTS_ACCEPT1
 
 // As accept_byte, selecting byte J of two pairs with one compare.
-#define POTTS_ACCEPT2(J)                                                                        \
-  asm("v_cmp_le_u32 vcc, %2, %3\n\t"                                                           \
+#define POTTS_ACCEPT2(J, TAIL)                                                                  \
+  asm("v_cmp_le_u32 vcc, %2, %3\n\ts_nop 1\n\t"                                              \
       "v_cndmask_b32_sdwa %0, %4, %5, vcc dst_sel:BYTE_" #J                                     \
       " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J "\n\t"              \
       "v_cndmask_b32_sdwa %1, %6, %7, vcc dst_sel:BYTE_" #J                                     \
-      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J                      \
+      " dst_unused:UNUSED_PRESERVE src0_sel:BYTE_" #J " src1_sel:BYTE_" #J TAIL                 \
       : "+v"(dst1), "+v"(dst2)                                                                  \
       : "v"(w), "v"(t), "v"(rej1), "v"(acc1), "v"(rej2), "v"(acc2)                              \
       : "vcc")
 template <int J>
 __device__ __forceinline__ void accept_byte2(uint32_t &dst1, uint32_t &dst2, uint32_t w, uint32_t t,
                                              uint32_t rej1, uint32_t acc1, uint32_t rej2, uint32_t acc2) {
-  if (J == 0) POTTS_ACCEPT2(0);
-  else if (J == 1) POTTS_ACCEPT2(1);
-  else if (J == 2) POTTS_ACCEPT2(2);
-  else POTTS_ACCEPT2(3);
+  if (J == 0) POTTS_ACCEPT2(0, "");
+  else if (J == 1) POTTS_ACCEPT2(1, "");
+  else if (J == 2) POTTS_ACCEPT2(2, "");
+  else POTTS_ACCEPT2(3, "\n\ts_nop 0");
 }
 #undef POTTS_ACCEPT2
 
