@@ -159,7 +159,12 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * per workgroup whose halo is recomputed, and moves the row-major lattice
  * between the state's two buffers; with library-owned buffers they trade
  * roles, so potts_device_spins may return the other one afterwards; shape
- * from potts_tune_tiles);
+ * from potts_tune_tiles), 6 = the LDS-resident kernel with its random words
+ * drawn beforehand (L % 16 == 0, L <= 64: a generator kernel over the whole
+ * GPU writes each site's proposal and acceptance word for up to 1024 sweeps
+ * into a device buffer of about 20 bytes per site and sweep, allocated on
+ * first use and held until potts_free, and the one-workgroup kernel reads
+ * them instead of computing them; the automatic choice for such L);
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
  * L); max_groups: persistent grid size in workgroups (0 = automatic).
  * Errors: EINVAL. */

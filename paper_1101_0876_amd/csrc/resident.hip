@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "drawn.hpp"
 #include "kernels.hpp"
 #include "sweep_row.hpp"
 
@@ -214,6 +215,213 @@ __global__ __launch_bounds__(NARROW ? 512 : 256) void resident_kernel(ResidentLa
     *reinterpret_cast<u32x4 *>(j.spins + off) = *reinterpret_cast<const u32x4 *>(lat + off);
 }
 
+// ---- pre-drawn words (drawn.hpp) ---------------------------------------------
+
+// Wave64 sum in registers (DPP within each row of 16 lanes, then the four
+// row sums read out), for a whole active wave: the per-sweep reductions of
+// the pre-drawn kernel sit on its critical path, where wave_sum's shuffles
+// take an LDS round trip each.
+__device__ __forceinline__ uint32_t wave_sum_rows(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// Item i of a half sweep (the order of half_sweep8): row y, byte column col.
+__device__ __forceinline__ void item_geometry(uint32_t L, uint32_t i, uint32_t &y, uint32_t &col) {
+  const uint32_t cpr = L >> 3, per_parity = (L >> 1) * cpr;
+  const uint32_t par = i >= per_parity;
+  const uint32_t k = i - par * per_parity;
+  const uint32_t rr = k / cpr;
+  y = 2 * rr + par;
+  col = (k - rr * cpr) * 8u;
+}
+
+// Word buffer of H half sweeps of n items: acceptance words (one u32x4 per
+// item, site j's word in component j) first, then the packed proposals.
+__host__ __device__ inline size_t drawn_acc_words(uint32_t H, uint32_t n) { return (size_t)H * n * 4u; }
+
+// One thread per (item, half sweep of the chunk): half sweep hs is colour
+// hs & 1 of sweep t0 + hs / 2.
+__global__ __launch_bounds__(256) void draw_words_kernel(ResidentJob j, uint32_t nitems, uint32_t H, uint32_t *words) {
+  const uint32_t hs = blockIdx.y;
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= nitems) return;
+  const uint64_t t = j.t0 + (hs >> 1);
+  const PhiloxHead h = philox_head((uint32_t)t, (uint32_t)(t >> 32), hs & 1u, j.k0, j.k1);
+  uint32_t y, col;
+  item_geometry(j.L, i, y, col);
+  // the blocks of update4: chunk ctr (even) and ctr + 1 == ctr ^ 1
+  const uint32_t x0 = h.a0 ^ (y * (j.L >> 2) + (col >> 2));
+  const Words b0 = philox_tail(x0, h);
+  const Words b1 = philox_tail(x0 ^ 1u, h);
+  const uint32_t q = j.q;
+  reinterpret_cast<u32x4 *>(words)[(size_t)hs * nitems + i] = u32x4{b0.w1, b0.w3, b1.w1, b1.w3};
+  words[drawn_acc_words(H, nitems) + (size_t)hs * nitems + i] =
+      pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
+}
+
+template <int COLOUR, int CMP, bool PRIV, bool WIDE>
+__device__ __forceinline__ uint32_t drawn_half(uint8_t *lat, uint32_t L, uint32_t y, uint32_t col, bool has,
+                                               uint32_t k, const u32x4 &a, const uint8_t *table, uint8_t *hist,
+                                               uint32_t lane_off) {
+  if (!has) return 0;
+  const uint32_t ro = y * L;
+  const uint32_t ru = (y == 0 ? L - 1 : y - 1) * L;
+  const uint32_t rd = (y + 1 == L ? 0 : y + 1) * L;
+  const uint2 cur = lds8(lat, ro + col);
+  const uint2 up = lds8(lat, ru + col);
+  const uint2 dn = lds8(lat, rd + col);
+  Row4 r;
+  if (((COLOUR + y) & 1u) == 0) {
+    const uint32_t side = lds4(lat, ro + (col == 0 ? L - 4 : col - 4));
+    r = update4_drawn<COLOUR, 0, CMP, WIDE>(perm(cur.y, cur.x, kSel<0>), perm(cur.y, cur.x, kSel<1>),
+                                            perm(up.y, up.x, kSel<0>), perm(dn.y, dn.x, kSel<0>), side, k, a.x, a.y,
+                                            a.z, a.w, table);
+  } else {
+    const uint32_t side = lds4(lat, ro + (col + 8 == L ? 0u : col + 8));
+    r = update4_drawn<COLOUR, 1, CMP, WIDE>(perm(cur.y, cur.x, kSel<1>), perm(cur.y, cur.x, kSel<0>),
+                                            perm(up.y, up.x, kSel<1>), perm(dn.y, dn.x, kSel<1>), side, k, a.x, a.y,
+                                            a.z, a.w, table);
+  }
+  *reinterpret_cast<uint2 *>(lat + ro + col) = make_uint2(r.out_x, r.out_y);
+  if (COLOUR == 1) {
+    if (PRIV)
+      count_active_private(hist, lane_off, r.out_x, r.out_y);
+    else
+      count_active_shared(reinterpret_cast<uint32_t *>(hist), r.out_x, r.out_y);
+    return __popc(r.nz & 0xF0F0F0F0u);
+  }
+  return 0;
+}
+
+// One lattice, 512 lanes, lane i owns item i of every half sweep.  The words
+// of half sweep h sit in register slot h % 4 and are loaded kDrawnAhead half
+// sweeps before use; the loop body spans two sweeps so every slot is a fixed
+// set of registers.  Two barriers per sweep: the counters of sweep s - 1 (one
+// of two sets, by sweep parity) are reduced into its record, and cleared,
+// while colour 0 of sweep s runs.
+template <int CMP, bool PRIV, bool WIDE>
+__global__ __launch_bounds__(512) void resident_drawn_kernel(ResidentJob j, const uint32_t *words) {
+  constexpr int kBlock = 512, kWaves = kBlock / 64;
+  __shared__ __align__(16) uint32_t table_words[512];
+  constexpr uint32_t kHistWords = PRIV ? 64u * (CMP == 0 ? 16u : kPrivateHistMaxQ) : 256u;
+  __shared__ __align__(16) uint32_t hist[2][kHistWords];
+  __shared__ uint32_t nzw[2][kWaves];  // colour-1 differing-neighbour sums per wave
+  extern __shared__ __align__(16) uint32_t lds[];
+  const uint32_t L = j.L, q = j.q, nbytes = L * L, nitems = nbytes >> 3;
+  const uint32_t H = 2u * (j.nsweeps + kDrawnPad);
+  uint8_t *lat = reinterpret_cast<uint8_t *>(lds);
+  uint8_t *table = reinterpret_cast<uint8_t *>(table_words);
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint32_t lane_off = lane * 4u;
+  const bool has = threadIdx.x < nitems;
+  const uint32_t me = has ? threadIdx.x : 0u;  // lanes without an item load item 0's words
+  uint32_t y = 0, col = 0;
+  item_geometry(L, me, y, col);
+  const u32x4 *aw = reinterpret_cast<const u32x4 *>(words) + me;
+  const uint32_t *kw = words + drawn_acc_words(H, nitems) + me;
+  const uint32_t nh = PRIV ? 64 * q : q;
+
+  fill_accept_table<WIDE>(table, j.thr);
+  for (uint32_t off = threadIdx.x * 16u; off < nbytes; off += kBlock * 16u)
+    *reinterpret_cast<u32x4 *>(lat + off) = *reinterpret_cast<const u32x4 *>(j.spins + off);
+  for (uint32_t i = threadIdx.x; i < nh; i += kBlock) {
+    hist[0][i] = 0;
+    hist[1][i] = 0;
+  }
+
+  // slots 0 .. 2 in the order the loop reloads them (each slot's two loads
+  // together), so the loads in flight at each use are counted the same way on
+  // the first pass as on later ones
+  u32x4 a0, a1, a2, a3;
+  uint32_t k0, k1, k2, k3;
+  a0 = aw[0];
+  k0 = kw[0];
+  __builtin_amdgcn_sched_barrier(0);
+  a1 = aw[nitems];
+  k1 = kw[nitems];
+  __builtin_amdgcn_sched_barrier(0);
+  a2 = aw[2 * nitems];
+  k2 = kw[2 * nitems];
+  __builtin_amdgcn_sched_barrier(0);
+  __syncthreads();
+
+  // the record of sweep t from counter set b, which is then cleared.  Fixed
+  // trip counts (no loop around the stores: the compiler would wait for every
+  // word load in flight before entering one)
+  auto record = [&](uint64_t t, uint32_t b) {
+    unsigned long long *rec = j.ring + (t & (j.cap - 1)) * (uint64_t)(q + 1);
+    if (PRIV) {
+      constexpr uint32_t kRounds = kHistWords / 64u / kWaves;
+#pragma unroll
+      for (uint32_t r = 0; r < kRounds; ++r) {
+        const uint32_t v = wave + r * kWaves;
+        if (v < q) {
+          const uint32_t c = wave_sum_rows(hist[b][v * 64u + lane]);
+          hist[b][v * 64u + lane] = 0;
+          if (lane == 0) rec[1 + v] = c;
+        }
+      }
+    } else if (threadIdx.x < q) {  // q <= 256 < kBlock
+      rec[1 + threadIdx.x] = hist[b][threadIdx.x];
+      hist[b][threadIdx.x] = 0;
+    }
+    if (threadIdx.x == 0) {
+      uint32_t nzt = 0;
+      for (int w = 0; w < kWaves; ++w) nzt += nzw[b][w];
+      // each colour-1 site has 4 bonds; e_sat = 4 * (N/2) - differing neighbours
+      rec[0] = (unsigned long long)(2u * nbytes - nzt);
+    }
+  };
+  // sweep s: colour 0 (and the record of sweep s - 1), colour 1 counting
+  // into set s & 1
+  auto colour0 = [&](uint32_t s, const u32x4 &a, uint32_t k) {
+    drawn_half<0, CMP, PRIV, WIDE>(lat, L, y, col, has, k, a, table, nullptr, lane_off);
+    if (s > 0) record(j.t0 + s - 1, (s - 1) & 1u);
+    __syncthreads();
+  };
+  auto colour1 = [&](uint32_t s, const u32x4 &a, uint32_t k) {
+    const uint32_t b = s & 1u;
+    const uint32_t nz =
+        drawn_half<1, CMP, PRIV, WIDE>(lat, L, y, col, has, k, a, table, reinterpret_cast<uint8_t *>(hist[b]), lane_off);
+    const uint32_t nz_w = wave_sum_rows(nz);
+    if (lane == 0) nzw[b][wave] = nz_w;
+    __syncthreads();
+  };
+  // half sweeps h .. h + 3 of two sweeps use slots 0 .. 3; a slot is reloaded
+  // (kDrawnAhead half sweeps ahead) right after the half sweep that used it.
+  // The body always runs both sweeps (an odd last one follows the loop), so
+  // the loads in flight at every use are the same three slots.
+  const uint32_t pairs = j.nsweeps >> 1;
+  for (uint32_t m = 0; m < pairs; ++m) {
+    const size_t h = 4u * (size_t)m;
+    a3 = aw[(h + 3) * nitems];
+    k3 = kw[(h + 3) * nitems];
+    colour0(2u * m, a0, k0);
+    a0 = aw[(h + 4) * nitems];
+    k0 = kw[(h + 4) * nitems];
+    colour1(2u * m, a1, k1);
+    a1 = aw[(h + 5) * nitems];
+    k1 = kw[(h + 5) * nitems];
+    colour0(2u * m + 1u, a2, k2);
+    a2 = aw[(h + 6) * nitems];
+    k2 = kw[(h + 6) * nitems];
+    colour1(2u * m + 1u, a3, k3);
+  }
+  if (j.nsweeps & 1u) {
+    colour0(j.nsweeps - 1u, a0, k0);
+    colour1(j.nsweeps - 1u, a1, k1);
+  }
+  record(j.t0 + j.nsweeps - 1u, (j.nsweeps - 1u) & 1u);
+  __syncthreads();
+  for (uint32_t off = threadIdx.x * 16u; off < nbytes; off += kBlock * 16u)
+    *reinterpret_cast<u32x4 *>(j.spins + off) = *reinterpret_cast<const u32x4 *>(lat + off);
+}
+
 template <int CMP, bool PRIV, bool WIDE>
 hipError_t launch_t(const ResidentLaunch &p, unsigned n, size_t lds, hipStream_t stream) {
   if (p.jobs)
@@ -241,6 +449,42 @@ size_t resident_lds_bytes(uint32_t L, uint32_t q) {
 
 bool resident_fits(uint32_t L, uint32_t q) {
   return L % 16 == 0 && (uint64_t)L * L <= 65536 && q >= 2 && q <= 256;
+}
+
+bool drawn_fits(uint32_t L, uint32_t q) { return resident_fits(L, q) && (L * L >> 3) <= kDrawnMaxItems; }
+
+size_t drawn_words_bytes(uint32_t L) {
+  // per item and half sweep: four acceptance words and the packed proposals
+  return (size_t)2u * (kDrawnChunk + kDrawnPad) * (L * L >> 3) * 20u;
+}
+
+hipError_t launch_draw_words(const ResidentJob &j, uint32_t *words, hipStream_t stream) {
+  if (j.nsweeps == 0) return hipSuccess;
+  if (!drawn_fits(j.L, j.q) || j.nsweeps > kDrawnChunk) return hipErrorInvalidValue;
+  const uint32_t nitems = j.L * j.L >> 3, H = 2u * (j.nsweeps + kDrawnPad);
+  hipLaunchKernelGGL(draw_words_kernel, dim3((nitems + 255) / 256, H), dim3(256), 0, stream, j, nitems, H, words);
+  return hipGetLastError();
+}
+
+template <int CMP, bool PRIV, bool WIDE>
+hipError_t launch_d(const ResidentJob &j, const uint32_t *words, hipStream_t stream) {
+  hipLaunchKernelGGL((resident_drawn_kernel<CMP, PRIV, WIDE>), dim3(1), dim3(512), (size_t)j.L * j.L, stream, j,
+                     words);
+  return hipGetLastError();
+}
+
+template <bool WIDE>
+hipError_t launch_dw(const ResidentJob &j, const uint32_t *words, hipStream_t stream) {
+  if (j.q <= 16) return launch_d<0, true, WIDE>(j, words, stream);
+  if (j.q <= kPrivateHistMaxQ) return launch_d<1, true, WIDE>(j, words, stream);
+  if (j.q <= 128) return launch_d<1, false, WIDE>(j, words, stream);
+  return launch_d<2, false, WIDE>(j, words, stream);
+}
+
+hipError_t launch_resident_drawn(const ResidentJob &j, const uint32_t *words, bool wide, hipStream_t stream) {
+  if (j.nsweeps == 0) return hipSuccess;
+  if (!drawn_fits(j.L, j.q) || j.nsweeps > kDrawnChunk) return hipErrorInvalidValue;
+  return wide ? launch_dw<true>(j, words, stream) : launch_dw<false>(j, words, stream);
 }
 
 hipError_t launch_resident(const ResidentLaunch &p, unsigned njobs, uint32_t max_L, uint32_t max_q,

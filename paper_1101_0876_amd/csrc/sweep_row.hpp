@@ -259,11 +259,10 @@ __device__ __forceinline__ Row8 update8(uint32_t s_lo, uint32_t s_hi, uint32_t p
   return r;
 }
 
-// The same update for the 4 active sites of 8 row bytes (two Philox blocks):
+// The same update for the 4 active sites of 8 row bytes, given their words:
 // s/p/u/d are the packed active, passive, up and down bytes, side the dword
-// left (O == 0) or right (O == 1) of the 8 bytes, ctr the chunk of the first
-// dword (even).  Used where more, smaller work items pay (the LDS-resident
-// kernel, one workgroup per small lattice).
+// left (O == 0) or right (O == 1) of the 8 bytes, k the four proposals
+// packed (site j in byte j) and a0..a3 the four acceptance words.
 struct Row4 {
   uint32_t out_x, out_y;  // the 8 bytes after the update
   uint32_t ns;            // the 4 updated bytes, packed
@@ -271,14 +270,10 @@ struct Row4 {
 };
 
 template <int COLOUR, int O, int CMP, bool WIDE>
-__device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint32_t d, uint32_t side,
-                                        uint32_t ctr, const PhiloxHead &h, uint32_t q, const uint8_t *table) {
+__device__ __forceinline__ Row4 update4_drawn(uint32_t s, uint32_t p, uint32_t u, uint32_t d, uint32_t side,
+                                              uint32_t k, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3,
+                                              const uint8_t *table) {
   const uint32_t x = O == 0 ? alignbyte(p, side, 3) : alignbyte(side, p, 1);
-  // ctr + 1 == ctr ^ 1 for even ctr
-  const uint32_t x0 = h.a0 ^ ctr;
-  const Words b0 = philox_tail(x0, h);
-  const Words b1 = philox_tail(x0 ^ 1u, h);
-  const uint32_t k = pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
   const uint32_t ps = diff_pattern<CMP>(s, u, d, p, x);
   const uint32_t pk = diff_pattern<CMP>(k, u, d, p, x);
   const uint32_t idx = bfi(0xF0F0F0F0u, pk, ps >> 4);
@@ -288,21 +283,21 @@ __device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint
     const uint32_t t0 = POTTS_T(0), t1 = POTTS_T(1), t2 = POTTS_T(2), t3 = POTTS_T(3);
 #undef POTTS_T
     // byte 0 by a whole-dword select, bytes 1..3 overwritten next
-    const bool a0 = b0.w1 <= t0;
-    ns = a0 ? k : s;
+    const bool acc0 = a0 <= t0;
+    ns = acc0 ? k : s;
     if (COLOUR == 0) {
-      accept_byte<1>(ns, b0.w3, t1, s, k);
-      accept_byte<2>(ns, b1.w1, t2, s, k);
-      accept_byte<3>(ns, b1.w3, t3, s, k);
+      accept_byte<1>(ns, a1, t1, s, k);
+      accept_byte<2>(ns, a2, t2, s, k);
+      accept_byte<3>(ns, a3, t3, s, k);
     } else {
-      nz = a0 ? pk : ps;
-      accept_byte2<1>(ns, nz, b0.w3, t1, s, k, ps, pk);
-      accept_byte2<2>(ns, nz, b1.w1, t2, s, k, ps, pk);
-      accept_byte2<3>(ns, nz, b1.w3, t3, s, k, ps, pk);
+      nz = acc0 ? pk : ps;
+      accept_byte2<1>(ns, nz, a1, t1, s, k, ps, pk);
+      accept_byte2<2>(ns, nz, a2, t2, s, k, ps, pk);
+      accept_byte2<3>(ns, nz, a3, t3, s, k, ps, pk);
     }
   } else {
     const uint64_t *t64 = reinterpret_cast<const uint64_t *>(table);
-    const uint32_t acc_w[4] = {b0.w1, b0.w3, b1.w1, b1.w3};
+    const uint32_t acc_w[4] = {a0, a1, a2, a3};
     uint32_t sel = 0x03020100u;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -318,6 +313,20 @@ __device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint
   r.ns = ns;
   r.nz = nz;
   return r;
+}
+
+// The update with its words drawn here (two Philox blocks): ctr is the chunk
+// of the first dword (even).  Used where more, smaller work items pay (the
+// LDS-resident kernel, one workgroup per small lattice).
+template <int COLOUR, int O, int CMP, bool WIDE>
+__device__ __forceinline__ Row4 update4(uint32_t s, uint32_t p, uint32_t u, uint32_t d, uint32_t side,
+                                        uint32_t ctr, const PhiloxHead &h, uint32_t q, const uint8_t *table) {
+  // ctr + 1 == ctr ^ 1 for even ctr
+  const uint32_t x0 = h.a0 ^ ctr;
+  const Words b0 = philox_tail(x0, h);
+  const Words b1 = philox_tail(x0 ^ 1u, h);
+  const uint32_t k = pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
+  return update4_drawn<COLOUR, O, CMP, WIDE>(s, p, u, d, side, k, b0.w1, b0.w3, b1.w1, b1.w3, table);
 }
 
 // Counts the 16 final values of a row into lane-private LDS columns:
