@@ -13,7 +13,8 @@ the roofline of the dominant kernel (the half-sweep kernel, timed with events
 on its own stream), the serial CPU oracle timed on a bounded sample, and the
 metric's other two parts at their workloads' own sizes: batched replicas in
 jobs/s beside the plain one-lattice-at-a-time loop, and the serving burst in
-jobs/s with p50/p99 latency (--no-extras skips these two).
+jobs/s with p50/p99 latency; and the plain method and the metastability
+ramps in ns per spin flip (--no-extras skips these four).
 """
 from __future__ import annotations
 
@@ -363,9 +364,19 @@ def run_extras(args):
     tuned launch shapes) beside the plain one-lattice-at-a-time loop, and the
     serving burst (1000 Poisson arrivals at 200/s) with its sweep counts scaled
     by 0.01 (the stated 10^3..10^5 sweeps per job offer ~60x one GPU's
-    throughput and take minutes: `--workload serve --serve-scale 1.0`)."""
+    throughput and take minutes: `--workload serve --serve-scale 1.0`).  Also
+    the other two configurations in ns per spin flip: the plain method in full
+    (L = 64, q = 9, 1000 sweeps, 20 runs) and the metastability ramps with 100
+    sweeps per point (10^4 in the configuration: `--workload ramp
+    --ramp-sweeps 10000`)."""
     import copy
 
+    p_args = copy.copy(args)
+    p_args.steps, p_args.no_cpu = 20, True
+    pl = run_plain(p_args)
+    r_args = copy.copy(args)
+    r_args.ramp_sweeps = 100
+    rp = run_ramp(r_args)
     b_args = copy.copy(args)
     b_args.steps, b_args.no_plain, b_args.tune_cache = 500, False, None
     b = run_batch(b_args)
@@ -380,6 +391,10 @@ def run_extras(args):
         "served": {"jobs_per_s": sv["value"], "latency_s": sv["latency_s"],
                    "ns_per_spin_flip": sv["ns_per_spin_flip"], "span_s": sv["span_s"], "config": sv["config"],
                    "note": "sweep counts x0.01 of the stated 10^3..10^5 per job"},
+        "plain": {"ns_per_spin_flip": pl["value"], "ms_per_run": pl["ms_per_step"], "runs": pl["steps"],
+                  "config": pl["config"]},
+        "ramp": {"ns_per_spin_flip": rp["value"], "wall_s": rp["wall_s"], "config": rp["config"],
+                 "note": "100 sweeps per point of the stated 10^4"},
     }
 
 
@@ -872,7 +887,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-extras", action="store_true",
-                    help="default workload: skip the batched and served summaries")
+                    help="default workload: skip the batched, served, plain-method and ramp summaries")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "

@@ -20,6 +20,7 @@
 #include "drawn.hpp"
 #include "kernels.hpp"
 #include "sweep_row.hpp"
+#include "wave.hpp"
 
 namespace potts {
 namespace {
@@ -188,11 +189,11 @@ __global__ __launch_bounds__(NARROW ? 512 : 256) void resident_kernel(ResidentLa
     __syncthreads();
     const uint32_t nz = NARROW ? half_sweep8<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off)
                                : half_sweep16<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off);
-    const uint32_t nz_w = wave_sum(nz);
+    const uint32_t nz_w = wave_sum_rows(nz);
     __syncthreads();
     if (PRIV) {
       for (uint32_t v = wave; v < q; v += kWaves) {
-        const uint32_t c = wave_sum(hist[v * 64u + lane]);
+        const uint32_t c = wave_sum_rows(hist[v * 64u + lane]);
         if (lane == 0) partial[v] = c;
       }
     } else {
@@ -216,19 +217,6 @@ __global__ __launch_bounds__(NARROW ? 512 : 256) void resident_kernel(ResidentLa
 }
 
 // ---- pre-drawn words (drawn.hpp) ---------------------------------------------
-
-// Wave64 sum in registers (DPP within each row of 16 lanes, then the four
-// row sums read out), for a whole active wave: the per-sweep reductions of
-// the pre-drawn kernel sit on its critical path, where wave_sum's shuffles
-// take an LDS round trip each.
-__device__ __forceinline__ uint32_t wave_sum_rows(uint32_t v) {
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
-         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-}
 
 // Item i of a half sweep (the order of half_sweep8): row y, byte column col.
 __device__ __forceinline__ void item_geometry(uint32_t L, uint32_t i, uint32_t &y, uint32_t &col) {
