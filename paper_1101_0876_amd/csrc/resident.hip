@@ -252,6 +252,10 @@ __global__ __launch_bounds__(256) void draw_words_kernel(ResidentJob j, uint32_t
       pack4(scale_to_q(b0.w0, q), scale_to_q(b0.w2, q), scale_to_q(b1.w0, q), scale_to_q(b1.w2, q));
 }
 
+// Item (y, col)'s part of a colour-COLOUR half sweep with its drawn words: k
+// the packed proposals, a the acceptance words.  Colour 1 counts the final
+// values of all 8 bytes and returns the differing-neighbour flags of its 4
+// sites.
 template <int COLOUR, int CMP, bool PRIV, bool WIDE>
 __device__ __forceinline__ uint32_t drawn_half(uint8_t *lat, uint32_t L, uint32_t y, uint32_t col, bool has,
                                                uint32_t k, const u32x4 &a, const uint8_t *table, uint8_t *hist,
