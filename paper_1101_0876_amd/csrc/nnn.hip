@@ -24,9 +24,10 @@
 // as three dwords per row and shifted into place with v_alignbyte and v_perm
 // (byte 0: the first site's view, byte 1: the second's); both sites are
 // compared at once as flag patterns and written back with byte stores, so
-// neighbouring threads never rewrite each other's bytes.  The record of a
-// sweep comes from one measurement kernel after its nine passes (partial sums
-// in striped slots, folded by a one-block kernel).
+// neighbouring threads never rewrite each other's bytes.  The row-class
+// launches count the record of their sweep as they go (partial sums in
+// striped slots, folded by a one-block kernel); after the per-colour passes
+// it comes from one measurement kernel over the final lattice.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -39,6 +40,7 @@
 #include "../../include/potts.h"
 #include "device.hpp"
 #include "sweep_row.hpp"
+#include "wave.hpp"
 
 struct potts_nnn_state {
   int32_t L = 0, q = 0;
@@ -80,6 +82,10 @@ using potts::zero_bytes;
 
 constexpr int kBlock = 256;
 constexpr int64_t kRingSlots = 4096;
+// partial records in striped slots (workgroup number mod kStripes), so that
+// no record word takes more than a few hundred atomics; a one-block kernel
+// folds them into the ring slot
+constexpr uint32_t kStripes = 32;
 
 struct NnnLattice {
   uint8_t *spins;
@@ -191,9 +197,42 @@ __device__ __forceinline__ void row_views(const uint32_t d[5], uint32_t &l, uint
   r = gather4<5 + CX, 8 + CX, 11 + CX, 14 + CX>(d);
 }
 
-template <int CMP, int CX>
+// The record of a sweep is counted while the row-class launches run: a bond
+// is counted when its later-coloured end is updated (its other end is final
+// then, and the colours are updated in increasing order), from that site's
+// final value; every site's final value is counted when it is updated.
+// Which of a site's neighbours come earlier depends only on its row class cy
+// and column class cx: left when cx >= 1, right when cx == 2, the row above
+// (and its diagonals) when cy >= 1, the row below when cy == 2.  mask1 / mask2
+// select those neighbours' flags (bits 7..4: left, right, up, down / up-left,
+// up-right, down-left, down-right) in every byte.
+struct RowRecord {
+  uint32_t mask1, mask2;
+  uint32_t e1, e2;      // this thread's satisfied nearest / diagonal bonds
+  uint8_t *hist;        // PRIV: lane-private columns (value << 8 | lane * 4), else q shared bins
+  uint32_t lane_off;
+};
+
+template <bool PRIV>
+__device__ __forceinline__ void count_values(RowRecord &r, uint32_t v) {
+#pragma unroll
+  for (uint32_t b = 0; b < 4; ++b) {
+    if (PRIV)
+      atomicAdd(reinterpret_cast<uint32_t *>(r.hist + perm(v, r.lane_off, 0x0C0C0000u | ((4u + b) << 8))), 1u);
+    else
+      atomicAdd(reinterpret_cast<uint32_t *>(r.hist) + byte_of(v, b), 1u);
+  }
+}
+
+template <int CMP, int CX, bool PRIV>
 __device__ __forceinline__ void rows_subpass(const NnnPass &p, uint32_t y, uint32_t *ru, uint32_t *rc, uint32_t *rd,
-                                             const uint64_t *table) {
+                                             const uint64_t *table, RowRecord &rec) {
+  {
+    const uint32_t cy = p.colour;
+    const uint32_t l_lo = CX >= 1, r_lo = CX == 2, u_lo = cy >= 1, d_lo = cy == 2;
+    rec.mask1 = ((l_lo << 7) | (r_lo << 6) | (u_lo << 5) | (d_lo << 4)) * 0x01010101u;
+    rec.mask2 = ((u_lo << 7) | (u_lo << 6) | (d_lo << 5) | (d_lo << 4)) * 0x01010101u;
+  }
   const uint32_t L = p.g.L, nblk = L / 12, spr = L / 6;
   const PhiloxHead h = philox_head(p.t_lo, p.t_hi, 16u + 3u * p.colour + CX, p.g.k0, p.g.k1);
   uint8_t *rcb = reinterpret_cast<uint8_t *>(rc);
@@ -220,12 +259,19 @@ __device__ __forceinline__ void rows_subpass(const NnnPass &p, uint32_t y, uint3
     const uint32_t s2 = diff_pattern<CMP>(cur, ul, ur, dl, dr), k2 = diff_pattern<CMP>(prop, ul, ur, dl, dr);
     const uint32_t c1 = count_flags(k1, s1), c2 = count_flags(k2, s2);
     const uint32_t wacc[4] = {a.w1, a.w3, b.w1, b.w3};
+    uint32_t sel = 0x03020100u;  // byte j from the proposal (4 + j) or the current value (j)
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) {
       const uint32_t mk = 0xFFu << (8 * j);
-      if ((uint64_t)wacc[j] < table[__popc(c1 & mk) * 9 + __popc(c2 & mk)])
+      if ((uint64_t)wacc[j] < table[__popc(c1 & mk) * 9 + __popc(c2 & mk)]) {
         rcb[4 + 12 * k + CX + 3 * j] = (uint8_t)(prop >> (8 * j));
+        sel |= 4u << (8 * j);
+      }
     }
+    // the final values' "differs" flags; equal earlier neighbours are bonds
+    rec.e1 += __popc(rec.mask1 & ~perm(k1, s1, sel));
+    rec.e2 += __popc(rec.mask2 & ~perm(k2, s2, sel));
+    count_values<PRIV>(rec, perm(prop, cur, sel));
   }
 }
 
@@ -234,11 +280,19 @@ __device__ __forceinline__ void rows_subpass(const NnnPass &p, uint32_t y, uint3
 // the periodic dwords at 0 and L/4 + 1.
 __host__ __device__ inline uint32_t rows_stride(uint32_t L) { return 64u * (((L >> 2) + 63u) >> 6) + 2u; }
 
-template <int CMP>
-__global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
+// PRIV (q <= 16): populations in 16 lane-private LDS columns, else q shared
+// bins.  The record is added into stripe blockIdx.x mod kStripes of stripes.
+template <int CMP, bool PRIV>
+__global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p, unsigned long long *stripes) {
   extern __shared__ uint32_t rows_lds[];
   __shared__ uint64_t table[81];
+  __shared__ __align__(16) uint32_t hist[PRIV ? 64 * 16 : 256];
+  __shared__ uint32_t part[256 + 2];
   for (uint32_t i = threadIdx.x; i < 81; i += kBlock) table[i] = p.thr[i];
+  const uint32_t q = p.g.q;
+  for (uint32_t i = threadIdx.x; i < (PRIV ? 64 * q : q); i += kBlock) hist[i] = 0;
+  if (threadIdx.x < 2) part[256 + threadIdx.x] = 0;
+  RowRecord rec{0u, 0u, 0u, 0u, reinterpret_cast<uint8_t *>(hist), (threadIdx.x & 63u) * 4u};
   const uint32_t L = p.g.L, cpr = L >> 2, W = rows_stride(L);
   const uint32_t y = 3 * blockIdx.x + p.colour;  // p.colour: the row class cy
   const uint32_t yu = y == 0 ? L - 1 : y - 1, yd = y + 1 == L ? 0 : y + 1;
@@ -268,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
     rd[cpr + 1] = rd[1];
   }
   __syncthreads();
-  rows_subpass<CMP, 0>(p, y, ru, rc, rd, table);
+  rows_subpass<CMP, 0, PRIV>(p, y, ru, rc, rd, table, rec);
   __syncthreads();
   // the padding dwords of row y mirror its ends: refresh them after each sub-pass
   if (threadIdx.x == 0) {
@@ -276,16 +330,37 @@ __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
     rc[cpr + 1] = rc[1];
   }
   __syncthreads();
-  rows_subpass<CMP, 1>(p, y, ru, rc, rd, table);
+  rows_subpass<CMP, 1, PRIV>(p, y, ru, rc, rd, table, rec);
   __syncthreads();
   if (threadIdx.x == 0) {
     rc[0] = rc[cpr];
     rc[cpr + 1] = rc[1];
   }
   __syncthreads();
-  rows_subpass<CMP, 2>(p, y, ru, rc, rd, table);
+  rows_subpass<CMP, 2, PRIV>(p, y, ru, rc, rd, table, rec);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < cpr; i += kBlock) __builtin_amdgcn_raw_buffer_store_b32(rc[i + 1], grow, 4 * i, 0, 0);
+  // the workgroup's share of the record
+  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t e1 = potts::wave_sum_rows(rec.e1), e2 = potts::wave_sum_rows(rec.e2);
+  if (lane == 0) {
+    if (e1) atomicAdd(&part[256], e1);
+    if (e2) atomicAdd(&part[257], e2);
+  }
+  if (PRIV) {
+    for (uint32_t v = wave; v < q; v += kBlock / 64) {
+      const uint32_t n = potts::wave_sum_rows(hist[v * 64u + lane]);
+      if (lane == 0) part[v] = n;
+    }
+  }
+  __syncthreads();
+  unsigned long long *dst = stripes + (blockIdx.x % kStripes) * (uint64_t)(q + 2);
+  for (uint32_t v = threadIdx.x; v < q; v += kBlock) {
+    const uint32_t n = PRIV ? part[v] : hist[v];
+    if (n) atomicAdd(&dst[2 + v], (unsigned long long)n);
+  }
+  if (threadIdx.x < 2 && part[256 + threadIdx.x])
+    atomicAdd(&dst[threadIdx.x], (unsigned long long)part[256 + threadIdx.x]);
 }
 
 // e1 (right, down), e2 (down-right, down-left) and populations of the
@@ -298,7 +373,6 @@ __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p) {
 // bins.
 constexpr uint32_t kMeasureRows = 8;
 constexpr uint32_t kPrivMaxQ = 64;
-constexpr uint32_t kStripes = 32;
 constexpr uint32_t kMeasureBlocks = 2048;
 
 template <bool PRIV>
@@ -485,11 +559,11 @@ int run(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
     for (uint32_t c = 0; rows && c < 3; ++c) {
       p.colour = c;  // the row class
       if (s->q <= 16)
-        hipLaunchKernelGGL(nnn_rows_kernel<0>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+        hipLaunchKernelGGL((nnn_rows_kernel<0, true>), dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p, s->stripes);
       else if (s->q <= 128)
-        hipLaunchKernelGGL(nnn_rows_kernel<1>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+        hipLaunchKernelGGL((nnn_rows_kernel<1, false>), dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p, s->stripes);
       else
-        hipLaunchKernelGGL(nnn_rows_kernel<2>, dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p);
+        hipLaunchKernelGGL((nnn_rows_kernel<2, false>), dim3(L / 3), dim3(kBlock), rows_lds, s->stream, p, s->stripes);
     }
     for (uint32_t c = 0; !rows && c < 9; ++c) {
       p.colour = c;
@@ -500,7 +574,11 @@ int run(potts_nnn_state *s, const uint64_t thr[81], int64_t nsweeps) {
       else
         hipLaunchKernelGGL(nnn_pass_kernel<2>, pass_grid, dim3(kBlock), 0, s->stream, p);
     }
-    launch_measure(p.g, s->stripes, s->records + (t & (s->rec_cap - 1)) * rl, s->stream);
+    unsigned long long *rec = s->records + (t & (s->rec_cap - 1)) * rl;
+    if (rows)  // the row-class launches counted the record into the stripes
+      hipLaunchKernelGGL(nnn_fold_kernel, dim3(1), dim3(kBlock), 0, s->stream, s->stripes, (uint32_t)rl, rec);
+    else
+      launch_measure(p.g, s->stripes, rec, s->stream);
     NNN_TRY(hipGetLastError());
   }
   s->t += nsweeps;
