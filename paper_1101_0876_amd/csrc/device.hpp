@@ -89,11 +89,19 @@ __device__ __forceinline__ uint32_t count_equal(uint32_t v, uint32_t a, uint32_t
 
 __device__ __forceinline__ uint32_t byte_of(uint32_t x, uint32_t i) { return (x >> (8u * i)) & 0xFFu; }
 
-// Wave64 sum.
+// Wave64 sum, the same total in every lane: adds within each row of 16 lanes
+// by DPP (two quad permutations, then the half-row and row mirrors) and reads
+// the four row sums out, instead of six shuffles with an LDS round trip each
+// (they sat on the critical path of the kernels that reduce a record every
+// sweep).  Needs the whole wave active: every caller reduces after its work
+// loop, outside any lane-dependent branch.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
 }  // namespace potts

@@ -40,7 +40,6 @@
 #include "../../include/potts.h"
 #include "device.hpp"
 #include "sweep_row.hpp"
-#include "wave.hpp"
 
 struct potts_nnn_state {
   int32_t L = 0, q = 0;
@@ -342,14 +341,14 @@ __global__ __launch_bounds__(kBlock) void nnn_rows_kernel(NnnPass p, unsigned lo
   for (uint32_t i = threadIdx.x; i < cpr; i += kBlock) __builtin_amdgcn_raw_buffer_store_b32(rc[i + 1], grow, 4 * i, 0, 0);
   // the workgroup's share of the record
   const uint32_t wave = threadIdx.x >> 6;
-  const uint32_t e1 = potts::wave_sum_rows(rec.e1), e2 = potts::wave_sum_rows(rec.e2);
+  const uint32_t e1 = wave_sum(rec.e1), e2 = wave_sum(rec.e2);
   if (lane == 0) {
     if (e1) atomicAdd(&part[256], e1);
     if (e2) atomicAdd(&part[257], e2);
   }
   if (PRIV) {
     for (uint32_t v = wave; v < q; v += kBlock / 64) {
-      const uint32_t n = potts::wave_sum_rows(hist[v * 64u + lane]);
+      const uint32_t n = wave_sum(hist[v * 64u + lane]);
       if (lane == 0) part[v] = n;
     }
   }

@@ -20,7 +20,6 @@
 #include "drawn.hpp"
 #include "kernels.hpp"
 #include "sweep_row.hpp"
-#include "wave.hpp"
 
 namespace potts {
 namespace {
@@ -189,11 +188,11 @@ __global__ __launch_bounds__(NARROW ? 512 : 256) void resident_kernel(ResidentLa
     __syncthreads();
     const uint32_t nz = NARROW ? half_sweep8<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off)
                                : half_sweep16<1, CMP, PRIV, WIDE, kBlock>(lat, j, t, table, hb, lane_off);
-    const uint32_t nz_w = wave_sum_rows(nz);
+    const uint32_t nz_w = wave_sum(nz);
     __syncthreads();
     if (PRIV) {
       for (uint32_t v = wave; v < q; v += kWaves) {
-        const uint32_t c = wave_sum_rows(hist[v * 64u + lane]);
+        const uint32_t c = wave_sum(hist[v * 64u + lane]);
         if (lane == 0) partial[v] = c;
       }
     } else {
@@ -353,7 +352,7 @@ __global__ __launch_bounds__(512) void resident_drawn_kernel(ResidentJob j, cons
       for (uint32_t r = 0; r < kRounds; ++r) {
         const uint32_t v = wave + r * kWaves;
         if (v < q) {
-          const uint32_t c = wave_sum_rows(hist[b][v * 64u + lane]);
+          const uint32_t c = wave_sum(hist[b][v * 64u + lane]);
           hist[b][v * 64u + lane] = 0;
           if (lane == 0) rec[1 + v] = c;
         }
@@ -380,7 +379,7 @@ __global__ __launch_bounds__(512) void resident_drawn_kernel(ResidentJob j, cons
     const uint32_t b = s & 1u;
     const uint32_t nz =
         drawn_half<1, CMP, PRIV, WIDE>(lat, L, y, col, has, k, a, table, reinterpret_cast<uint8_t *>(hist[b]), lane_off);
-    const uint32_t nz_w = wave_sum_rows(nz);
+    const uint32_t nz_w = wave_sum(nz);
     if (lane == 0) nzw[b][wave] = nz_w;
     __syncthreads();
   };

@@ -31,7 +31,6 @@
 #include "device.hpp"
 #include "kernels.hpp"
 #include "sweep_row.hpp"
-#include "wave.hpp"
 
 namespace potts {
 namespace {
@@ -157,11 +156,11 @@ __global__ __launch_bounds__(kBlock) void tile_kernel(TileParams p) {
     tile_half<0, CMP, PRIV, WIDE>(tile, p, y0, x0, t, table, hb, lane_off);
     __syncthreads();
     const uint32_t nz = tile_half<1, CMP, PRIV, WIDE>(tile, p, y0, x0, t, table, hb, lane_off);
-    const uint32_t nz_w = wave_sum_rows(nz);
+    const uint32_t nz_w = wave_sum(nz);
     __syncthreads();
     if (PRIV) {
       for (uint32_t v = wave; v < q; v += kWaves) {
-        const uint32_t c = wave_sum_rows(hist[v * 64u + lane]);
+        const uint32_t c = wave_sum(hist[v * 64u + lane]);
         if (lane == 0) partial[v] = c;
       }
     } else {
