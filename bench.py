@@ -473,8 +473,17 @@ def run_ramp(args):
         lat.observables()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # eight segments of eight points per ramp (state carried over, the same
+    # chain as one call), with a progress line after each: at the stated
+    # 10^4 sweeps per point the whole run takes minutes
+    results = [[] for _ in runs]
     with ThreadPoolExecutor(max_workers=len(runs)) as pool:
-        results = list(pool.map(lambda a: a[0].ramp(a[1][3], per - half, half), zip(lats, runs)))
+        for seg in range(8):
+            parts = list(pool.map(lambda i: lats[i].ramp(runs[i][3][8 * seg: 8 * seg + 8], per - half, half),
+                                  range(len(runs))))
+            for i, pts in enumerate(parts):
+                results[i].extend(pts)
+            print(f"ramp: {8 * seg + 8} of 64 points, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     t_all = time.perf_counter() - t0
     for lat in lats:
         lat.close()
