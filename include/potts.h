@@ -153,8 +153,9 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * lattice in LDS and runs all sweeps of a call in one launch), 4 = the
  * colour-split kernel (L % 32 == 0, L <= 65520: a call copies the lattice into
  * two colour planes in the second buffer, sweeps there and copies it back;
- * the automatic choice for such L above 2048), 5 = the multi-sweep tile kernel
- * (L % 16 == 0, L <= 65520; the automatic choice for 256 < L <= 2048: each
+ * the automatic choice for such L above 2048 that kernel 7 does not take),
+ * 5 = the multi-sweep tile kernel (L % 16 == 0, L <= 65520; the automatic
+ * choice for 256 < L <= 2048 that kernel 7 does not take: each
  * launch runs several sweeps, one LDS tile
  * per workgroup whose halo is recomputed, and moves the row-major lattice
  * between the state's two buffers; with library-owned buffers they trade
@@ -164,7 +165,18 @@ int potts_sweep_heatbath_thr(potts_state *s, const uint32_t thr[4], int64_t nswe
  * GPU writes each site's proposal and acceptance word for up to 1024 sweeps
  * into a device buffer of about 20 bytes per site and sweep, allocated on
  * first use and held until potts_free, and the one-workgroup kernel reads
- * them instead of computing them; the automatic choice for such L);
+ * them instead of computing them; the automatic choice for such L),
+ * 7 = persistent sweeps on LDS bands (L % 32 == 0, L <= 16384, a band shape
+ * from potts_tune_band whose grid the GPU holds at once; the automatic choice
+ * for 2048 <= L <= 4096 when it can take the lattice): each workgroup keeps
+ * a band of whole rows of the colour-split lattice in LDS for up to 64 sweeps
+ * per cooperative launch and trades its two edge rows with the neighbouring
+ * bands after every half sweep (an exchange buffer of 2 x L x L / rows bytes,
+ * held until potts_free); every wait on a neighbour is bounded (0.25 s, or
+ * the microseconds in the environment variable POTTS_BAND_WAIT_US, read at
+ * each sweep call), and one that expires, possible only if the grid was not
+ * resident at once or the bound is set too short, is reported as EDEVICE by
+ * the next call that sweeps or reads results;
  * strip_rows: rows per strip work item (0 = automatic, else an even divisor of
  * L); max_groups: persistent grid size in workgroups (0 = automatic).
  * Errors: EINVAL. */
@@ -179,6 +191,16 @@ int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_g
  * largest even divisor below, 4 sweeps).  Results never depend on it.
  * Errors: EINVAL (a shape the lattice cannot take; the old one is kept). */
 int potts_tune_tiles(potts_state *s, int32_t tx, int32_t ty, int32_t sweeps);
+
+/* Shape of the band kernel (kernel 7): `rows` rows per band (even, dividing
+ * L; L / rows workgroups) of `block` lanes (256, 512 or 1024, at least
+ * L / 16); 0 for both = automatic (the first of 8, 16, 4, 32, 2 rows whose
+ * grid the GPU holds at once, the fewest lanes that give each item of a half
+ * sweep its own, else 1024); block 0 with rows > 0 = that rule for block.  A
+ * band with its two halo rows (L x (rows + 2) bytes) must fit in 136 KiB of
+ * LDS.  Results never depend on it.  Errors: EINVAL (a shape the lattice or
+ * the GPU cannot take; the old one is kept). */
+int potts_tune_band(potts_state *s, int32_t rows, int32_t block);
 
 /* Occupancy of the colour-split kernel: 0 = the compiler's register budget
  * (the default), 8 = at most 64 VGPRs so that 8 waves fit on each SIMD (the

@@ -131,6 +131,11 @@ class Lattice:
         """Replay colour-split sweeps from a captured graph of `sweeps` sweeps (0: off)."""
         check(self._lib.potts_tune_graph(self._h, int(sweeps)))
 
+    def tune_band(self, rows: int = 0, block: int = 0) -> None:
+        """Band kernel (kernel 7) shape: rows per band and lanes per workgroup
+        (0 = automatic); results are identical for every shape."""
+        check(self._lib.potts_tune_band(self._h, int(rows), int(block)))
+
     @property
     def t(self) -> int:
         return int(self._lib.potts_time(self._h))

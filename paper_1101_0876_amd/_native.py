@@ -146,6 +146,7 @@ SIGNATURES = [
     ("potts_tune_occupancy", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("potts_tune_graph", ctypes.c_int, [_VP, ctypes.c_int32]),
     ("potts_tune_tiles", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("potts_tune_band", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     ("potts_tune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     ("potts_slab_half_sweep", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_int32, _U32P, _VP,

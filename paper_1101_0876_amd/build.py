@@ -17,7 +17,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["capi.hip", "kernels.hip", "strip.hip", "packed.hip", "resident.hip", "stats.hip", "batch.hip",
-           "server.hip", "cubic.hip", "cubic_packed.hip", "nnn.hip", "tune_cache.hip", "heatbath_packed.hip", "noalloc.hip", "tiles.hip"]
+           "server.hip", "cubic.hip", "cubic_packed.hip", "nnn.hip", "tune_cache.hip", "heatbath_packed.hip", "noalloc.hip", "tiles.hip", "band.hip"]
 # the kernels whose launch shapes the tuners pick
 TUNED = ["strip.hip", "packed.hip", "sweep_row.hpp", "device.hpp", "kernels.hpp"]
 LIB_PATH = os.path.join(_HERE, "libpotts.so")

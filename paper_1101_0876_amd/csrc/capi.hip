@@ -4,6 +4,7 @@
 
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -32,7 +33,7 @@ struct potts_state {
   bool have_thr = false;
   double thr_beta = 0.0;
   uint32_t thr[4] = {0, 0, 0, 0};
-  int kernel = 0;          // 0 automatic, 1 strip, 2 chunk, 3 LDS-resident, 4 colour-split, 5 tiles, 6 LDS-resident with pre-drawn words
+  int kernel = 0;          // 0 automatic, 1 strip, 2 chunk, 3 LDS-resident, 4 colour-split, 5 tiles, 6 LDS-resident with pre-drawn words, 7 LDS bands
   uint32_t rows = 0;       // strip rows per work item, 0 = automatic
   unsigned max_groups = 0; // persistent grid size, 0 = automatic
   uint32_t wpe = 0;        // colour-split kernel: waves per SIMD asked of the compiler (0 = its choice)
@@ -64,6 +65,20 @@ struct potts_state {
   unsigned long long *tstripes = nullptr;
   // pre-drawn random words of a chunk of sweeps (drawn.hpp), allocated on first use
   uint32_t *drawn = nullptr;
+  // persistent sweeps on LDS bands (band.hip): the shape asked for (0 =
+  // automatic), the edge-row exchange buffer, the flags with their epoch, the
+  // partial records of a launch and the host-visible error word
+  uint32_t band_rows = 0, band_block = 0;
+  uint32_t band_auto_rows = 0, band_auto_block = 0;  // the automatic shape, once found
+  bool band_auto_tried = false;
+  uint8_t *bxbuf = nullptr;
+  size_t bxbytes = 0;
+  uint32_t *bflags = nullptr;
+  size_t bflag_words = 0;
+  uint32_t bepoch = 0;
+  unsigned long long *bstripes = nullptr;
+  uint32_t *berr = nullptr;
+  uint64_t bclock_khz = 0;  // rate of the kernel's wall clock
 };
 
 namespace {
@@ -137,6 +152,10 @@ void release(potts_state *s) {
   if (s->hb_dev) (void)hipFree(s->hb_dev);
   if (s->tstripes) (void)hipFree(s->tstripes);
   if (s->drawn) (void)hipFree(s->drawn);
+  if (s->bxbuf) (void)hipFree(s->bxbuf);
+  if (s->bflags) (void)hipFree(s->bflags);
+  if (s->bstripes) (void)hipFree(s->bstripes);
+  if (s->berr) (void)hipHostFree(s->berr);
   if (s->hb_host) (void)hipHostFree(s->hb_host);
   if (s->owns_stream && s->stream) (void)hipStreamDestroy(s->stream);
   delete s;
@@ -309,6 +328,61 @@ bool use_tiles(const potts_state *s) {
 }
 
 bool wide_table(const uint32_t thr[4]) { return !thr[0] || !thr[1] || !thr[2] || !thr[3]; }
+
+// Lanes per band workgroup: the fewest of 256 / 512 / 1024 that give every
+// item of a half sweep its own lane, else 1024.
+uint32_t band_block_for(uint32_t L, uint32_t rows) {
+  const uint64_t items = (uint64_t)rows * (L / 32);
+  return items <= 256 ? 256u : items <= 512 ? 512u : 1024u;
+}
+
+// The band shape (rows per band, lanes per workgroup): the one asked for, or
+// the first of 8, 16, 4, 32, 2 rows whose grid of L / rows workgroups can be
+// resident at once.
+bool band_shape(potts_state *s, uint32_t *rows, uint32_t *block) {
+  const uint32_t L = (uint32_t)s->L;
+  if (s->band_rows) {
+    *rows = s->band_rows;
+    *block = s->band_block ? s->band_block : band_block_for(L, *rows);
+    bool fits = false;
+    return potts::band_resident(L, (uint32_t)s->q, *rows, *block, &fits) == hipSuccess && fits;
+  }
+  if (!s->band_auto_tried) {
+    s->band_auto_tried = true;
+    static const uint32_t cand[] = {8, 16, 4, 32, 2};
+    for (uint32_t r : cand) {
+      bool fits = false;
+      const uint32_t blk = band_block_for(L, r);
+      if (potts::band_resident(L, (uint32_t)s->q, r, blk, &fits) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+      }
+      if (fits) {
+        s->band_auto_rows = r;
+        s->band_auto_block = blk;
+        break;
+      }
+    }
+  }
+  *rows = s->band_auto_rows;
+  *block = s->band_auto_block;
+  return *rows != 0;
+}
+
+bool band_ok(potts_state *s) {
+  uint32_t rows, block;
+  return s->L % 32 == 0 && s->L <= 16384 && band_shape(s, &rows, &block);
+}
+
+// The automatic choice for L = 2048 .. 4096: measured on MI355X (q = 6, ps
+// per site update), L = 2048 2.06 (8-row bands of 512 lanes; the tile kernel
+// 2.68), L = 4096 1.08 (16-row bands of 1024 lanes; the colour-split kernel
+// 1.64).  At L = 1024 the tile kernel stays ahead (6.1 against 9.1: a half
+// sweep there is shorter than the exchange of edge rows), and from L = 8192
+// no band of whole rows whose grid the GPU holds at once fits in LDS.
+bool auto_band(potts_state *s) { return s->L >= 2048 && s->L <= 4096 && band_ok(s); }
+
+bool use_band(potts_state *s) { return s->kernel == 7 ? band_ok(s) : s->kernel == 0 && auto_band(s); }
 
 }  // namespace
 
@@ -628,11 +702,142 @@ int run_tiles(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   return POTTS_OK;
 }
 
+// A neighbour wait of the band kernel that outlived its bound (possible only
+// if its grid was not resident at once) leaves the error word set; the next
+// call that sweeps or reads results reports it, and the flags start over.
+int band_check(potts_state *s) {
+  if (!s->berr || !__atomic_load_n(s->berr, __ATOMIC_ACQUIRE)) return POTTS_OK;
+  __atomic_store_n(s->berr, 0u, __ATOMIC_RELEASE);
+  if (s->bflags) HIP_TRY(potts::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->bflags),
+                                                (s->bflag_words + 1) / 2, 0ull, s->stream));
+  s->bepoch = 0;
+  return fail(POTTS_EDEVICE, "band sweeps: a wait on a neighbouring band outlived its bound; "
+                             "the sweeps since the last successful read are invalid");
+}
+
+// Sweeps on LDS bands (band.hip), up to kBandMaxSweeps per cooperative
+// launch, each launch's records folded into their ring slots right after it.
+int run_band(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
+  uint32_t rows, block;
+  if (!band_shape(s, &rows, &block)) return fail(POTTS_EINVAL, "no band shape fits this lattice");
+  const uint32_t L = (uint32_t)s->L, q = (uint32_t)s->q;
+  const uint32_t bands = L / rows, parts = potts::band_parts(L);
+  const size_t xbytes = (size_t)2 * bands * L;  // [plane][band][top, bottom][L/2]
+  const size_t fwords = (size_t)bands * parts;
+  if (xbytes > s->bxbytes) {
+    if (s->bxbuf) (void)hipFree(s->bxbuf);
+    s->bxbuf = nullptr;
+    s->bxbytes = 0;
+    if (hipMalloc(&s->bxbuf, xbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the band exchange buffer failed");
+    }
+    s->bxbytes = xbytes;
+  }
+  if (fwords != s->bflag_words) {
+    if (s->bflags) (void)hipFree(s->bflags);
+    s->bflags = nullptr;
+    s->bflag_words = 0;
+    if (hipMalloc(&s->bflags, (fwords + 1) / 2 * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the band flags failed");
+    }
+    HIP_TRY(potts::launch_fill_u64(reinterpret_cast<unsigned long long *>(s->bflags), (fwords + 1) / 2, 0ull,
+                                   s->stream));
+    s->bflag_words = fwords;
+    s->bepoch = 0;
+  }
+  const uint32_t sw = potts::stripe_words(q);
+  if (!s->bstripes) {
+    const uint64_t words = (uint64_t)potts::kBandMaxSweeps * kStripes * sw;
+    if (hipMalloc(&s->bstripes, words * sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(POTTS_ENOMEM, "allocation of the band partial records failed");
+    }
+    HIP_TRY(potts::launch_fill_u64(s->bstripes, words, 0ull, s->stream));
+  }
+  if (!s->berr) {
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->berr), sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      s->berr = nullptr;
+      return fail(POTTS_ENOMEM, "allocation of the band error word failed");
+    }
+    __atomic_store_n(s->berr, 0u, __ATOMIC_RELEASE);
+  }
+  if (!s->bclock_khz) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    s->bclock_khz = (uint64_t)(khz > 0 ? khz : 100000);
+  }
+  // the bound on one neighbour wait: 0.25 s, or POTTS_BAND_WAIT_US
+  // microseconds (a short bound makes the failure path testable)
+  uint64_t wait_us = 250000;
+  if (const char *w = getenv("POTTS_BAND_WAIT_US")) {
+    char *end = nullptr;
+    const unsigned long long v = strtoull(w, &end, 10);
+    if (end != w && v > 0 && v <= 10000000ull) wait_us = v;
+  }
+  if (!s->planes_valid) {
+    HIP_TRY(potts::launch_pack(s->spins, s->spins2, L, s->stream));
+    s->planes_valid = true;
+  }
+  s->spins_valid = false;
+  potts::BandParams p{};
+  p.planes = s->spins2;
+  p.xbuf = s->bxbuf;
+  p.flags = s->bflags;
+  p.err = s->berr;
+  p.stripes = s->bstripes;
+  p.nstripes = kStripes;
+  p.L = L;
+  p.q = q;
+  p.rows = rows;
+  p.bands = bands;
+  p.parts = parts;
+  p.prow_magic = (uint32_t)(((1ull << 32) + L / 32 - 1) / (L / 32));
+  p.k0 = (uint32_t)s->seed;
+  p.k1 = (uint32_t)(s->seed >> 32);
+  for (int i = 0; i < 4; ++i) p.thr.v[i] = thr[i];
+  p.wait_ticks = s->bclock_khz * wait_us / 1000u;
+  potts::TileParams f{};
+  f.q = q;
+  f.stripes = s->bstripes;
+  f.nstripes = kStripes;
+  // one launch's records fold into distinct ring slots
+  const int64_t kmax = std::min<int64_t>(potts::kBandMaxSweeps, s->rec_cap);
+  for (int64_t done = 0; done < nsweeps;) {
+    const int64_t K = std::min<int64_t>(kmax, nsweeps - done);
+    p.t0 = (uint64_t)(s->t + done);
+    p.nsweeps = (uint32_t)K;
+    p.epoch = s->bepoch;
+    HIP_TRY(potts::launch_band(p, block, s->stream));
+    s->bepoch += 2u * (uint32_t)K;
+    f.t0 = p.t0;
+    f.nsweeps = (uint32_t)K;
+    HIP_TRY(potts::launch_fold_sets(f, s->records, (uint64_t)s->rec_cap, s->stream));
+    done += K;
+  }
+  s->t += nsweeps;
+  if (!s->owns_spins) {
+    HIP_TRY(potts::launch_unpack(s->spins2, s->spins, L, s->stream));
+    s->spins_valid = true;
+    s->planes_valid = false;
+  }
+  return POTTS_OK;
+}
+
 int run_sweeps(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
+  {
+    const int rc = band_check(s);
+    if (rc) return rc;
+  }
   if (nsweeps == 0) return POTTS_OK;
+  const bool band = use_band(s);
+  if (band) return run_band(s, thr, nsweeps);
   if (use_resident(s) || !use_packed(s)) {
     // every other kernel sweeps the row-major lattice (the LDS-resident one
     // too, although the lattice may have a colour-split copy from heat-bath
@@ -765,7 +970,7 @@ int run_heatbath(potts_state *s, const uint32_t thr[4], int64_t nsweeps) {
   if (nsweeps < 0) return fail(POTTS_EINVAL, "nsweeps must be >= 0");
   if (nsweeps > INT64_MAX - s->t) return fail(POTTS_ERANGE, "sweep counter overflow");
   if (nsweeps == 0) return POTTS_OK;
-  if (packed_ok(s) && (s->kernel == 0 || s->kernel == 4)) {
+  if (packed_ok(s) && (s->kernel == 0 || s->kernel == 4 || s->kernel == 7)) {
     const int64_t rl = s->q + 1;
     HIP_TRY(potts::launch_fill_u64(s->records + (s->t % s->rec_cap) * rl, (uint64_t)rl, 0ull, s->stream));
     return run_heatbath_packed(s, thr, nsweeps);
@@ -826,7 +1031,7 @@ int copy_records(potts_state *s, int64_t t0, int64_t n, int64_t *out) {
     done += run;
   }
   HIP_TRY(hipStreamSynchronize(s->stream));
-  return POTTS_OK;
+  return band_check(s);
 }
 
 void fill_obs(const potts_state *s, const int64_t *rec, potts_obs *out) {
@@ -940,6 +1145,23 @@ int potts_tune_tiles(potts_state *s, int32_t tx, int32_t ty, int32_t sweeps) {
   return POTTS_OK;
 }
 
+int potts_tune_band(potts_state *s, int32_t rows, int32_t block) {
+  if (!s) return fail(POTTS_EINVAL, "state is NULL");
+  if (rows < 0 || block < 0 || (!rows && block)) return fail(POTTS_EINVAL, "rows and block >= 0, block only with rows");
+  const uint32_t old_rows = s->band_rows, old_block = s->band_block;
+  s->band_rows = (uint32_t)rows;
+  s->band_block = (uint32_t)block;
+  uint32_t r, b;
+  if (rows && !band_shape(s, &r, &b)) {
+    (void)hipGetLastError();
+    s->band_rows = old_rows;
+    s->band_block = old_block;
+    return fail(POTTS_EINVAL, "band shape: rows even dividing L, block 256 / 512 / 1024 >= L / 16, "
+                              "LDS of one band within 136 KiB, grid resident at once");
+  }
+  return POTTS_OK;
+}
+
 int potts_tune_graph(potts_state *s, int32_t sweeps) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
   if (sweeps < 0 || sweeps > 4096) return fail(POTTS_EINVAL, "sweeps per graph must be 0 .. 4096");
@@ -970,7 +1192,9 @@ int potts_slab_records(const int64_t *dev_rings, int32_t nslabs, int64_t ring_sl
 
 int potts_tune(potts_state *s, int32_t kernel, int32_t strip_rows, int32_t max_groups) {
   if (!s) return fail(POTTS_EINVAL, "state is NULL");
-  if (kernel < 0 || kernel > 6) return fail(POTTS_EINVAL, "kernel must be 0 .. 6");
+  if (kernel < 0 || kernel > 7) return fail(POTTS_EINVAL, "kernel must be 0 .. 7");
+  if (kernel == 7 && !band_ok(s))
+    return fail(POTTS_EINVAL, "band kernel needs L % 32 == 0, L <= 16384 and a band shape whose grid fits the GPU");
   if (kernel == 6 && !drawn_ok(s))
     return fail(POTTS_EINVAL, "pre-drawn resident kernel needs L % 16 == 0 and L*L <= 4096");
   if (kernel == 5 && !tiles_ok(s)) return fail(POTTS_EINVAL, "tile kernel needs L % 16 == 0 and a tile shape");
@@ -1004,6 +1228,8 @@ int potts_measure(potts_state *s, potts_obs *out) {
   std::vector<int64_t> rec((size_t)rl);
   HIP_TRY(hipMemcpyAsync(rec.data(), s->scratch, (size_t)rl * 8, hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  const int brc = band_check(s);
+  if (brc) return brc;
   fill_obs(s, rec.data(), out);
   return POTTS_OK;
 }
@@ -1043,6 +1269,8 @@ int potts_stats(potts_state *s, int64_t t0, int64_t n, double beta, potts_summar
   double v[5];
   HIP_TRY(hipMemcpyAsync(v, s->stats_out, sizeof(v), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  rc = band_check(s);
+  if (rc) return rc;
   out->n = n;
   out->e = v[0];
   out->C = v[1];
@@ -1177,7 +1405,7 @@ int potts_get_spins(potts_state *s, uint8_t *host_out) {
   if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(host_out, s->spins, (size_t)n_sites(s), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  return POTTS_OK;
+  return band_check(s);
 }
 
 int potts_set_spins(potts_state *s, const uint8_t *host_in, int64_t t) {
