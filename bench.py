@@ -48,7 +48,10 @@ CUBE_SOURCES = ["paper_1101_0876_amd/csrc/cubic_packed.hip", "paper_1101_0876_am
 # the first-plus-second-neighbour workload's kernels (one sweep)
 NNN_SOURCES = ["paper_1101_0876_amd/csrc/nnn.hip", "paper_1101_0876_amd/csrc/sweep_row.hpp",
                "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
-SOURCES_OF = {"large": KERNEL_SOURCES, "cubic": CUBE_SOURCES, "nnn": NNN_SOURCES}
+# the mid-size workload's kernel (64 sweeps per launch)
+MID_SOURCES = ["paper_1101_0876_amd/csrc/band.hip", "paper_1101_0876_amd/csrc/band.hpp", "paper_1101_0876_amd/csrc/sweep_row.hpp",
+               "paper_1101_0876_amd/csrc/device.hpp", "paper_1101_0876_amd/csrc/kernels.hpp"]
+SOURCES_OF = {"large": KERNEL_SOURCES, "cubic": CUBE_SOURCES, "nnn": NNN_SOURCES, "mid": MID_SOURCES}
 
 
 def kernel_hash(sources=None) -> str:
@@ -66,8 +69,8 @@ def kernel_hash(sources=None) -> str:
 
 def counter_traffic(workload: str):
     """HBM bytes per launch of the dominant kernel (per sweep for the nnn
-    workload) from the committed rocprofv3 --pmc summary, if it was taken on
-    the current kernel source."""
+    workload, per 64-sweep launch for the mid-size one) from the committed
+    rocprofv3 --pmc summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -642,6 +645,74 @@ def run_heatbath(args):
             "event_ms": ev_ms, "cpu_baseline": cpu}
 
 
+def run_mid(args):
+    """Mid-size single lattices, where a half sweep is too short to hide a
+    kernel boundary: q=6, beta_c(6), random start, seed 1, records every
+    sweep.  The value is L=4096 with the automatic kernel (the band kernel:
+    64 sweeps per cooperative launch, --steps sweeps, default 640); beside it
+    L = 1024 / 2048 / 4096 with the automatic kernel and with the streaming
+    colour-split kernel (two launches per sweep; --no-extras skips these)."""
+    import torch
+
+    import paper_1101_0876_amd as potts
+
+    torch.cuda.set_device(0)
+    q, seed = 6, 1
+    beta = math.log1p(math.sqrt(q))
+    steps = args.steps if args.steps != 2000 else 640
+    st = torch.cuda.Stream()
+
+    def timed(L, kernel, n):
+        with potts.Lattice.on_stream(L, q, seed, potts.RANDOM, stream=st) as lat:
+            lat.tune(kernel=kernel)
+            lat.sweep(beta, max(1, args.warmup))
+            st.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record(st)
+            lat.sweep(beta, n)
+            ev1.record(st)
+            st.synchronize()
+            wall = time.perf_counter() - t0
+            rec = lat.records(lat.t - 1, 1)
+            assert int(rec[0, 1:].sum()) == L * L, "population sum != N"
+            return wall, ev0.elapsed_time(ev1)
+
+    sizes = {}
+    for L in (() if args.no_extras else (1024, 2048, 4096)):
+        n = max(64, steps * (4096 // L) ** 2)
+        _, ev_auto = timed(L, args.kernel, n)
+        _, ev_split = timed(L, 4, n)
+        sizes[str(L)] = {"auto_ps": ev_auto * 1e9 / (n * L * L), "colour_split_ps": ev_split * 1e9 / (n * L * L),
+                         "sweeps": n}
+        print(f"mid: L={L} automatic {sizes[str(L)]['auto_ps']:.3f} ps, colour-split "
+              f"{sizes[str(L)]['colour_split_ps']:.3f} ps per spin flip", file=sys.stderr, flush=True)
+    L = 4096
+    wall, ev_ms = timed(L, args.kernel, steps)
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_seconds)
+    launches = -(-steps // 64)
+    per_launch_s = ev_ms * 1e-3 / launches
+    achieved_ops = ALGO_OPS_PER_SITE * L * L * (steps / launches) / per_launch_s
+    return {"metric": "ns per spin flip", "value": wall * 1e9 / (steps * L * L), "unit": "ns", "n_gpus": 1,
+            "steps": steps, "warmup": max(1, args.warmup), "ms_per_step": wall * 1e3 / steps,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "mid-size single lattice", "q": q, "L": L, "beta": beta, "seed": seed,
+                       "start": "random", "records": "every sweep", "kernel": args.kernel},
+            "roofline": {
+                "bound": "alu",
+                "achieved": achieved_ops / 1e12,
+                "peak": VALU_PEAK_OPS / 1e12,
+                "unit": "Tops/s",
+                "frac": achieved_ops / VALU_PEAK_OPS,
+                "traffic": counter_traffic("mid") if args.kernel in (0, 7) and steps % 64 == 0 else None,
+                "kernel": "band_kernel (64 sweeps per launch)" if args.kernel in (0, 7) else f"kernel {args.kernel}",
+                "avg_launch_us": per_launch_s * 1e6,
+                "algorithmic_ops_per_site_update": ALGO_OPS_PER_SITE,
+            },
+            "sizes": sizes, "event_ms": ev_ms, "cpu_baseline": cpu}
+
+
 def run_cubic(args):
     """Simple-cubic lattice (Sec. 7's three-dimensional variant): q = 3,
     L = 1024 (2^30 uint8 spins, the default workload's site count), beta =
@@ -877,7 +948,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs",
+    ap.add_argument("--workload", default="large", choices=["large", "copy", "batch", "serve", "plain", "ramp", "slabs", "mid",
                                                      "metastability", "heatbath", "cubic", "nnn", "e2e"])
     ap.add_argument("--kernel", type=int, default=0,
                     help="large: 0 automatic (colour-split), 1 strip, 2 chunk, 4 colour-split; "
@@ -911,6 +982,9 @@ def main():
         return
     if args.workload == "ramp":
         print(json.dumps(run_ramp(args)), flush=True)
+        return
+    if args.workload == "mid":
+        print(json.dumps(run_mid(args)), flush=True)
         return
     if args.workload == "heatbath":
         print(json.dumps(run_heatbath(args)), flush=True)

@@ -44,6 +44,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "band.hpp"
 #include "kernels.hpp"
 #include "sweep_row.hpp"
 

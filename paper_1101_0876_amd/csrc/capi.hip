@@ -13,6 +13,7 @@
 
 #include "../../include/potts.h"
 #include "drawn.hpp"
+#include "band.hpp"
 #include "kernels.hpp"
 
 struct potts_state {

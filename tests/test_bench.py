@@ -21,7 +21,7 @@ def test_more_than_one_gpu_is_refused():
     assert res.stdout.strip() == ""
 
 
-@pytest.mark.parametrize("workload", ["large", "cubic", "nnn"])
+@pytest.mark.parametrize("workload", ["large", "cubic", "nnn", "mid"])
 def test_counter_traffic_follows_the_source_hash(workload, tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
@@ -42,6 +42,17 @@ def test_counter_traffic_follows_the_source_hash(workload, tmp_path, monkeypatch
     assert bench.counter_traffic(workload) == 1234.0
     src.write_text(src.read_text() + "\nint an_extra_symbol;\n")
     assert bench.counter_traffic(workload) is None
+
+
+@pytest.mark.parametrize("workload", ["large", "cubic", "nnn", "mid"])
+def test_committed_counter_records_match_the_kernels(workload):
+    """The committed traffic records were taken on the kernel sources as they
+    stand (a header shared by every kernel counts too), so the bench lines
+    report counter traffic rather than null."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.counter_traffic(workload) is not None
 
 
 def test_cpu_baseline_is_the_oracle():

@@ -175,3 +175,30 @@ def test_band_kernel_rejects_shapes_it_cannot_take(potts):
             with pytest.raises(potts.PottsError):
                 lat.tune_band(rows, block)
         lat.tune_band(8, 0)
+
+
+def test_band_kernel_on_two_streams_at_once(potts, oracle_lib):
+    """Two lattices of the band range sweep on two streams at the same time
+    (their cooperative launches queued together): both chains equal the
+    oracle's."""
+    import torch
+
+    q, beta, n = 6, beta_c(6), 8
+    _say("band two streams L=2048 and L=4096")
+    jobs = [(2048, 3), (4096, 4)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    lats = [potts.Lattice.on_stream(L, q, seed, potts.RANDOM, stream=st) for (L, seed), st in zip(jobs, streams)]
+    try:
+        for lat in lats:
+            lat.tune(kernel=7)
+        for lat in lats:  # both queued before either is waited for
+            lat.sweep(beta, n)
+        torch.cuda.synchronize()
+        for (L, seed), lat in zip(jobs, lats):
+            s = oracle_lib.init(L, q, seed, 1)
+            want = oracle_lib.sweeps(s, q, seed, 0, n, oracle_lib.threshold_table(beta))
+            assert np.array_equal(lat.records(0, n), want)
+            assert np.array_equal(lat.spins(), s)
+    finally:
+        for lat in lats:
+            lat.close()
