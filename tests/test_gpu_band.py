@@ -202,3 +202,22 @@ def test_band_kernel_on_two_streams_at_once(potts, oracle_lib):
     finally:
         for lat in lats:
             lat.close()
+
+
+@pytest.mark.parametrize("L,n", [(2048, 3000), (4096, 1000)])
+def test_band_kernel_long_chain_equals_colour_split_kernel(potts, L, n):
+    """Thousands of edge-row exchanges (2 x n half sweeps between every pair
+    of neighbouring bands): the band kernel's chain, every record and the
+    final lattice, equals the streaming colour-split kernel's, so no half
+    sweep read a stale edge row."""
+    q, seed, beta = 6, 12, beta_c(6)
+    _say(f"band long chain L={L} n={n}")
+    out = []
+    for kernel in (4, 7):
+        with potts.Lattice(L, q, seed, potts.RANDOM) as lat:
+            lat.reserve_records(n + 1)
+            lat.tune(kernel=kernel)
+            lat.sweep(beta, n)
+            out.append((lat.spins(), lat.records(0, n)))
+    assert np.array_equal(out[1][1], out[0][1])
+    assert np.array_equal(out[1][0], out[0][0])
