@@ -221,3 +221,41 @@ def test_band_kernel_long_chain_equals_colour_split_kernel(potts, L, n):
             out.append((lat.spins(), lat.records(0, n)))
     assert np.array_equal(out[1][1], out[0][1])
     assert np.array_equal(out[1][0], out[0][0])
+
+
+def test_band_kernel_with_checkpoints_ramps_and_heat_bath(potts, oracle_lib, tmp_path):
+    """The band path (the automatic choice at L = 2048) inside a chain that
+    also checkpoints and resumes, and interleaves heat-bath sweeps (which run
+    on the same colour-split copy): spins and records equal the oracle's."""
+    L, q, seed = 2048, 7, 5
+    b1, b2 = beta_c(7), 1.05 * beta_c(7)
+    _say(f"band chain with checkpoint and heat bath L={L}")
+    s = oracle_lib.init(L, q, seed, 1)
+    want = [oracle_lib.sweeps(s, q, seed, 0, 5, oracle_lib.threshold_table(b1)),
+            oracle_lib.heatbath_sweeps(s, q, seed, 5, 2, oracle_lib.threshold_table(b2)),
+            oracle_lib.sweeps(s, q, seed, 7, 4, oracle_lib.threshold_table(b2))]
+    want = np.concatenate(want)
+    path = str(tmp_path / "band.ckpt")
+    with potts.Lattice(L, q, seed, 1) as lat:
+        lat.sweep(b1, 5)
+        lat.save(path)
+    with potts.Lattice.load_checkpoint(path) as lat:
+        assert lat.t == 5
+        lat.sweep_heatbath(b2, 2)
+        lat.sweep(b2, 4)
+        assert np.array_equal(lat.records(5, 6), want[5:])
+        assert np.array_equal(lat.spins(), s)
+
+
+def test_band_kernel_ramp_equals_colour_split_ramp(potts):
+    """potts_ramp over the band path: the per-point statistics equal those of
+    the same ramp on the streaming colour-split kernel."""
+    L, q, seed = 4096, 6, 8
+    betas = [0.98 * beta_c(6), beta_c(6), 1.02 * beta_c(6)]
+    _say(f"band ramp L={L}")
+    out = []
+    for kernel in (4, 0):
+        with potts.Lattice(L, q, seed, potts.ORDERED) as lat:
+            lat.tune(kernel=kernel)
+            out.append(lat.ramp(betas, 30, 40))
+    assert out[0] == out[1]
