@@ -358,13 +358,19 @@ bool band_shape_ok(uint32_t L, uint32_t rows, uint32_t block) {
 hipError_t band_resident(uint32_t L, uint32_t q, uint32_t rows, uint32_t block, bool *fits) {
   *fits = false;
   if (!band_shape_ok(L, rows, block)) return hipSuccess;
-  const void *k = pick(q, false, block);
+  // both table forms: a call may take either (the wide one holds more registers)
   const size_t lds = band_lds_bytes(L, rows);
-  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  int per_cu = 0, dev = 0, cus = 0, coop = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, (int)block, lds);
-  if (e == hipSuccess) e = hipGetDevice(&dev);
+  int per_cu = 1 << 30;
+  for (bool wide : {false, true}) {
+    const void *k = pick(q, wide, block);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    int n = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, (int)block, lds);
+    if (e != hipSuccess) return e;
+    per_cu = n < per_cu ? n : per_cu;
+  }
+  int dev = 0, cus = 0, coop = 0;
+  hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
   if (e != hipSuccess) return e;
