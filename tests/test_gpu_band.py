@@ -259,3 +259,43 @@ def test_band_kernel_ramp_equals_colour_split_ramp(potts):
             lat.tune(kernel=kernel)
             out.append(lat.ramp(betas, 30, 40))
     assert out[0] == out[1]
+
+
+def test_band_kernel_seeded_shapes_equal_colour_split_kernel(potts):
+    """Seeded draws of lattice size (multiples of 32 from 64 to 4096, many
+    not powers of two: rows of an odd number of items, edge rows that end
+    inside a wave), band height, lanes, q, start and temperature: each band
+    chain equals the streaming colour-split kernel's, every record and the
+    final lattice."""
+    rng = np.random.default_rng(20261203)
+    done = 0
+    for _ in range(400):
+        if done == 14:
+            break
+        L = 32 * int(rng.integers(2, 129))
+        rows = int(rng.choice([2, 4, 6, 8, 10, 12, 16, 20, 24, 32]))
+        block = int(rng.choice([256, 512, 1024]))
+        q = int(rng.choice([2, 3, 5, 9, 16, 17, 40, 64, 65, 200]))
+        start = int(rng.integers(0, 2))
+        beta = float(rng.uniform(0.9, 1.1)) * beta_c(q)
+        n = int(rng.integers(1, 90))
+        seed = 100 + done
+        out = []
+        for kernel in (7, 4):
+            with potts.Lattice(L, q, seed, start) as lat:
+                try:
+                    lat.tune(kernel=kernel)
+                    if kernel == 7:
+                        lat.tune_band(rows, block)
+                except potts.PottsError:
+                    break  # a shape this lattice cannot take: draw again
+                if kernel == 7:
+                    _say(f"band seeded L={L} rows={rows} block={block} q={q} start={start} n={n}")
+                lat.sweep(beta, n)
+                out.append((lat.spins(), lat.records(0, n)))
+        if len(out) < 2:
+            continue
+        assert np.array_equal(out[0][1], out[1][1]), (L, rows, block, q, n)
+        assert np.array_equal(out[0][0], out[1][0]), (L, rows, block, q, n)
+        done += 1
+    assert done == 14
