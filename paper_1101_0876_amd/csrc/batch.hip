@@ -104,7 +104,8 @@ struct potts_batch {
   potts::TuneCache cache;
   // device tables
   potts::StripParams *d_strip = nullptr;    // per strip group: jobs' descriptors, contiguous
-  potts::StripTile *d_tiles = nullptr;
+  potts::StripTile *d_tiles = nullptr;      // colour-0 tables, then (at tiles_cap) the colour-1 ones
+  size_t tiles_cap = 0;
   std::vector<size_t> strip_desc_off, tile_off, tile_count;  // per strip group
   potts::ResidentJob *d_res = nullptr;      // per resident group and chunk
   std::vector<size_t> res_off;              // per (group, chunk)
@@ -176,6 +177,19 @@ void build_strip_tables(const potts_batch *b, const StripGroup &g, const potts::
       tiles.push_back(t);
     }
   }
+  // Longest tiles first (a tile's work is its items times their rows): the
+  // last workgroups of a launch, which leave CUs idle while they finish, are
+  // then short ones.  Jobs of one batch differ up to 8x in rows per item.
+  std::stable_sort(tiles.begin(), tiles.end(), [&desc](const potts::StripTile &x, const potts::StripTile &y) {
+    return (uint64_t)desc[x.job].rows * x.count > (uint64_t)desc[y.job].rows * y.count;
+  });
+}
+
+// The colour-1 launch takes its workgroups' tiles from the end of the table
+// (it walks the lattice bottom-up), so it gets the table reversed: both
+// launches then dispatch the longest tiles first.
+std::vector<potts::StripTile> reversed(const std::vector<potts::StripTile> &t) {
+  return std::vector<potts::StripTile>(t.rbegin(), t.rend());
 }
 
 int upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
@@ -185,20 +199,23 @@ int upload(void *dst, const void *src, size_t bytes, hipStream_t s) {
   return POTTS_OK;
 }
 
-// One launch pair (colour 0, colour 1) of a strip group for sweep s.
+// One launch pair (colour 0, colour 1) of a strip group for sweep s; tiles0
+// and tiles1: the group's table and its reverse.
 int launch_strip_sweep(const StripGroup &g, const potts::TileShape &shape, const potts::StripParams *d_desc,
-                       const potts::StripTile *d_tiles, size_t ntiles, uint32_t s, hipStream_t st) {
-  potts::StripLaunch l{};
-  l.jobs = d_desc;
-  l.tiles = d_tiles;
-  l.sweep = s;
+                       const potts::StripTile *tiles0, const potts::StripTile *tiles1, size_t ntiles, uint32_t s,
+                       hipStream_t st) {
+  potts::StripLaunch l0{}, l1{};
+  l0.jobs = l1.jobs = d_desc;
+  l0.tiles = tiles0;
+  l1.tiles = tiles1;
+  l0.sweep = l1.sweep = s;
   const uint32_t mq = class_max_q(g.qc);
   if (g.packed) {
-    HIP_TRY(potts::launch_packed_tiled(l, 0, (unsigned)ntiles, shape, mq, g.wide, st));
-    HIP_TRY(potts::launch_packed_tiled(l, 1, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_packed_tiled(l0, 0, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_packed_tiled(l1, 1, (unsigned)ntiles, shape, mq, g.wide, st));
   } else {
-    HIP_TRY(potts::launch_strip_tiled(l, 0, (unsigned)ntiles, shape, mq, g.wide, st));
-    HIP_TRY(potts::launch_strip_tiled(l, 1, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_strip_tiled(l0, 0, (unsigned)ntiles, shape, mq, g.wide, st));
+    HIP_TRY(potts::launch_strip_tiled(l1, 1, (unsigned)ntiles, shape, mq, g.wide, st));
   }
   return POTTS_OK;
 }
@@ -214,9 +231,13 @@ int timed_strip_sweeps(potts_batch *b, const StripGroup &g, const potts::TileSha
   if (rc) return rc;
   rc = upload(b->d_tiles, tiles.data(), tiles.size() * sizeof(tiles[0]), b->stream);
   if (rc) return rc;
+  const std::vector<potts::StripTile> rev = reversed(tiles);
+  rc = upload(b->d_tiles + b->tiles_cap, rev.data(), rev.size() * sizeof(rev[0]), b->stream);
+  if (rc) return rc;
   HIP_TRY(hipEventRecord(b->ev_t0, b->stream));
   for (int s = 0; s < reps; ++s) {
-    rc = launch_strip_sweep(g, shape, b->d_strip, b->d_tiles, tiles.size(), (uint32_t)s, b->stream);
+    rc = launch_strip_sweep(g, shape, b->d_strip, b->d_tiles, b->d_tiles + b->tiles_cap, tiles.size(), (uint32_t)s,
+                            b->stream);
     if (rc) return rc;
   }
   HIP_TRY(hipEventRecord(b->ev_t1, b->stream));
@@ -318,7 +339,7 @@ int autotune(potts_batch *b, bool time_new) {
 int queue_rest(potts_batch *b) {
   // strip tables for the remaining sweeps
   std::vector<potts::StripParams> all_desc;
-  std::vector<potts::StripTile> all_tiles;
+  std::vector<potts::StripTile> all_tiles, all_rev;
   b->strip_desc_off.clear();
   b->tile_off.clear();
   b->tile_count.clear();
@@ -333,10 +354,13 @@ int queue_rest(potts_batch *b) {
     for (const auto &d : desc) strip_sweeps = std::max<int64_t>(strip_sweeps, (int64_t)d.nsweeps);
     all_desc.insert(all_desc.end(), desc.begin(), desc.end());
     all_tiles.insert(all_tiles.end(), tiles.begin(), tiles.end());
+    all_rev.insert(all_rev.end(), tiles.rbegin(), tiles.rend());
   }
   int rc = upload(b->d_strip, all_desc.data(), all_desc.size() * sizeof(all_desc[0]), b->stream);
   if (rc) return rc;
   rc = upload(b->d_tiles, all_tiles.data(), all_tiles.size() * sizeof(all_tiles[0]), b->stream);
+  if (rc) return rc;
+  rc = upload(b->d_tiles + b->tiles_cap, all_rev.data(), all_rev.size() * sizeof(all_rev[0]), b->stream);
   if (rc) return rc;
 
   // resident descriptors, one array per (group, chunk)
@@ -397,7 +421,8 @@ int queue_rest(potts_batch *b) {
     for (size_t gi = 0; gi < b->strip_groups.size() && !err; ++gi) {
       if (!b->tile_count[gi]) continue;
       err = launch_strip_sweep(b->strip_groups[gi], b->shape[gi], b->d_strip + b->strip_desc_off[gi],
-                               b->d_tiles + b->tile_off[gi], b->tile_count[gi], (uint32_t)s, st);
+                               b->d_tiles + b->tile_off[gi], b->d_tiles + b->tiles_cap + b->tile_off[gi],
+                               b->tile_count[gi], (uint32_t)s, st);
     }
   }
   if (!err && (hipEventRecord(b->ev_join, b->side) != hipSuccess || hipStreamWaitEvent(st, b->ev_join, 0) != hipSuccess))
@@ -557,7 +582,7 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
     nres += g.jobs.size() * (size_t)std::max<int64_t>(1, (most + kResidentChunk - 1) / kResidentChunk);
   }
   if ((nstrip_desc && (hipMalloc(&b->d_strip, nstrip_desc * sizeof(potts::StripParams)) != hipSuccess ||
-                       hipMalloc(&b->d_tiles, ntiles_max * sizeof(potts::StripTile)) != hipSuccess)) ||
+                       hipMalloc(&b->d_tiles, 2 * ntiles_max * sizeof(potts::StripTile)) != hipSuccess)) ||
       (nres && hipMalloc(&b->d_res, nres * sizeof(potts::ResidentJob)) != hipSuccess) ||
       hipMalloc(&b->d_stats, (size_t)n * sizeof(potts::StatsParams)) != hipSuccess ||
       hipMalloc(&b->d_stats_out, (size_t)n * 8 * sizeof(double)) != hipSuccess) {
@@ -565,6 +590,7 @@ int potts_batch_create(const potts_job *jobs, int32_t n, const potts_batch_opts 
     release(b);
     return record_error(POTTS_ENOMEM, "batch table allocation failed");
   }
+  b->tiles_cap = ntiles_max;
   // initial conditions
   for (int32_t i = 0; i < n; ++i) {
     potts::InitParams p{};
