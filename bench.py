@@ -81,6 +81,20 @@ def counter_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu() -> str:
+    """The host's CPU model and hardware thread count (the oracle runs on one)."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} hardware threads visible"
+
+
 def cpu_baseline(seconds_target: float = 15.0):
     """The oracle (serial C, one thread) on a bounded sample of the workload:
     an L = 4096 lattice, q = 6, beta_c, random start, sweeps with records."""
@@ -98,7 +112,7 @@ def cpu_baseline(seconds_target: float = 15.0):
         el = time.perf_counter() - t0
         if el >= seconds_target or n >= 64:
             break
-    return {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+    return {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": f"L={L} q={q} beta_c random start, {n} sweeps with per-sweep records, 1 thread"}
 
 
@@ -435,7 +449,7 @@ def run_plain(args):
         t0 = time.perf_counter()
         oracle.sweeps(spins, q, seed, 0, n, oracle.threshold_table(beta), record=True)
         el = time.perf_counter() - t0
-        cpu = {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+        cpu = {"value": el * 1e9 / (n * L * L), "unit": "ns per spin flip", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"the whole workload (L={L} q={q}, {n} sweeps with records), 1 thread"}
     return {"metric": "ns per spin flip", "value": med * 1e9 / (n * L * L), "unit": "ns", "n_gpus": 1,
             "steps": reps, "warmup": 1, "ms_per_step": med * 1e3, "higher_is_better": False,
@@ -626,7 +640,7 @@ def run_heatbath(args):
             el = time.perf_counter() - t1
             if el >= args.cpu_seconds or n >= 64:
                 break
-        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"L={Ls} q={q} heat-bath, random start, {n} sweeps with records, 1 thread"}
     ev_ms = ev0.elapsed_time(ev1)
     per_launch_s = ev_ms * 1e-3 / (2 * steps)
@@ -766,7 +780,7 @@ def run_cubic(args):
             el = time.perf_counter() - t1
             if el >= args.cpu_seconds or n >= 64:
                 break
-        cpu = {"value": el * 1e9 / (n * Ls ** 3), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+        cpu = {"value": el * 1e9 / (n * Ls ** 3), "unit": "ns per spin flip", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"L={Ls}^3 q={q} cubic, random start, {n} sweeps with records, 1 thread"}
     ns = wall * 1e9 / (steps * N)
     packed = kernel in (0, 1)
@@ -846,7 +860,7 @@ def run_nnn(args):
             el = time.perf_counter() - t1
             if el >= args.cpu_seconds or n >= 64:
                 break
-        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle",
+        cpu = {"value": el * 1e9 / (n * Ls * Ls), "unit": "ns per spin flip", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"L={Ls} q={q} j2={j2} nine-colour chain, random start, {n} sweeps with records, 1 thread"}
     ns = wall * 1e9 / (steps * N)
     sweep_s = ev_ms * 1e-3 / steps
@@ -934,7 +948,7 @@ def run_e2e(args):
             if el >= args.cpu_seconds or n >= 200:
                 break
         per_sweep = el / n
-        cpu = {"value": per_sweep * sweeps, "unit": "s (extrapolated whole run)", "cores": 1, "kind": "oracle",
+        cpu = {"value": per_sweep * sweeps, "unit": "s (extrapolated whole run)", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"L={L} q={q} T={temps[0]} ordered start, {n} sweeps with records timed, "
                          f"x {sweeps} sweeps of the run, 1 thread"}
     return {"metric": "end-to-end run time", "value": wall, "unit": "s", "n_gpus": 1, "steps": sweeps, "warmup": 1,
