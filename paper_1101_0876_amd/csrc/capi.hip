@@ -346,7 +346,11 @@ bool band_shape(potts_state *s, uint32_t *rows, uint32_t *block) {
     *rows = s->band_rows;
     *block = s->band_block ? s->band_block : band_block_for(L, *rows);
     bool fits = false;
-    return potts::band_resident(L, (uint32_t)s->q, *rows, *block, &fits) == hipSuccess && fits;
+    if (potts::band_resident(L, (uint32_t)s->q, *rows, *block, &fits) != hipSuccess) {
+      (void)hipGetLastError();  // not left for a later launch check to report
+      return false;
+    }
+    return fits;
   }
   if (!s->band_auto_tried) {
     s->band_auto_tried = true;
