@@ -78,6 +78,15 @@ def test_bad_beta_and_null_state(lib):
     lib.potts_free(None)
 
 
+def test_tuning_calls_reject_a_null_state(lib):
+    # checked before any device query, so this holds without a GPU
+    assert lib.potts_tune(None, 7, 0, 0) == -1
+    assert lib.potts_tune_band(None, 8, 256) == -1
+    assert lib.potts_tune_tiles(None, 0, 0, 0) == -1
+    assert lib.potts_tune_graph(None, 0) == -1
+    assert lib.potts_tune_occupancy(None, 0) == -1
+
+
 @pytest.mark.parametrize("bad", [dict(L=20), dict(L=8), dict(L=65552), dict(q=1), dict(q=257), dict(h=0),
                                  dict(h=3), dict(y0=1), dict(y0=-2), dict(y0=240, h=32), dict(colour=2),
                                  dict(t=-1), dict(slab=None), dict(thr=None), dict(ring=None),
